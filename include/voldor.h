@@ -1,0 +1,182 @@
+/*
+ * voldor.h -- C ABI of the MI355X (gfx950) library for the dense hot path of
+ * VOLDOR+SLAM (Min & Dunn, arXiv 2104.06800): generalized-EM inference of
+ * inverse depth, rigidness and camera poses over a window of N optical flows
+ * (sec. III-A, Eqs. 1-6), and robust point-to-plane inverse-depth keyframe
+ * alignment (sec. III-B, Eqs. 10 and 12).
+ *
+ * Conventions (all entry points)
+ *   - Every array is caller-owned and lives in device memory of the context's
+ *     GPU unless stated otherwise.  The library never frees caller memory and
+ *     keeps no pointer after the work it enqueued has completed.  It allocates
+ *     only its own scratch (grown on demand, freed by voldor_ctx_destroy).
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *     default stream).  Buffers must stay valid until the stream reaches it.
+ *   - Return value: VOLDOR_OK or an error code.  Shapes, parameters and null
+ *     pointers are checked before anything is enqueued (VOLDOR_EINVAL, message
+ *     in voldor_last_error).  A HIP failure returns VOLDOR_EDEVICE.  NaN or Inf
+ *     inside the data are not errors: they make the affected terms invalid and
+ *     are counted in the statistics.  No C++ exception crosses this boundary.
+ *   - Images are row-major [H][W]; pixel (u, v) is at integer coordinates.
+ *     A pose 6-vector (w, t) maps reference-camera points to camera t as
+ *     X_t = exp([w]x) X_ref + t (Rodrigues rotation vector w), FP64.
+ *   - The state is inverse depth rho = 1/theta (the paper's theta is depth).
+ *   - Not thread-safe per context: calls on one context must not overlap
+ *     across host threads; calls on different contexts may.
+ */
+#ifndef VOLDOR_H
+#define VOLDOR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VOLDOR_OK = 0,
+    VOLDOR_EINVAL = 1,     /* bad shape / parameter / null pointer; nothing enqueued  */
+    VOLDOR_ENOMEM = 2,     /* scratch allocation failed                               */
+    VOLDOR_EDEVICE = 3,    /* HIP runtime error; see voldor_last_error                */
+    VOLDOR_ESINGULAR = 4   /* per-pair status of voldor_align_p2p: 6x6 system not PD  */
+};
+
+enum { VOLDOR_LEVEL_COARSE = 0, VOLDOR_LEVEL_LOCAL = 1 };
+enum { VOLDOR_ROBUST_HUBER = 0, VOLDOR_ROBUST_CAUCHY = 1 };
+
+#define VOLDOR_MAX_FRAMES 8     /* N <= 8 flows per window              */
+#define VOLDOR_MAX_PRIORS 4     /* P <= 4 depth priors per window       */
+#define VOLDOR_SCORE_LEN 29     /* energy, H upper (21), g (6), count   */
+#define VOLDOR_STATS_LEN 8
+
+typedef struct voldor_ctx_s* voldor_ctx;
+
+/* Window geometry and model constants (host struct, passed by pointer). */
+typedef struct {
+    int32_t H, W;              /* image size                                              */
+    int32_t N;                 /* flows in the window, 1..8                               */
+    int32_t P;                 /* depth priors, 0..4                                      */
+    float fx, fy, cx, cy;      /* pinhole intrinsics                                      */
+    float fisk_alpha;          /* log-logistic scale of the flow end-point error (px)     */
+    float fisk_beta;           /* log-logistic shape, in [1, 4]; 2 takes a fast path      */
+    float outlier_density;     /* planar outlier density L0 (px^-2), e.g. 1/(pi 8^2)      */
+    float hmm_gamma;           /* rigidness-chain stay probability, in (0.5, 1]           */
+    float idepth_min, idepth_max;  /* candidate inverse-depth range                       */
+    float perturb_sigma0;      /* relative width of perturbation candidates at it 0,1     */
+    float prior_sigma_rel;     /* Eq. 3: sigma(rho^) = prior_sigma_rel * rho^             */
+    float prior_uniform_rel;   /* Eq. 3: U(rho^) = 1 / (prior_uniform_rel * rho^)         */
+    float prior_inlier_default;/* prior weight where prior_weight is NULL                 */
+    int32_t n_candidates;      /* K slots per pixel per pass, 3..64                       */
+    int32_t coarse_stride;     /* s of the coarse lattice, >= 1                           */
+    int32_t tile;              /* T of the local tiles: 8, 16, 32, 64, 128 or 256         */
+    int32_t pose_gn_steps;     /* Gauss-Newton steps per frame in the pose step, >= 0     */
+    int32_t chain_axis;        /* rigidness chains: 0 spatial (paper), 1 frame window     */
+    int32_t reserved0;
+    uint64_t seed;             /* Philox key                                              */
+    uint32_t window_id;        /* Philox counter word 3                                   */
+    uint32_t reserved1;
+} voldor_window;
+
+/* Device buffers of one window.  Sizes: Hc x Wc from voldor_lattice_shape. */
+typedef struct {
+    const float*  flow;          /* [N][H][W][2] flow X_t (frame t-1 -> t) on frame t-1's grid  */
+    double*       pose;          /* [N][6] T_t, reference -> camera t (in/out)                  */
+    float*        idepth;        /* [H][W] inverse depth of the reference frame (in/out)        */
+    float*        rigid;         /* [N][H][W] rigidness posteriors q_t (out of the E-step)      */
+    float*        idepth_coarse; /* [Hc][Wc] coarse-lattice inverse depth (work buffer)         */
+    float*        rigid_coarse;  /* [N][Hc][Wc] coarse-lattice rigidness (work buffer)          */
+    const float*  prior_idepth;  /* [P][H][W] prior inverse depth, NaN = hole; NULL if P = 0    */
+    const double* prior_pose;    /* [P][6] fixed pose T^_k of prior k (reference -> camera k)  */
+    const float*  prior_weight;  /* [P][H][W] prior inlier weight pi^ in [0,1], or NULL         */
+    float*        conf;          /* [H][W] confidence C (Eq. 6), written by voldor_finalize     */
+    double*       stats;         /* [8] statistics, written by voldor_finalize                  */
+} voldor_buffers;
+
+/* Context bound to one device ordinal.  Owns scratch memory only. */
+int  voldor_ctx_create(voldor_ctx* out, int device_ordinal);
+void voldor_ctx_destroy(voldor_ctx ctx);
+/* Message of the last non-zero status on this context (or of ctx creation when ctx is NULL). */
+const char* voldor_last_error(voldor_ctx ctx);
+/* Size of the coarse lattice {(s U + floor(s/2), s V + floor(s/2))} inside H x W (host). */
+int voldor_lattice_shape(int32_t H, int32_t W, int32_t stride, int32_t* Hc, int32_t* Wc);
+
+/* Random initial inverse depth, rho_min + u (rho_max - rho_min) with u from Philox
+ * (counter: pixel index, 0, purpose INIT at iteration 0 / local level, window id).
+ * Writes idepth. */
+int voldor_init_idepth(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
+                       void* stream);
+
+/* E-step of one level (sec. III-A "Hierarchical Propagation Scheme": HMM smoothing of the
+ * rigidness maps by forward-backward on the alternately directed 1D chains), direction
+ * iter mod 4.  Emissions use the current idepth and poses.  Level COARSE writes
+ * rigid_coarse (chains = whole lattice rows/columns); level LOCAL writes rigid (chains =
+ * rows/columns of tile x tile blocks).  With chain_axis = 1 each pixel's chain runs over
+ * the frame window instead. */
+int voldor_rigidness_fb(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
+                        int iter, int level, void* stream);
+
+/* M-step of one level (sec. III-A, Eqs. 3-5): per pixel argmin of the maximum-inlier energy
+ * over K candidate slots -- 0 current value, 1 predecessor's updated value along the chain,
+ * 2 coarse result of the pixel's lattice cell (LOCAL only), 3..K-1 Philox draws -- ties to
+ * the lowest slot, chains swept in direction iter mod 4.  Uses the level's rigidness from
+ * its last E-step and the prior posteriors at the current value.  COARSE writes
+ * idepth_coarse; LOCAL writes idepth. */
+int voldor_depth_update(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
+                        int iter, int level, void* stream);
+
+/* Scores candidate poses of frame t (1..N) (sec. III-A "Uncertainty-aware Pose Estimation":
+ * the quantity its pose samples are judged by).  For each candidate: energy
+ * sum_j q_t^j log1p(L0/L1(r)) (invalid terms cost q log 2), the Gauss-Newton normal
+ * equations H = sum w J^T J (upper triangle, row-major, 21 values) and g = sum w J^T e of
+ * the residual e = p_t - o_t with IRLS weight w = q d cost / d r^2 and J the derivative
+ * w.r.t. a left update (dw, dv), and the count of valid terms.  o_t uses the current pose
+ * of frame t-1.  cand_pose: [n_cand][6] device FP64; out: [n_cand][29] device FP64. */
+int voldor_pose_score(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
+                      int t, int n_cand, const double* cand_pose, double* out, void* stream);
+
+/* Pose step: frames t = 1..N in order, pose_gn_steps FP64 Cholesky solves of
+ * (H + 1e-9 tr(H)/6 I) delta = -g each, T_t <- (exp([dw]x) R, exp([dw]x) t + dv).
+ * A numerically singular system leaves that frame's pose unchanged. */
+int voldor_pose_step(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
+                     void* stream);
+
+/* One GEM iteration: coarse E+M, local E+M, pose step (each level fused in one launch). */
+int voldor_gem_step(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
+                    int iter, void* stream);
+
+/* Final local E-step (direction iter mod 4), confidence C^j = (sum_t q_t + sum_k q^_k)/(N+P)
+ * (Eq. 6) and statistics: [0] log-likelihood (sum of chain log Z, densities in px^-2),
+ * [1] MIE energy sum_j E_j(rho_j) (natural log), [2] valid flow terms, [3] invalid flow
+ * terms, [4] prior terms present (q^ > 0), [5] sum of C, [6..7] 0. */
+int voldor_finalize(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
+                    int iter, void* stream);
+
+/* Keyframe-alignment parameters (sec. III-B, Eqs. 10, 12). */
+typedef struct {
+    int32_t H, W;
+    float fx, fy, cx, cy;
+    int32_t robust;            /* VOLDOR_ROBUST_HUBER or VOLDOR_ROBUST_CAUCHY          */
+    float robust_scale;        /* Huber delta / Cauchy scale, inverse-depth units      */
+    int32_t gn_steps;          /* Gauss-Newton steps, >= 0                             */
+    float normal_disc_rel;     /* normal invalid if |rho_nb - rho| > this * rho        */
+    float scale_s;             /* relative depth scale s (1 for absolute scale)        */
+} voldor_align_params;
+
+/* Robust point-to-plane inverse-depth alignment of n_pairs keyframe pairs (Eq. 10):
+ * r_j = rho1(l) <n(l), P1(l) - Q_j> / (s Q_j,z), Q_j = T X2_j, l the nearest pixel of Q_j's
+ * projection (fixed within a step), normals by central differences of idepth1; weight
+ * conf2_j * psi'(r)/r; undamped Gauss-Newton with an FP64 Cholesky solve per step; then
+ * cov = H^-1 at the final pose (Eq. 12's covariance).  Inputs [n][H][W] FP32 (NaN or <= 0
+ * = missing); pose_inout [n][6] FP64 (T: camera 2 -> camera 1); cov_out [n][36];
+ * stats_out [n][4] = initial cost, final cost, final valid count, steps taken;
+ * status_out [n] int32: VOLDOR_OK or VOLDOR_ESINGULAR (the failing step is not applied and
+ * cov is NaN).  All device memory. */
+int voldor_align_p2p(voldor_ctx ctx, const voldor_align_params* ap, int n_pairs,
+                     const float* idepth1, const float* idepth2, const float* conf2,
+                     double* pose_inout, double* cov_out, double* stats_out, int32_t* status_out,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VOLDOR_H */

@@ -1,0 +1,238 @@
+"""ctypes binding of libvoldor.so: the same entry points, argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; PyTorch supplies device
+memory (tensors) and the current HIP stream.  Importing this module loads the in-tree
+library and fails loudly when it has not been built.
+"""
+import ctypes
+import os
+
+import torch
+
+from .build import LIB
+
+OK, EINVAL, ENOMEM, EDEVICE, ESINGULAR = 0, 1, 2, 3, 4
+COARSE, LOCAL = 0, 1
+SCORE_LEN = 29
+STATS_LEN = 8
+MAX_FRAMES, MAX_PRIORS = 8, 4
+
+
+class VoldorError(RuntimeError):
+    pass
+
+
+class Window(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("N", ctypes.c_int32), ("P", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("fisk_alpha", ctypes.c_float), ("fisk_beta", ctypes.c_float),
+                ("outlier_density", ctypes.c_float), ("hmm_gamma", ctypes.c_float),
+                ("idepth_min", ctypes.c_float), ("idepth_max", ctypes.c_float), ("perturb_sigma0", ctypes.c_float),
+                ("prior_sigma_rel", ctypes.c_float), ("prior_uniform_rel", ctypes.c_float),
+                ("prior_inlier_default", ctypes.c_float),
+                ("n_candidates", ctypes.c_int32), ("coarse_stride", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("pose_gn_steps", ctypes.c_int32), ("chain_axis", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("window_id", ctypes.c_uint32), ("reserved1", ctypes.c_uint32)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("flow", "pose", "idepth", "rigid", "idepth_coarse", "rigid_coarse",
+                 "prior_idepth", "prior_pose", "prior_weight", "conf", "stats")]
+
+
+class AlignParams(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("robust", ctypes.c_int32), ("robust_scale", ctypes.c_float), ("gn_steps", ctypes.c_int32),
+                ("normal_disc_rel", ctypes.c_float), ("scale_s", ctypes.c_float)]
+
+
+EXPORTS = ["voldor_ctx_create", "voldor_ctx_destroy", "voldor_last_error", "voldor_lattice_shape",
+           "voldor_init_idepth", "voldor_rigidness_fb", "voldor_depth_update", "voldor_pose_score",
+           "voldor_pose_step", "voldor_gem_step", "voldor_finalize", "voldor_align_p2p"]
+
+
+def load_library(path=LIB):
+    if not os.path.exists(path):
+        raise VoldorError(f"{path} is missing: build it first (python -m paper_2104_06800_amd.build)")
+    lib = ctypes.CDLL(path)
+    P, I, V = ctypes.POINTER, ctypes.c_int, ctypes.c_void_p
+    W, B = P(Window), P(Buffers)
+    lib.voldor_ctx_create.argtypes = [P(V), I]
+    lib.voldor_ctx_destroy.argtypes = [V]
+    lib.voldor_ctx_destroy.restype = None
+    lib.voldor_last_error.argtypes = [V]
+    lib.voldor_last_error.restype = ctypes.c_char_p
+    lib.voldor_lattice_shape.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         P(ctypes.c_int32), P(ctypes.c_int32)]
+    lib.voldor_init_idepth.argtypes = [V, W, B, V]
+    lib.voldor_rigidness_fb.argtypes = [V, W, B, I, I, V]
+    lib.voldor_depth_update.argtypes = [V, W, B, I, I, V]
+    lib.voldor_pose_score.argtypes = [V, W, B, I, I, V, V, V]
+    lib.voldor_pose_step.argtypes = [V, W, B, V]
+    lib.voldor_gem_step.argtypes = [V, W, B, I, V]
+    lib.voldor_finalize.argtypes = [V, W, B, I, V]
+    lib.voldor_align_p2p.argtypes = [V, P(AlignParams), I, V, V, V, V, V, V, V, V]
+    for n in EXPORTS:
+        if n not in ("voldor_ctx_destroy", "voldor_last_error"):
+            getattr(lib, n).restype = ctypes.c_int
+    return lib
+
+
+_LIB = load_library()
+
+
+def lattice_shape(H, W, stride):
+    hc, wc = ctypes.c_int32(), ctypes.c_int32()
+    rc = _LIB.voldor_lattice_shape(H, W, stride, ctypes.byref(hc), ctypes.byref(wc))
+    if rc:
+        raise VoldorError(f"bad lattice {H}x{W} stride {stride}")
+    return hc.value, wc.value
+
+
+def make_window(p):
+    """Window struct from a parameter dict (keys as in the struct)."""
+    w = Window()
+    for name, _ in Window._fields_:
+        if name.startswith("reserved"):
+            continue
+        setattr(w, name, p[name] if name != "seed" else int(p[name]) & 0xFFFFFFFFFFFFFFFF)
+    return w
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Voldor:
+    """One library context on a device; methods mirror the C entry points."""
+
+    def __init__(self, device=0):
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = _LIB.voldor_ctx_create(ctypes.byref(h), device)
+        if rc:
+            raise VoldorError(f"voldor_ctx_create: {_LIB.voldor_last_error(None).decode()}")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _LIB.voldor_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc:
+            raise VoldorError(f"{what} -> {rc}: {_LIB.voldor_last_error(self._h).decode()}")
+
+    # -- buffers ---------------------------------------------------------------
+    def alloc(self, p, flow, pose, prior_idepth=None, prior_pose=None, prior_weight=None):
+        """Device buffer set for one window; inputs are copied to the device."""
+        dev = torch.device("cuda", self.device)
+        H, W, N, P = p["H"], p["W"], p["N"], p.get("P", 0)
+        hc, wc = lattice_shape(H, W, p["coarse_stride"])
+        f32 = dict(dtype=torch.float32, device=dev)
+        b = dict(
+            flow=torch.as_tensor(flow, dtype=torch.float32).to(dev).contiguous(),
+            pose=torch.as_tensor(pose, dtype=torch.float64).to(dev).contiguous(),
+            idepth=torch.zeros((H, W), **f32), rigid=torch.zeros((N, H, W), **f32),
+            idepth_coarse=torch.zeros((hc, wc), **f32), rigid_coarse=torch.zeros((N, hc, wc), **f32),
+            prior_idepth=None, prior_pose=None, prior_weight=None,
+            conf=torch.zeros((H, W), **f32), stats=torch.zeros(8, dtype=torch.float64, device=dev))
+        if P:
+            b["prior_idepth"] = torch.as_tensor(prior_idepth, dtype=torch.float32).to(dev).contiguous()
+            b["prior_pose"] = torch.as_tensor(prior_pose, dtype=torch.float64).to(dev).contiguous()
+            if prior_weight is not None:
+                b["prior_weight"] = torch.as_tensor(prior_weight, dtype=torch.float32).to(dev).contiguous()
+        return b
+
+    def _bufs(self, p, b):
+        H, W, N, P = p["H"], p["W"], p["N"], p.get("P", 0)
+        hc, wc = lattice_shape(H, W, p["coarse_stride"])
+        shapes = dict(flow=(N, H, W, 2), pose=(N, 6), idepth=(H, W), rigid=(N, H, W),
+                      idepth_coarse=(hc, wc), rigid_coarse=(N, hc, wc), conf=(H, W), stats=(8,))
+        if P:
+            shapes.update(prior_idepth=(P, H, W), prior_pose=(P, 6))
+            if b.get("prior_weight") is not None:
+                shapes["prior_weight"] = (P, H, W)
+        for k, shp in shapes.items():
+            t = b.get(k)
+            if t is None:
+                raise VoldorError(f"buffer {k} missing")
+            want = torch.float64 if k in ("pose", "prior_pose", "stats") else torch.float32
+            if tuple(t.shape) != shp or t.dtype != want or not t.is_cuda or not t.is_contiguous():
+                raise VoldorError(f"buffer {k}: need contiguous {want} {shp} on the GPU, got "
+                                  f"{t.dtype} {tuple(t.shape)} cuda={t.is_cuda}")
+        return Buffers(*[_ptr(b.get(n)) for n, _ in Buffers._fields_])
+
+    # -- entry points -----------------------------------------------------------
+    def init_idepth(self, p, b, stream=None):
+        self._check(_LIB.voldor_init_idepth(self._h, make_window(p), self._bufs(p, b), _stream(stream)),
+                    "voldor_init_idepth")
+
+    def rigidness_fb(self, p, b, it, level, stream=None):
+        self._check(_LIB.voldor_rigidness_fb(self._h, make_window(p), self._bufs(p, b), it, level,
+                                             _stream(stream)), "voldor_rigidness_fb")
+
+    def depth_update(self, p, b, it, level, stream=None):
+        self._check(_LIB.voldor_depth_update(self._h, make_window(p), self._bufs(p, b), it, level,
+                                             _stream(stream)), "voldor_depth_update")
+
+    def pose_score(self, p, b, t, cand, stream=None):
+        cand = torch.as_tensor(cand, dtype=torch.float64).to(b["pose"].device).reshape(-1, 6).contiguous()
+        out = torch.zeros((cand.shape[0], SCORE_LEN), dtype=torch.float64, device=cand.device)
+        self._check(_LIB.voldor_pose_score(self._h, make_window(p), self._bufs(p, b), t, cand.shape[0],
+                                           _ptr(cand), _ptr(out), _stream(stream)), "voldor_pose_score")
+        return out
+
+    def pose_step(self, p, b, stream=None):
+        self._check(_LIB.voldor_pose_step(self._h, make_window(p), self._bufs(p, b), _stream(stream)),
+                    "voldor_pose_step")
+
+    def gem_step(self, p, b, it, stream=None):
+        self._check(_LIB.voldor_gem_step(self._h, make_window(p), self._bufs(p, b), it, _stream(stream)),
+                    "voldor_gem_step")
+
+    def finalize(self, p, b, it, stream=None):
+        self._check(_LIB.voldor_finalize(self._h, make_window(p), self._bufs(p, b), it, _stream(stream)),
+                    "voldor_finalize")
+
+    def run(self, p, b, iters=None, init=True, stream=None):
+        """Plain GEM: random init, iterations 0..I-1, finalize (all on the stream)."""
+        iters = p.get("iters", 5) if iters is None else iters
+        if init:
+            self.init_idepth(p, b, stream)
+        for it in range(iters):
+            self.gem_step(p, b, it, stream)
+        self.finalize(p, b, iters - 1, stream)
+
+    def align_p2p(self, ap, idepth1, idepth2, conf2, pose_inout, stream=None):
+        """Returns (cov [n][36], stats [n][4], status [n]); pose_inout is updated in place."""
+        n = idepth1.shape[0]
+        dev = idepth1.device
+        for t, dt in ((idepth1, torch.float32), (idepth2, torch.float32), (conf2, torch.float32),
+                      (pose_inout, torch.float64)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise VoldorError("align inputs must be contiguous device tensors of the documented dtypes")
+        if tuple(idepth1.shape) != (n, ap["H"], ap["W"]) or idepth2.shape != idepth1.shape \
+                or conf2.shape != idepth1.shape or tuple(pose_inout.shape) != (n, 6):
+            raise VoldorError("align input shapes disagree")
+        a = AlignParams(**{k: ap[k] for k, _ in AlignParams._fields_})
+        cov = torch.zeros((n, 36), dtype=torch.float64, device=dev)
+        stats = torch.zeros((n, 4), dtype=torch.float64, device=dev)
+        status = torch.zeros(n, dtype=torch.int32, device=dev)
+        self._check(_LIB.voldor_align_p2p(self._h, ctypes.byref(a), n, _ptr(idepth1), _ptr(idepth2), _ptr(conf2),
+                                          _ptr(pose_inout), _ptr(cov), _ptr(stats), _ptr(status),
+                                          _stream(stream)), "voldor_align_p2p")
+        return cov, stats, status

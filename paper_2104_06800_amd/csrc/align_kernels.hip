@@ -1,0 +1,190 @@
+// Robust point-to-plane inverse-depth keyframe alignment on gfx950 (VOLDOR+SLAM sec.
+// III-B, Eq. 10 with the criterion of Eq. 12, no photometric term).
+//
+//   prepare : per map-1 pixel l, the plane (A, b) = (rho1 n, n . x~_l) from central
+//             differences of map 1 (NaN where the normal is invalid), so that for a
+//             map-2 point Q~ = rho2 Q the residual is r = (rho2 b - A . Q~) / (s Q~_z)
+//   step    : per map-2 pixel the residual, its Jacobian w.r.t. a left pose update and the
+//             robust weight, reduced in FP64 to H (21), g (6), cost, count per pair; the
+//             last block of a pair solves H delta = -g by Cholesky and updates the pose,
+//             or (final pass) inverts H into the covariance.
+#include "device.h"
+#include "kernels.h"
+
+namespace vd {
+
+__global__ void __launch_bounds__(VD_BLOCK)
+k_align_prepare(AlignArgs a, AlignBufs B) {
+    const size_t plane = (size_t)a.H * a.W;
+    const size_t j = (size_t)blockIdx.x * VD_BLOCK + threadIdx.x;
+    if (j < (size_t)a.n_pairs) {            // per-pair bookkeeping
+        B.status[j] = 0;
+        for (int k = 0; k < 4; ++k) B.stats[4 * j + k] = 0.0;
+    }
+    if (j >= plane * a.n_pairs) return;
+    const int pair = (int)(j / plane);
+    const int l = (int)(j - (size_t)pair * plane);
+    const int v = l / a.W, u = l - v * a.W;
+    const float* R = B.idepth1 + (size_t)pair * plane;
+    float4 out = make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+    if (u >= 1 && u <= a.W - 2 && v >= 1 && v <= a.H - 2) {
+        const float r0 = R[l];
+        const float rr = R[l + 1], rl = R[l - 1], rd = R[l + a.W], ru = R[l - a.W];
+        const float lim = a.disc * r0;
+        bool ok = r0 > 0.f && isfinite(r0);
+        ok = ok && rr > 0.f && isfinite(rr) && fabsf(rr - r0) <= lim;
+        ok = ok && rl > 0.f && isfinite(rl) && fabsf(rl - r0) <= lim;
+        ok = ok && rd > 0.f && isfinite(rd) && fabsf(rd - r0) <= lim;
+        ok = ok && ru > 0.f && isfinite(ru) && fabsf(ru - r0) <= lim;
+        if (ok) {
+            // P(l) = x~_l / rho;  dx = P(l+x) - P(l-x),  dy = P(l+y) - P(l-y)
+            const float xr = ((float)(u + 1) - a.cx) * a.ifx, xl = ((float)(u - 1) - a.cx) * a.ifx;
+            const float xc = ((float)u - a.cx) * a.ifx;
+            const float yd = ((float)(v + 1) - a.cy) * a.ify, yu = ((float)(v - 1) - a.cy) * a.ify;
+            const float yc = ((float)v - a.cy) * a.ify;
+            const float irr = 1.f / rr, irl = 1.f / rl, ird = 1.f / rd, iru = 1.f / ru;
+            const float dx0 = xr * irr - xl * irl, dx1 = yc * irr - yc * irl, dx2 = irr - irl;
+            const float dy0 = xc * ird - xc * iru, dy1 = yd * ird - yu * iru, dy2 = ird - iru;
+            float n0 = dx1 * dy2 - dx2 * dy1;
+            float n1 = dx2 * dy0 - dx0 * dy2;
+            float n2 = dx0 * dy1 - dx1 * dy0;
+            const float nn = sqrtf(n0 * n0 + n1 * n1 + n2 * n2);
+            if (nn > 0.f && isfinite(nn)) {
+                n0 /= nn; n1 /= nn; n2 /= nn;
+                const float b = n0 * xc + n1 * yc + n2;          // n . x~_l (sign of n . P)
+                if (b > 0.f) { n0 = -n0; n1 = -n1; n2 = -n2; }
+                out = make_float4(r0 * n0, r0 * n1, r0 * n2, b > 0.f ? -b : b);
+            }
+        }
+    }
+    B.normals[j] = out;
+}
+
+__device__ __forceinline__ void robust(int kind, float scale, float r, float& psi, float& w) {
+    const float ar = fabsf(r);
+    if (kind == 0) {
+        if (ar <= scale) { psi = 0.5f * r * r; w = 1.f; }
+        else { psi = scale * (ar - 0.5f * scale); w = scale / ar; }
+    } else {
+        const float z = r / scale;
+        psi = 0.5f * scale * scale * log1pf(z * z);
+        w = 1.f / fmaf(z, z, 1.f);
+    }
+}
+
+__global__ void __launch_bounds__(VD_BLOCK)
+k_align_step(AlignArgs a, AlignBufs B, int final_pass) {
+    __shared__ double red[(VD_BLOCK / 64) * 29];
+    __shared__ PoseF Tsh;
+    __shared__ int flag;
+    const int tid = threadIdx.x;
+    const int pair = blockIdx.y;
+    if (B.status[pair] != 0) return;          // frozen after a singular step (uniform per pair)
+    if (tid == 0) pose_to_f(B.pose + 6 * pair, &Tsh);
+    __syncthreads();
+    const PoseF T = Tsh;
+    const size_t plane = (size_t)a.H * a.W;
+    const float* R2 = B.idepth2 + (size_t)pair * plane;
+    const float* C2 = B.conf2 + (size_t)pair * plane;
+    const float4* NB = B.normals + (size_t)pair * plane;
+    const float is = 1.f / a.s;
+    double acc[29];
+#pragma unroll
+    for (int k = 0; k < 29; ++k) acc[k] = 0.0;
+    for (int j = blockIdx.x * VD_BLOCK + tid; j < (int)plane; j += gridDim.x * VD_BLOCK) {
+        const float rho2 = R2[j], c2 = C2[j];
+        if (!(rho2 > 0.f) || !isfinite(rho2) || !isfinite(c2)) continue;
+        const int v = j / a.W, u = j - v * a.W;
+        const float x0 = ((float)u - a.cx) * a.ifx, x1 = ((float)v - a.cy) * a.ify;
+        // Q~ = rho2 (R X2 + t) = R x~ + rho2 t
+        const float Qx = fmaf(rho2, T.t[0], fmaf(T.r[0], x0, fmaf(T.r[1], x1, T.r[2])));
+        const float Qy = fmaf(rho2, T.t[1], fmaf(T.r[3], x0, fmaf(T.r[4], x1, T.r[5])));
+        const float Qz = fmaf(rho2, T.t[2], fmaf(T.r[6], x0, fmaf(T.r[7], x1, T.r[8])));
+        if (!(Qz > 0.f)) continue;
+        const float iz = 1.f / Qz;
+        const float lx = floorf(fmaf(a.fx, Qx * iz, a.cx) + 0.5f);
+        const float ly = floorf(fmaf(a.fy, Qy * iz, a.cy) + 0.5f);
+        if (!(lx >= 1.f && lx <= (float)(a.W - 2) && ly >= 1.f && ly <= (float)(a.H - 2))) continue;
+        const float4 nb = NB[(int)ly * a.W + (int)lx];
+        if (!isfinite(nb.x)) continue;
+        const float r = (rho2 * nb.w - (nb.x * Qx + nb.y * Qy + nb.z * Qz)) * is * iz;
+        // d = -(A/s + r e_z) / Q~_z ;  J_w = d (-[Q~]x),  J_v = rho2 d
+        const float d0 = -nb.x * is * iz, d1 = -nb.y * is * iz, d2 = -(nb.z * is + r) * iz;
+        const float J[6] = {-d1 * Qz + d2 * Qy, d0 * Qz - d2 * Qx, -d0 * Qy + d1 * Qx,
+                            rho2 * d0, rho2 * d1, rho2 * d2};
+        float psi, wr;
+        robust(a.robust, a.scale, r, psi, wr);
+        const float W = c2 * wr;
+        int k = 1;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+#pragma unroll
+            for (int l = i; l < 6; ++l) acc[k++] += (double)(W * J[i] * J[l]);
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) acc[22 + i] += (double)(W * J[i] * r);
+        acc[0] += (double)(c2 * psi);
+        acc[28] += 1.0;
+    }
+    block_reduce<29>(acc, red);
+    double* part = B.partials + ((size_t)pair * gridDim.x + blockIdx.x) * 29;
+    if (tid < 29) part[tid] = red[tid];
+    if (!last_block(B.counters + pair, gridDim.x, &flag)) return;
+    if (tid < 29) {
+        const double* pc = B.partials + (size_t)pair * gridDim.x * 29;
+        double s = 0.0;
+        for (unsigned bi = 0; bi < gridDim.x; ++bi) s += __builtin_nontemporal_load(pc + (size_t)bi * 29 + tid);
+        red[tid] = s;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    B.counters[pair] = 0u;
+    double H[36], g[6], x[6];
+    int k = 1;
+    for (int i = 0; i < 6; ++i)
+        for (int l = i; l < 6; ++l) { H[6 * i + l] = H[6 * l + i] = red[k++]; }
+    for (int i = 0; i < 6; ++i) g[i] = -red[22 + i];
+    double* st = B.stats + 4 * pair;
+    if (!final_pass) {
+        if (st[3] == 0.0) st[0] = red[0];
+        if (chol6_solve(H, g, x)) {
+            left_update(B.pose + 6 * pair, x);
+            st[3] += 1.0;
+        } else {
+            // ESINGULAR: the pose keeps the completed steps; cost and count at that pose
+            B.status[pair] = 4;
+            st[1] = red[0];
+            st[2] = red[28];
+            for (int i = 0; i < 36; ++i) B.cov[36 * pair + i] = __builtin_nan("");
+        }
+        return;
+    }
+    if (st[3] == 0.0) st[0] = red[0];
+    st[1] = red[0];
+    st[2] = red[28];
+    double* cov = B.cov + 36 * pair;
+    bool ok = true;
+    for (int c = 0; c < 6 && ok; ++c) {
+        double e[6] = {0, 0, 0, 0, 0, 0};
+        e[c] = 1.0;
+        ok = chol6_solve(H, e, x);
+        for (int i = 0; i < 6; ++i) cov[6 * i + c] = x[i];
+    }
+    if (!ok) {
+        for (int i = 0; i < 36; ++i) cov[i] = __builtin_nan("");
+        B.status[pair] = 4;
+    }
+}
+
+hipError_t launch_align_prepare(const AlignArgs& a, const AlignBufs& b, hipStream_t st) {
+    const size_t n = (size_t)a.H * a.W * a.n_pairs;
+    hipLaunchKernelGGL(k_align_prepare, dim3((unsigned)((n + VD_BLOCK - 1) / VD_BLOCK)), dim3(VD_BLOCK), 0, st, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_align_step(const AlignArgs& a, const AlignBufs& b, int final_pass, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_align_step, dim3(nblocks, a.n_pairs), dim3(VD_BLOCK), 0, st, a, b, final_pass);
+    return hipGetLastError();
+}
+
+}  // namespace vd

@@ -1,0 +1,467 @@
+// C ABI of the library: context and scratch management, argument validation, and the
+// launch sequences of the GEM entry points and of keyframe alignment.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/voldor.h"
+#include "device.h"
+#include "kernels.h"
+
+struct voldor_ctx_s {
+    int device = 0;
+    std::string err;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int n_cu = 256;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+constexpr size_t kCounterSlots = 4096;     // per-candidate / per-pair last-block counters
+constexpr size_t kLevelLdsMax = 150 * 1024;
+
+int fail(voldor_ctx ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(voldor_ctx ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_create_err = buf;
+    return code;
+}
+
+int hip_fail(voldor_ctx ctx, hipError_t e, const char* what) {
+    return fail(ctx, VOLDOR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define VD_CHECK(call, what)                                   \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what);  \
+    } while (0)
+
+inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Scratch layout: [counters | poses | region A | region B]; grown on demand.
+struct Scratch {
+    unsigned* counters;
+    vd::PoseF* poses;
+    char* a;
+};
+
+int ensure_scratch(voldor_ctx ctx, size_t extra, hipStream_t st, Scratch& s) {
+    const size_t head = align_up(kCounterSlots * sizeof(unsigned)) + align_up((VD_NMAX + VD_PMAX) * sizeof(vd::PoseF));
+    const size_t need = head + align_up(extra);
+    if (need > ctx->scratch_bytes) {
+        VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+        if (ctx->scratch) {
+            VD_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
+            VD_CHECK(hipFree(ctx->scratch), "hipFree");
+            ctx->scratch = nullptr;
+            ctx->scratch_bytes = 0;
+        }
+        const size_t bytes = need + need / 4;
+        if (hipMalloc(&ctx->scratch, bytes) != hipSuccess) {
+            ctx->scratch = nullptr;
+            return fail(ctx, VOLDOR_ENOMEM, "scratch allocation of %zu bytes failed", bytes);
+        }
+        VD_CHECK(hipMemset(ctx->scratch, 0, align_up(kCounterSlots * sizeof(unsigned))), "hipMemset");
+        ctx->scratch_bytes = bytes;
+    }
+    char* p = (char*)ctx->scratch;
+    s.counters = (unsigned*)p;
+    p += align_up(kCounterSlots * sizeof(unsigned));
+    s.poses = (vd::PoseF*)p;
+    p += align_up((VD_NMAX + VD_PMAX) * sizeof(vd::PoseF));
+    s.a = p;
+    return VOLDOR_OK;
+}
+
+int lattice(int H, int W, int s, int* hc, int* wc) {
+    const int o = s / 2;
+    if (s < 1 || H <= o || W <= o) return 0;
+    *hc = (H - o + s - 1) / s;
+    *wc = (W - o + s - 1) / s;
+    return 1;
+}
+
+int check_window(voldor_ctx ctx, const voldor_window* w, const voldor_buffers* b) {
+    if (!ctx) return VOLDOR_EINVAL;
+    if (!w || !b) return fail(ctx, VOLDOR_EINVAL, "null window or buffer struct");
+    if (w->H < 1 || w->W < 1 || (int64_t)w->H * w->W > (1 << 28))
+        return fail(ctx, VOLDOR_EINVAL, "bad image size %dx%d", w->W, w->H);
+    if (w->N < 1 || w->N > VD_NMAX) return fail(ctx, VOLDOR_EINVAL, "N=%d outside 1..%d", w->N, VD_NMAX);
+    if (w->P < 0 || w->P > VD_PMAX) return fail(ctx, VOLDOR_EINVAL, "P=%d outside 0..%d", w->P, VD_PMAX);
+    if (!(w->fx > 0) || !(w->fy > 0) || !std::isfinite(w->cx) || !std::isfinite(w->cy))
+        return fail(ctx, VOLDOR_EINVAL, "bad intrinsics");
+    if (!(w->fisk_alpha > 0) || !(w->fisk_beta >= 1.0f && w->fisk_beta <= 4.0f))
+        return fail(ctx, VOLDOR_EINVAL, "bad log-logistic parameters (alpha > 0, beta in [1, 4])");
+    if (!(w->outlier_density > 0)) return fail(ctx, VOLDOR_EINVAL, "outlier_density must be > 0");
+    if (!(w->hmm_gamma > 0.5f && w->hmm_gamma <= 1.0f)) return fail(ctx, VOLDOR_EINVAL, "hmm_gamma must be in (0.5, 1]");
+    if (!(w->idepth_min > 0) || !(w->idepth_max > w->idepth_min))
+        return fail(ctx, VOLDOR_EINVAL, "need 0 < idepth_min < idepth_max");
+    if (!(w->perturb_sigma0 >= 0)) return fail(ctx, VOLDOR_EINVAL, "perturb_sigma0 must be >= 0");
+    if (w->P > 0 && (!(w->prior_sigma_rel > 0) || !(w->prior_uniform_rel > 0) ||
+                     !(w->prior_inlier_default >= 0 && w->prior_inlier_default <= 1)))
+        return fail(ctx, VOLDOR_EINVAL, "bad prior constants");
+    if (w->n_candidates < 3 || w->n_candidates > 64) return fail(ctx, VOLDOR_EINVAL, "n_candidates outside 3..64");
+    int hc, wc;
+    if (!lattice(w->H, w->W, w->coarse_stride, &hc, &wc)) return fail(ctx, VOLDOR_EINVAL, "bad coarse_stride");
+    if (hc > 2048 || wc > 2048) return fail(ctx, VOLDOR_EINVAL, "coarse lattice longer than 2048 along an axis");
+    const int T = w->tile;
+    if (!(T == 8 || T == 16 || T == 32 || T == 64 || T == 128 || T == 256))
+        return fail(ctx, VOLDOR_EINVAL, "tile must be 8, 16, 32, 64, 128 or 256");
+    if (w->pose_gn_steps < 0 || w->pose_gn_steps > 100) return fail(ctx, VOLDOR_EINVAL, "pose_gn_steps outside 0..100");
+    if (w->chain_axis != 0 && w->chain_axis != 1) return fail(ctx, VOLDOR_EINVAL, "chain_axis must be 0 or 1");
+    if (!b->flow || !b->pose || !b->idepth || !b->rigid || !b->idepth_coarse || !b->rigid_coarse)
+        return fail(ctx, VOLDOR_EINVAL, "null buffer pointer");
+    if (w->P > 0 && (!b->prior_idepth || !b->prior_pose)) return fail(ctx, VOLDOR_EINVAL, "null prior pointer");
+    return VOLDOR_OK;
+}
+
+vd::Win make_win(const voldor_window* v, int it, int level, const voldor_buffers* b = nullptr) {
+    vd::Win w;
+    std::memset(&w, 0, sizeof(w));
+    w.H = v->H; w.W = v->W; w.N = v->N; w.P = v->P;
+    w.fx = v->fx; w.fy = v->fy; w.cx = v->cx; w.cy = v->cy;
+    w.ifx = (float)(1.0 / (double)v->fx);
+    w.ify = (float)(1.0 / (double)v->fy);
+    const double al = v->fisk_alpha, be = v->fisk_beta, L0 = v->outlier_density;
+    w.inv_a2 = (float)(1.0 / (al * al));
+    w.beta = (float)be;
+    w.beta2 = (v->fisk_beta == 2.0f);
+    w.fl_c = w.beta2 ? (float)(L0 * M_PI * al * al) : (float)std::log2(L0 * 2.0 * M_PI * al * al / be);
+    w.zfloor = be < 2.0 ? 1e-3f : 0.0f;
+    w.ln_L0 = (float)std::log(L0);
+    w.gamma = v->hmm_gamma;
+    w.rmin = v->idepth_min; w.rmax = v->idepth_max;
+    w.sigma_it = (float)std::fmax(v->perturb_sigma0 * std::ldexp(1.0, -(it / 2)), 0.005);
+    w.csig = v->prior_sigma_rel;
+    w.log2kappa = v->P > 0 ? (float)std::log2(std::sqrt(2.0 * M_PI) * v->prior_sigma_rel / v->prior_uniform_rel) : 0.f;
+    w.pi_default = v->prior_inlier_default;
+    w.K = v->n_candidates;
+    w.s = v->coarse_stride;
+    lattice(v->H, v->W, v->coarse_stride, &w.hc, &w.wc);
+    w.it = it; w.level = level; w.dir = it & 3;
+    w.chain_axis = v->chain_axis;
+    w.key0 = (uint32_t)(v->seed & 0xffffffffu);
+    w.key1 = (uint32_t)(v->seed >> 32);
+    w.window_id = v->window_id;
+    w.has_prior_weight = (b && v->P > 0 && b->prior_weight) ? 1 : 0;
+    return w;
+}
+
+vd::LevelGeom make_geom(const voldor_window* v, const vd::Win& w, int level, int it) {
+    vd::LevelGeom g;
+    g.horizontal = ((it & 3) % 2 == 0);
+    if (level == VOLDOR_LEVEL_COARSE) {
+        g.h = w.hc; g.w = w.wc; g.s = w.s; g.off = w.s / 2;
+        g.seg = g.horizontal ? g.w : g.h;
+    } else {
+        g.h = v->H; g.w = v->W; g.s = 1; g.off = 0;
+        g.seg = v->tile;
+    }
+    // one lane per (chain, frame) in the forward-backward phase: C * N <= block size
+    g.C = std::max(1, std::min(VD_BLOCK / g.seg, VD_BLOCK / v->N));
+    const int axis = g.horizontal ? g.w : g.h;
+    const int lines = g.horizontal ? g.h : g.w;
+    g.nseg = (axis + g.seg - 1) / g.seg;
+    g.nblocks = g.nseg * ((lines + g.C - 1) / g.C);
+    return g;
+}
+
+struct GemLaunch {
+    voldor_ctx ctx;
+    const voldor_window* v;
+    const voldor_buffers* b;
+    hipStream_t st;
+    Scratch s;
+    double* ll_partial;
+    double* pose_partials;
+    int pose_blocks;
+    int max_level_blocks;
+};
+
+int gem_prepare(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, hipStream_t st, GemLaunch& L,
+                int n_cand = 1) {
+    L.ctx = ctx; L.v = v; L.b = b; L.st = st;
+    vd::Win w0 = make_win(v, 0, 1);
+    int mx = 0;
+    for (int lvl = 0; lvl < 2; ++lvl)
+        for (int d = 0; d < 2; ++d) mx = std::max(mx, make_geom(v, w0, lvl, d).nblocks);
+    L.max_level_blocks = mx;
+    const int64_t npix = (int64_t)v->H * v->W;
+    L.pose_blocks = (int)std::min<int64_t>(std::max<int64_t>(1, (npix + VD_BLOCK - 1) / VD_BLOCK), 2048);
+    const int fin_blocks = (int)((npix + VD_BLOCK - 1) / VD_BLOCK);
+    const size_t ll_bytes = align_up(sizeof(double) * mx);
+    const size_t pp_bytes = align_up(sizeof(double) * 29 * (size_t)L.pose_blocks * n_cand);
+    const size_t fin_bytes = align_up(sizeof(double) * 5 * (size_t)fin_blocks);
+    int rc = ensure_scratch(ctx, ll_bytes + std::max(pp_bytes, fin_bytes), st, L.s);
+    if (rc) return rc;
+    L.ll_partial = (double*)L.s.a;
+    L.pose_partials = (double*)(L.s.a + ll_bytes);
+    return VOLDOR_OK;
+}
+
+int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll) {
+    voldor_ctx ctx = L.ctx;
+    const vd::Win w = make_win(L.v, it, level, L.b);
+    const vd::LevelGeom g = make_geom(L.v, w, level, it);
+    const size_t lds = vd::level_lds_bytes(g);
+    if (lds > kLevelLdsMax) return fail(ctx, VOLDOR_EINVAL, "chain segment too long for LDS (%zu bytes)", lds);
+    vd::LevelBufs B;
+    B.P = L.s.poses;
+    B.flow = (const float2*)L.b->flow;
+    B.idepth = L.b->idepth;
+    B.idepth_coarse = L.b->idepth_coarse;
+    B.prior = L.b->prior_idepth;
+    B.prior_weight = L.b->prior_weight;
+    float* q = level == VOLDOR_LEVEL_COARSE ? L.b->rigid_coarse : L.b->rigid;
+    B.q_out = q;
+    B.q_in = q;
+    B.rho_out = level == VOLDOR_LEVEL_COARSE ? L.b->idepth_coarse : L.b->idepth;
+    B.ll_partial = want_ll ? L.ll_partial : nullptr;
+    VD_CHECK(vd::launch_level(w, g, B, do_e, do_m, L.st), "level kernel launch");
+    return VOLDOR_OK;
+}
+
+int run_pose_step(GemLaunch& L) {
+    voldor_ctx ctx = L.ctx;
+    vd::Win w = make_win(L.v, 0, 1);
+    vd::PoseBufs B;
+    B.P = L.s.poses;
+    B.flow = (const float2*)L.b->flow;
+    B.idepth = L.b->idepth;
+    B.rigid = L.b->rigid;
+    B.pose = L.b->pose;
+    B.partials = L.pose_partials;
+    B.counters = L.s.counters;
+    B.out = nullptr;
+    for (int t = 1; t <= L.v->N; ++t)
+        for (int k = 0; k < L.v->pose_gn_steps; ++k)
+            VD_CHECK(vd::launch_pose(w, B, t, nullptr, 1, 1, L.pose_blocks, L.st), "pose kernel launch");
+    return VOLDOR_OK;
+}
+
+int prep_poses(GemLaunch& L) {
+    voldor_ctx ctx = L.ctx;
+    VD_CHECK(vd::launch_pose_prep(L.b->pose, L.v->N, L.b->prior_pose, L.v->P, L.s.poses, L.st), "pose prep launch");
+    return VOLDOR_OK;
+}
+
+}  // namespace
+
+// ======================================================================================
+extern "C" {
+
+int voldor_ctx_create(voldor_ctx* out, int device_ordinal) {
+    if (!out) return fail(nullptr, VOLDOR_EINVAL, "null output pointer");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device_ordinal < 0 || device_ordinal >= n)
+        return fail(nullptr, VOLDOR_EINVAL, "device %d not available (%d devices)", device_ordinal, n);
+    voldor_ctx c = new (std::nothrow) voldor_ctx_s;
+    if (!c) return fail(nullptr, VOLDOR_ENOMEM, "context allocation failed");
+    c->device = device_ordinal;
+    if (hipSetDevice(device_ordinal) != hipSuccess) {
+        delete c;
+        return fail(nullptr, VOLDOR_EDEVICE, "hipSetDevice(%d) failed", device_ordinal);
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device_ordinal) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    if (vd::set_level_lds_limit(kLevelLdsMax) != hipSuccess) {
+        delete c;
+        return fail(nullptr, VOLDOR_EDEVICE, "cannot raise the LDS limit of the level kernel");
+    }
+    *out = c;
+    return VOLDOR_OK;
+}
+
+void voldor_ctx_destroy(voldor_ctx ctx) {
+    if (!ctx) return;
+    if (ctx->scratch) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->scratch);
+    }
+    delete ctx;
+}
+
+const char* voldor_last_error(voldor_ctx ctx) {
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int voldor_lattice_shape(int32_t H, int32_t W, int32_t stride, int32_t* Hc, int32_t* Wc) {
+    int hc, wc;
+    if (!Hc || !Wc || !lattice(H, W, stride, &hc, &wc)) return VOLDOR_EINVAL;
+    *Hc = hc;
+    *Wc = wc;
+    return VOLDOR_OK;
+}
+
+int voldor_init_idepth(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    VD_CHECK(vd::launch_init(make_win(v, 0, 1), b->idepth, st), "init launch");
+    return VOLDOR_OK;
+}
+
+int voldor_rigidness_fb(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int iter, int level,
+                        void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    if (iter < 0 || iter > 0xffffff || (level != 0 && level != 1)) return fail(ctx, VOLDOR_EINVAL, "bad iter/level");
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    GemLaunch L;
+    if ((rc = gem_prepare(ctx, v, b, st, L))) return rc;
+    if ((rc = prep_poses(L))) return rc;
+    return run_level(L, iter, level, 1, 0, false);
+}
+
+int voldor_depth_update(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int iter, int level,
+                        void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    if (iter < 0 || iter > 0xffffff || (level != 0 && level != 1)) return fail(ctx, VOLDOR_EINVAL, "bad iter/level");
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    GemLaunch L;
+    if ((rc = gem_prepare(ctx, v, b, st, L))) return rc;
+    if ((rc = prep_poses(L))) return rc;
+    return run_level(L, iter, level, 0, 1, false);
+}
+
+int voldor_pose_score(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int t, int n_cand,
+                      const double* cand_pose, double* out, void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    if (t < 1 || t > v->N) return fail(ctx, VOLDOR_EINVAL, "t=%d outside 1..N", t);
+    if (n_cand < 1 || n_cand > (int)kCounterSlots || !cand_pose || !out)
+        return fail(ctx, VOLDOR_EINVAL, "bad candidate set");
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    GemLaunch L;
+    if ((rc = gem_prepare(ctx, v, b, st, L, n_cand))) return rc;
+    if ((rc = prep_poses(L))) return rc;
+    vd::PoseBufs B;
+    B.P = L.s.poses;
+    B.flow = (const float2*)b->flow;
+    B.idepth = b->idepth;
+    B.rigid = b->rigid;
+    B.pose = b->pose;
+    B.partials = L.pose_partials;
+    B.counters = L.s.counters;
+    B.out = out;
+    VD_CHECK(vd::launch_pose(make_win(v, 0, 1), B, t, cand_pose, n_cand, 0, L.pose_blocks, st), "pose score launch");
+    return VOLDOR_OK;
+}
+
+int voldor_pose_step(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    GemLaunch L;
+    if ((rc = gem_prepare(ctx, v, b, st, L))) return rc;
+    if ((rc = prep_poses(L))) return rc;
+    return run_pose_step(L);
+}
+
+int voldor_gem_step(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int iter, void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    if (iter < 0 || iter > 0xffffff) return fail(ctx, VOLDOR_EINVAL, "bad iter");
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    GemLaunch L;
+    if ((rc = gem_prepare(ctx, v, b, st, L))) return rc;
+    if ((rc = prep_poses(L))) return rc;
+    if ((rc = run_level(L, iter, VOLDOR_LEVEL_COARSE, 1, 1, false))) return rc;
+    if ((rc = run_level(L, iter, VOLDOR_LEVEL_LOCAL, 1, 1, false))) return rc;
+    return run_pose_step(L);
+}
+
+int voldor_finalize(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int iter, void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    if (!b->conf || !b->stats) return fail(ctx, VOLDOR_EINVAL, "null conf/stats pointer");
+    if (iter < 0 || iter > 0xffffff) return fail(ctx, VOLDOR_EINVAL, "bad iter");
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    GemLaunch L;
+    if ((rc = gem_prepare(ctx, v, b, st, L))) return rc;
+    if ((rc = prep_poses(L))) return rc;
+    if ((rc = run_level(L, iter, VOLDOR_LEVEL_LOCAL, 1, 0, true))) return rc;
+    const vd::Win w = make_win(v, iter, 1, b);
+    const vd::LevelGeom g = make_geom(v, w, 1, iter);
+    vd::FinalBufs B;
+    B.P = L.s.poses;
+    B.flow = (const float2*)b->flow;
+    B.idepth = b->idepth;
+    B.rigid = b->rigid;
+    B.prior = b->prior_idepth;
+    B.prior_weight = b->prior_weight;
+    B.conf = b->conf;
+    B.stats = b->stats;
+    B.partials = L.pose_partials;
+    B.ll_partial = L.ll_partial;
+    B.counter = L.s.counters;
+    VD_CHECK(vd::launch_finalize(w, B, g.nblocks, st), "finalize launch");
+    return VOLDOR_OK;
+}
+
+int voldor_align_p2p(voldor_ctx ctx, const voldor_align_params* ap, int n_pairs, const float* idepth1,
+                     const float* idepth2, const float* conf2, double* pose_inout, double* cov_out,
+                     double* stats_out, int32_t* status_out, void* stream) {
+    if (!ctx) return VOLDOR_EINVAL;
+    if (!ap) return fail(ctx, VOLDOR_EINVAL, "null params");
+    if (n_pairs < 0 || n_pairs > (int)kCounterSlots) return fail(ctx, VOLDOR_EINVAL, "n_pairs outside 0..%zu", kCounterSlots);
+    if (n_pairs == 0) return VOLDOR_OK;
+    if (ap->H < 3 || ap->W < 3 || (int64_t)ap->H * ap->W > (1 << 28)) return fail(ctx, VOLDOR_EINVAL, "bad image size");
+    if (!(ap->fx > 0) || !(ap->fy > 0)) return fail(ctx, VOLDOR_EINVAL, "bad intrinsics");
+    if (ap->robust != 0 && ap->robust != 1) return fail(ctx, VOLDOR_EINVAL, "robust must be 0 or 1");
+    if (!(ap->robust_scale > 0) || !(ap->scale_s > 0) || !(ap->normal_disc_rel > 0))
+        return fail(ctx, VOLDOR_EINVAL, "robust_scale, scale_s and normal_disc_rel must be > 0");
+    if (ap->gn_steps < 0 || ap->gn_steps > 1000) return fail(ctx, VOLDOR_EINVAL, "gn_steps outside 0..1000");
+    if (!idepth1 || !idepth2 || !conf2 || !pose_inout || !cov_out || !stats_out || !status_out)
+        return fail(ctx, VOLDOR_EINVAL, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t plane = (size_t)ap->H * ap->W;
+    const int nblk = (int)std::min<size_t>(std::max<size_t>(1, (plane + VD_BLOCK * 4 - 1) / (VD_BLOCK * 4)), 512);
+    const size_t nrm_bytes = align_up(sizeof(float4) * plane * n_pairs);
+    const size_t part_bytes = align_up(sizeof(double) * 29 * nblk * (size_t)n_pairs);
+    Scratch s;
+    int rc = ensure_scratch(ctx, nrm_bytes + part_bytes, st, s);
+    if (rc) return rc;
+    vd::AlignArgs a;
+    a.H = ap->H; a.W = ap->W;
+    a.fx = ap->fx; a.fy = ap->fy; a.cx = ap->cx; a.cy = ap->cy;
+    a.ifx = (float)(1.0 / (double)ap->fx);
+    a.ify = (float)(1.0 / (double)ap->fy);
+    a.robust = ap->robust; a.scale = ap->robust_scale; a.disc = ap->normal_disc_rel; a.s = ap->scale_s;
+    a.n_pairs = n_pairs;
+    vd::AlignBufs B;
+    B.idepth1 = idepth1; B.idepth2 = idepth2; B.conf2 = conf2;
+    B.normals = (float4*)s.a;
+    B.partials = (double*)(s.a + nrm_bytes);
+    B.pose = pose_inout; B.cov = cov_out; B.stats = stats_out; B.status = status_out;
+    B.counters = s.counters;
+    VD_CHECK(vd::launch_align_prepare(a, B, st), "align prepare launch");
+    for (int k = 0; k < ap->gn_steps; ++k) VD_CHECK(vd::launch_align_step(a, B, 0, nblk, st), "align step launch");
+    VD_CHECK(vd::launch_align_step(a, B, 1, nblk, st), "align final launch");
+    return VOLDOR_OK;
+}
+
+}  // extern "C"

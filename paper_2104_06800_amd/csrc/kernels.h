@@ -1,0 +1,95 @@
+// Internal interface between the C-ABI layer (api.hip) and the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vd {
+
+struct PoseF;
+struct Win;
+
+// Chain geometry of one launch of the level kernel.
+struct LevelGeom {
+    int h, w;          // level grid (coarse lattice or full image)
+    int s, off;        // full-resolution coordinate = s * index + off
+    int seg;           // chain segment length (tile, or a whole lattice row / column)
+    int horizontal;    // chains run along x
+    int C;             // chain segments per block
+    int nseg;          // segments per line
+    int nblocks;
+};
+
+struct LevelBufs {
+    const PoseF* P;
+    const float2* flow;
+    const float* idepth;         // full resolution, read
+    const float* idepth_coarse;  // slot 2 source (local level)
+    const float* prior;
+    const float* prior_weight;
+    float* q_out;                // E-step output (level grid)
+    const float* q_in;           // M-step input when the E-step is not fused
+    float* rho_out;              // M-step output (coarse lattice or full image)
+    double* ll_partial;          // per-block log-likelihood, or null
+};
+
+struct PoseBufs {
+    PoseF* P;
+    const float2* flow;
+    const float* idepth;
+    const float* rigid;
+    double* pose;
+    double* partials;
+    unsigned* counters;
+    double* out;
+};
+
+struct FinalBufs {
+    const PoseF* P;
+    const float2* flow;
+    const float* idepth;
+    const float* rigid;
+    const float* prior;
+    const float* prior_weight;
+    float* conf;
+    double* stats;
+    double* partials;
+    const double* ll_partial;
+    unsigned* counter;
+};
+
+struct AlignArgs {
+    int H, W;
+    float fx, fy, cx, cy, ifx, ify;
+    int robust;
+    float scale;
+    float disc;
+    float s;
+    int n_pairs;
+};
+
+struct AlignBufs {
+    const float* idepth1;
+    const float* idepth2;
+    const float* conf2;
+    float4* normals;
+    double* pose;
+    double* cov;
+    double* stats;
+    int32_t* status;
+    double* partials;
+    unsigned* counters;
+};
+
+size_t level_lds_bytes(const LevelGeom& g);
+hipError_t launch_pose_prep(const double* pose, int N, const double* prior_pose, int P, PoseF* out, hipStream_t st);
+hipError_t launch_init(const Win& w, float* idepth, hipStream_t st);
+hipError_t launch_level(const Win& w, const LevelGeom& g, const LevelBufs& b, int do_e, int do_m, hipStream_t st);
+hipError_t launch_pose(const Win& w, const PoseBufs& b, int t, const double* cand, int n_cand, int solve,
+                       int nblocks, hipStream_t st);
+hipError_t launch_finalize(const Win& w, const FinalBufs& b, int n_ll, hipStream_t st);
+hipError_t set_level_lds_limit(size_t bytes);
+
+hipError_t launch_align_prepare(const AlignArgs& a, const AlignBufs& b, hipStream_t st);
+hipError_t launch_align_step(const AlignArgs& a, const AlignBufs& b, int final_pass, int nblocks, hipStream_t st);
+
+}  // namespace vd
