@@ -53,7 +53,7 @@ typedef struct voldor_ctx_s* voldor_ctx;
 
 /* Window geometry and model constants (host struct, passed by pointer). */
 typedef struct {
-    int32_t H, W;              /* image size                                              */
+    int32_t H, W;              /* image size, both >= 2                                   */
     int32_t N;                 /* flows in the window, 1..8                               */
     int32_t P;                 /* depth priors, 0..4                                      */
     float fx, fy, cx, cy;      /* pinhole intrinsics                                      */
@@ -140,6 +140,12 @@ int voldor_pose_score(voldor_ctx ctx, const voldor_window* win, const voldor_buf
 int voldor_pose_step(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
                      void* stream);
 
+/* One pass of one level: its E-step immediately followed by its M-step (same chains,
+ * direction iter mod 4), fused in a single launch; equivalent to voldor_rigidness_fb then
+ * voldor_depth_update on the same level. */
+int voldor_level_step(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
+                      int iter, int level, void* stream);
+
 /* One GEM iteration: coarse E+M, local E+M, pose step (each level fused in one launch). */
 int voldor_gem_step(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
                     int iter, void* stream);
@@ -147,7 +153,7 @@ int voldor_gem_step(voldor_ctx ctx, const voldor_window* win, const voldor_buffe
 /* Final local E-step (direction iter mod 4), confidence C^j = (sum_t q_t + sum_k q^_k)/(N+P)
  * (Eq. 6) and statistics: [0] log-likelihood (sum of chain log Z, densities in px^-2),
  * [1] MIE energy sum_j E_j(rho_j) (natural log), [2] valid flow terms, [3] invalid flow
- * terms, [4] prior terms present (q^ > 0), [5] sum of C, [6..7] 0. */
+ * terms, [4] prior terms with a valid transfer (not a hole), [5] sum of C, [6..7] 0. */
 int voldor_finalize(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
                     int iter, void* stream);
 

@@ -487,7 +487,8 @@ def finalize(win, bufs, it):
 
     C^j = (sum_t q_t^j + sum_k q^_k^j) / (N + P)   (Eq. 6; holes count with q^ = 0).
     stats: [0] log-likelihood sum of log Z, [1] MIE energy sum_j E_j(rho_j),
-           [2] valid flow terms, [3] invalid flow terms, [4] prior terms present,
+           [2] valid flow terms, [3] invalid flow terms, [4] prior terms with a valid
+           transfer (not a hole) at the final depth,
            [5] sum of C, [6], [7] zero."""
     w = Window(win, bufs)
     loglik = rigidness_fb(win, bufs, it, LOCAL)
@@ -504,7 +505,7 @@ def finalize(win, bufs, it):
     stats[1] = E.sum()
     stats[2] = ok.sum()
     stats[3] = ok.size - ok.sum()
-    stats[4] = (qhat > 0).sum()
+    stats[4] = sum(int(w.prior_z(k, lv.u, lv.v, rho)[1].sum()) for k in range(w.P))
     stats[5] = conf.sum()
     bufs["stats"][...] = stats
     return stats

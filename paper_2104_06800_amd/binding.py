@@ -48,9 +48,10 @@ class AlignParams(ctypes.Structure):
                 ("normal_disc_rel", ctypes.c_float), ("scale_s", ctypes.c_float)]
 
 
-EXPORTS = ["voldor_ctx_create", "voldor_ctx_destroy", "voldor_last_error", "voldor_lattice_shape",
-           "voldor_init_idepth", "voldor_rigidness_fb", "voldor_depth_update", "voldor_pose_score",
-           "voldor_pose_step", "voldor_gem_step", "voldor_finalize", "voldor_align_p2p"]
+EXPORTS = sorted(["voldor_ctx_create", "voldor_ctx_destroy", "voldor_last_error", "voldor_lattice_shape",
+                  "voldor_init_idepth", "voldor_rigidness_fb", "voldor_depth_update", "voldor_level_step",
+                  "voldor_pose_score", "voldor_pose_step", "voldor_gem_step", "voldor_finalize",
+                  "voldor_align_p2p"])
 
 
 def load_library(path=LIB):
@@ -69,6 +70,7 @@ def load_library(path=LIB):
     lib.voldor_init_idepth.argtypes = [V, W, B, V]
     lib.voldor_rigidness_fb.argtypes = [V, W, B, I, I, V]
     lib.voldor_depth_update.argtypes = [V, W, B, I, I, V]
+    lib.voldor_level_step.argtypes = [V, W, B, I, I, V]
     lib.voldor_pose_score.argtypes = [V, W, B, I, I, V, V, V]
     lib.voldor_pose_step.argtypes = [V, W, B, V]
     lib.voldor_gem_step.argtypes = [V, W, B, I, V]
@@ -188,6 +190,10 @@ class Voldor:
     def depth_update(self, p, b, it, level, stream=None):
         self._check(_LIB.voldor_depth_update(self._h, make_window(p), self._bufs(p, b), it, level,
                                              _stream(stream)), "voldor_depth_update")
+
+    def level_step(self, p, b, it, level, stream=None):
+        self._check(_LIB.voldor_level_step(self._h, make_window(p), self._bufs(p, b), it, level,
+                                           _stream(stream)), "voldor_level_step")
 
     def pose_score(self, p, b, t, cand, stream=None):
         cand = torch.as_tensor(cand, dtype=torch.float64).to(b["pose"].device).reshape(-1, 6).contiguous()

@@ -73,10 +73,9 @@ __device__ __forceinline__ void robust(int kind, float scale, float r, float& ps
 }
 
 __global__ void __launch_bounds__(VD_BLOCK)
-k_align_step(AlignArgs a, AlignBufs B, int final_pass) {
+k_align_step(AlignArgs a, AlignBufs B) {
     __shared__ double red[(VD_BLOCK / 64) * 29];
     __shared__ PoseF Tsh;
-    __shared__ int flag;
     const int tid = threadIdx.x;
     const int pair = blockIdx.y;
     if (B.status[pair] != 0) return;          // frozen after a singular step (uniform per pair)
@@ -127,18 +126,18 @@ k_align_step(AlignArgs a, AlignBufs B, int final_pass) {
         acc[28] += 1.0;
     }
     block_reduce<29>(acc, red);
-    double* part = B.partials + ((size_t)pair * gridDim.x + blockIdx.x) * 29;
-    if (tid < 29) part[tid] = red[tid];
-    if (!last_block(B.counters + pair, gridDim.x, &flag)) return;
-    if (tid < 29) {
-        const double* pc = B.partials + (size_t)pair * gridDim.x * 29;
-        double s = 0.0;
-        for (unsigned bi = 0; bi < gridDim.x; ++bi) s += __builtin_nontemporal_load(pc + (size_t)bi * 29 + tid);
-        red[tid] = s;
-    }
-    __syncthreads();
-    if (tid != 0) return;
-    B.counters[pair] = 0u;
+    if (tid < 29) B.partials[((size_t)pair * 29 + tid) * gridDim.x + blockIdx.x] = red[tid];
+}
+
+// One block per pair: sum the pair's block records (fixed order), then the FP64 solve and
+// pose update, or (final pass) the covariance.
+__global__ void __launch_bounds__(VD_BLOCK)
+k_align_finish(AlignBufs B, unsigned nb, int final_pass) {
+    __shared__ double red[(VD_BLOCK / 64) * 29];
+    const int pair = blockIdx.x;
+    if (B.status[pair] != 0) return;
+    reduce_partials<29>(B.partials + (size_t)pair * nb * 29, nb, red);
+    if (threadIdx.x != 0) return;
     double H[36], g[6], x[6];
     int k = 1;
     for (int i = 0; i < 6; ++i)
@@ -183,7 +182,10 @@ hipError_t launch_align_prepare(const AlignArgs& a, const AlignBufs& b, hipStrea
 }
 
 hipError_t launch_align_step(const AlignArgs& a, const AlignBufs& b, int final_pass, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_align_step, dim3(nblocks, a.n_pairs), dim3(VD_BLOCK), 0, st, a, b, final_pass);
+    hipLaunchKernelGGL(k_align_step, dim3(nblocks, a.n_pairs), dim3(VD_BLOCK), 0, st, a, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_align_finish, dim3(a.n_pairs), dim3(VD_BLOCK), 0, st, b, (unsigned)nblocks, final_pass);
     return hipGetLastError();
 }
 

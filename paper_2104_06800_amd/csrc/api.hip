@@ -23,7 +23,7 @@ namespace {
 
 thread_local std::string g_create_err;
 
-constexpr size_t kCounterSlots = 4096;     // per-candidate / per-pair last-block counters
+constexpr size_t kMaxBatch = 4096;         // candidates per pose_score call / pairs per align call
 constexpr size_t kLevelLdsMax = 150 * 1024;
 
 int fail(voldor_ctx ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
@@ -50,15 +50,15 @@ int hip_fail(voldor_ctx ctx, hipError_t e, const char* what) {
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Scratch layout: [counters | poses | region A | region B]; grown on demand.
+// Scratch layout: [FP32 poses | FP64 poses | work region]; grown on demand.
 struct Scratch {
-    unsigned* counters;
     vd::PoseF* poses;
+    vd::PoseD* posed;
     char* a;
 };
 
 int ensure_scratch(voldor_ctx ctx, size_t extra, hipStream_t st, Scratch& s) {
-    const size_t head = align_up(kCounterSlots * sizeof(unsigned)) + align_up((VD_NMAX + VD_PMAX) * sizeof(vd::PoseF));
+    const size_t head = align_up((VD_NMAX + VD_PMAX) * sizeof(vd::PoseF)) + align_up(VD_NMAX * sizeof(vd::PoseD));
     const size_t need = head + align_up(extra);
     if (need > ctx->scratch_bytes) {
         VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
@@ -73,14 +73,13 @@ int ensure_scratch(voldor_ctx ctx, size_t extra, hipStream_t st, Scratch& s) {
             ctx->scratch = nullptr;
             return fail(ctx, VOLDOR_ENOMEM, "scratch allocation of %zu bytes failed", bytes);
         }
-        VD_CHECK(hipMemset(ctx->scratch, 0, align_up(kCounterSlots * sizeof(unsigned))), "hipMemset");
         ctx->scratch_bytes = bytes;
     }
     char* p = (char*)ctx->scratch;
-    s.counters = (unsigned*)p;
-    p += align_up(kCounterSlots * sizeof(unsigned));
     s.poses = (vd::PoseF*)p;
     p += align_up((VD_NMAX + VD_PMAX) * sizeof(vd::PoseF));
+    s.posed = (vd::PoseD*)p;
+    p += align_up(VD_NMAX * sizeof(vd::PoseD));
     s.a = p;
     return VOLDOR_OK;
 }
@@ -96,7 +95,7 @@ int lattice(int H, int W, int s, int* hc, int* wc) {
 int check_window(voldor_ctx ctx, const voldor_window* w, const voldor_buffers* b) {
     if (!ctx) return VOLDOR_EINVAL;
     if (!w || !b) return fail(ctx, VOLDOR_EINVAL, "null window or buffer struct");
-    if (w->H < 1 || w->W < 1 || (int64_t)w->H * w->W > (1 << 28))
+    if (w->H < 2 || w->W < 2 || (int64_t)w->H * w->W > (1 << 28))
         return fail(ctx, VOLDOR_EINVAL, "bad image size %dx%d", w->W, w->H);
     if (w->N < 1 || w->N > VD_NMAX) return fail(ctx, VOLDOR_EINVAL, "N=%d outside 1..%d", w->N, VD_NMAX);
     if (w->P < 0 || w->P > VD_PMAX) return fail(ctx, VOLDOR_EINVAL, "P=%d outside 0..%d", w->P, VD_PMAX);
@@ -175,6 +174,8 @@ vd::LevelGeom make_geom(const voldor_window* v, const vd::Win& w, int level, int
     const int lines = g.horizontal ? g.h : g.w;
     g.nseg = (axis + g.seg - 1) / g.seg;
     g.nblocks = g.nseg * ((lines + g.C - 1) / g.C);
+    // the coarse level's long chains run many nodes per propagated value: deeper speculation
+    g.spec = level == VOLDOR_LEVEL_COARSE ? VD_SPEC : 1;
     return g;
 }
 
@@ -186,6 +187,14 @@ struct GemLaunch {
     Scratch s;
     double* ll_partial;
     double* pose_partials;
+    float* pa_E;          // coarse-level phase-A results [Hc*Wc]
+    float* pa_V;
+    int* pa_S;
+    float* pa_spec;       // [VD_SPEC][Hc*Wc]
+    float4* flow2;        // [N][H][W] row-pair layout of the flows
+    vd::PoseD* hist;      // pose history of a pose step
+    float2* obs;          // [H][W] observed displacements
+    int gn_blocks;
     int pose_blocks;
     int max_level_blocks;
 };
@@ -199,15 +208,35 @@ int gem_prepare(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b,
         for (int d = 0; d < 2; ++d) mx = std::max(mx, make_geom(v, w0, lvl, d).nblocks);
     L.max_level_blocks = mx;
     const int64_t npix = (int64_t)v->H * v->W;
-    L.pose_blocks = (int)std::min<int64_t>(std::max<int64_t>(1, (npix + VD_BLOCK - 1) / VD_BLOCK), 2048);
+    // ~4 pixels per thread: enough blocks to fill the chip, few partial records
+    L.pose_blocks = (int)std::min<int64_t>(std::max<int64_t>(1, (npix + 2 * VD_BLOCK - 1) / (2 * VD_BLOCK)), 2048);
     const int fin_blocks = (int)((npix + VD_BLOCK - 1) / VD_BLOCK);
     const size_t ll_bytes = align_up(sizeof(double) * mx);
     const size_t pp_bytes = align_up(sizeof(double) * 29 * (size_t)L.pose_blocks * n_cand);
     const size_t fin_bytes = align_up(sizeof(double) * 5 * (size_t)fin_blocks);
-    int rc = ensure_scratch(ctx, ll_bytes + std::max(pp_bytes, fin_bytes), st, L.s);
+    const size_t red_bytes = std::max(pp_bytes, fin_bytes);
+    const size_t lat = (size_t)w0.hc * w0.wc;
+    const size_t pa_bytes = align_up(sizeof(float) * lat);
+    const size_t f2_bytes = align_up(sizeof(float4) * (size_t)npix * v->N);
+    // pose step: one block per 1024 pixels keeps the per-block prologue cheap
+    L.gn_blocks = (int)std::min<int64_t>(std::max<int64_t>(1, (npix + 4 * VD_BLOCK - 1) / (4 * VD_BLOCK)), 256);
+    const size_t gnp_bytes = align_up(sizeof(double) * 29 * 2 * (size_t)L.gn_blocks);
+    const size_t hist_bytes = align_up(sizeof(vd::PoseD) * (size_t)v->N * std::max(1, v->pose_gn_steps));
+    const size_t obs_bytes = align_up(sizeof(float2) * (size_t)npix);
+    const size_t red2_bytes = std::max(red_bytes, gnp_bytes);
+    int rc = ensure_scratch(ctx, f2_bytes + hist_bytes + obs_bytes + ll_bytes + red2_bytes + (3 + VD_SPEC) * pa_bytes,
+                            st, L.s);
     if (rc) return rc;
-    L.ll_partial = (double*)L.s.a;
-    L.pose_partials = (double*)(L.s.a + ll_bytes);
+    L.flow2 = (float4*)L.s.a;
+    L.hist = (vd::PoseD*)(L.s.a + f2_bytes);
+    L.obs = (float2*)(L.s.a + f2_bytes + hist_bytes);
+    char* q = L.s.a + f2_bytes + hist_bytes + obs_bytes;
+    L.ll_partial = (double*)q;
+    L.pose_partials = (double*)(q + ll_bytes);
+    L.pa_E = (float*)(q + ll_bytes + red2_bytes);
+    L.pa_V = (float*)(q + ll_bytes + red2_bytes + pa_bytes);
+    L.pa_S = (int*)(q + ll_bytes + red2_bytes + 2 * pa_bytes);
+    L.pa_spec = (float*)(q + ll_bytes + red2_bytes + 3 * pa_bytes);
     return VOLDOR_OK;
 }
 
@@ -220,6 +249,7 @@ int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll)
     vd::LevelBufs B;
     B.P = L.s.poses;
     B.flow = (const float2*)L.b->flow;
+    B.flow2 = L.flow2;
     B.idepth = L.b->idepth;
     B.idepth_coarse = L.b->idepth_coarse;
     B.prior = L.b->prior_idepth;
@@ -229,6 +259,19 @@ int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll)
     B.q_in = q;
     B.rho_out = level == VOLDOR_LEVEL_COARSE ? L.b->idepth_coarse : L.b->idepth;
     B.ll_partial = want_ll ? L.ll_partial : nullptr;
+    B.pa_E = L.pa_E;
+    B.pa_V = L.pa_V;
+    B.pa_S = L.pa_S;
+    B.pa_spec = L.pa_spec;
+    if (level == VOLDOR_LEVEL_COARSE && do_m) {
+        // few long chains: E-step per chain, phase A over the whole lattice, then the
+        // per-chain speculation + scan from the stored phase-A results
+        if (do_e) VD_CHECK(vd::launch_level(w, g, B, 1, 0, L.st), "level kernel launch");
+        VD_CHECK(vd::launch_phase_a(w, g, B, L.st), "phase A launch");
+        VD_CHECK(vd::launch_phase_a2(w, g, B, L.st), "phase A2 launch");
+        VD_CHECK(vd::launch_level(w, g, B, 0, 2, L.st), "level kernel launch");
+        return VOLDOR_OK;
+    }
     VD_CHECK(vd::launch_level(w, g, B, do_e, do_m, L.st), "level kernel launch");
     return VOLDOR_OK;
 }
@@ -238,22 +281,29 @@ int run_pose_step(GemLaunch& L) {
     vd::Win w = make_win(L.v, 0, 1);
     vd::PoseBufs B;
     B.P = L.s.poses;
+    B.PD = L.s.posed;
     B.flow = (const float2*)L.b->flow;
+    B.flow2 = L.flow2;
     B.idepth = L.b->idepth;
     B.rigid = L.b->rigid;
     B.pose = L.b->pose;
     B.partials = L.pose_partials;
-    B.counters = L.s.counters;
     B.out = nullptr;
-    for (int t = 1; t <= L.v->N; ++t)
-        for (int k = 0; k < L.v->pose_gn_steps; ++k)
-            VD_CHECK(vd::launch_pose(w, B, t, nullptr, 1, 1, L.pose_blocks, L.st), "pose kernel launch");
+    B.hist = L.hist;
+    B.obs = L.obs;
+    const int G = L.v->pose_gn_steps;
+    if (G == 0) return VOLDOR_OK;
+    for (int s = 0; s < L.v->N * G; ++s)
+        VD_CHECK(vd::launch_pose_gn(w, B, s, G, L.gn_blocks, L.st), "pose step launch");
+    VD_CHECK(vd::launch_pose_gn_finish(B, L.v->N, G, L.gn_blocks, L.st), "pose finish launch");
     return VOLDOR_OK;
 }
 
 int prep_poses(GemLaunch& L) {
     voldor_ctx ctx = L.ctx;
-    VD_CHECK(vd::launch_pose_prep(L.b->pose, L.v->N, L.b->prior_pose, L.v->P, L.s.poses, L.st), "pose prep launch");
+    VD_CHECK(vd::launch_pose_prep(L.b->pose, L.v->N, L.b->prior_pose, L.v->P, L.s.poses, L.s.posed, L.st),
+             "pose prep launch");
+    VD_CHECK(vd::launch_flow_pairs((const float2*)L.b->flow, L.flow2, L.v->N, L.v->H, L.v->W, L.st), "flow layout launch");
     return VOLDOR_OK;
 }
 
@@ -342,12 +392,25 @@ int voldor_depth_update(voldor_ctx ctx, const voldor_window* v, const voldor_buf
     return run_level(L, iter, level, 0, 1, false);
 }
 
+int voldor_level_step(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int iter, int level,
+                      void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    if (iter < 0 || iter > 0xffffff || (level != 0 && level != 1)) return fail(ctx, VOLDOR_EINVAL, "bad iter/level");
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    GemLaunch L;
+    if ((rc = gem_prepare(ctx, v, b, st, L))) return rc;
+    if ((rc = prep_poses(L))) return rc;
+    return run_level(L, iter, level, 1, 1, false);
+}
+
 int voldor_pose_score(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int t, int n_cand,
                       const double* cand_pose, double* out, void* stream) {
     int rc = check_window(ctx, v, b);
     if (rc) return rc;
     if (t < 1 || t > v->N) return fail(ctx, VOLDOR_EINVAL, "t=%d outside 1..N", t);
-    if (n_cand < 1 || n_cand > (int)kCounterSlots || !cand_pose || !out)
+    if (n_cand < 1 || n_cand > (int)kMaxBatch || !cand_pose || !out)
         return fail(ctx, VOLDOR_EINVAL, "bad candidate set");
     hipStream_t st = (hipStream_t)stream;
     VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
@@ -356,12 +419,13 @@ int voldor_pose_score(voldor_ctx ctx, const voldor_window* v, const voldor_buffe
     if ((rc = prep_poses(L))) return rc;
     vd::PoseBufs B;
     B.P = L.s.poses;
+    B.PD = L.s.posed;
     B.flow = (const float2*)b->flow;
+    B.flow2 = L.flow2;
     B.idepth = b->idepth;
     B.rigid = b->rigid;
     B.pose = b->pose;
     B.partials = L.pose_partials;
-    B.counters = L.s.counters;
     B.out = out;
     VD_CHECK(vd::launch_pose(make_win(v, 0, 1), B, t, cand_pose, n_cand, 0, L.pose_blocks, st), "pose score launch");
     return VOLDOR_OK;
@@ -408,6 +472,7 @@ int voldor_finalize(voldor_ctx ctx, const voldor_window* v, const voldor_buffers
     vd::FinalBufs B;
     B.P = L.s.poses;
     B.flow = (const float2*)b->flow;
+    B.flow2 = L.flow2;
     B.idepth = b->idepth;
     B.rigid = b->rigid;
     B.prior = b->prior_idepth;
@@ -416,7 +481,6 @@ int voldor_finalize(voldor_ctx ctx, const voldor_window* v, const voldor_buffers
     B.stats = b->stats;
     B.partials = L.pose_partials;
     B.ll_partial = L.ll_partial;
-    B.counter = L.s.counters;
     VD_CHECK(vd::launch_finalize(w, B, g.nblocks, st), "finalize launch");
     return VOLDOR_OK;
 }
@@ -426,7 +490,7 @@ int voldor_align_p2p(voldor_ctx ctx, const voldor_align_params* ap, int n_pairs,
                      double* stats_out, int32_t* status_out, void* stream) {
     if (!ctx) return VOLDOR_EINVAL;
     if (!ap) return fail(ctx, VOLDOR_EINVAL, "null params");
-    if (n_pairs < 0 || n_pairs > (int)kCounterSlots) return fail(ctx, VOLDOR_EINVAL, "n_pairs outside 0..%zu", kCounterSlots);
+    if (n_pairs < 0 || n_pairs > (int)kMaxBatch) return fail(ctx, VOLDOR_EINVAL, "n_pairs outside 0..%zu", kMaxBatch);
     if (n_pairs == 0) return VOLDOR_OK;
     if (ap->H < 3 || ap->W < 3 || (int64_t)ap->H * ap->W > (1 << 28)) return fail(ctx, VOLDOR_EINVAL, "bad image size");
     if (!(ap->fx > 0) || !(ap->fy > 0)) return fail(ctx, VOLDOR_EINVAL, "bad intrinsics");
@@ -457,7 +521,6 @@ int voldor_align_p2p(voldor_ctx ctx, const voldor_align_params* ap, int n_pairs,
     B.normals = (float4*)s.a;
     B.partials = (double*)(s.a + nrm_bytes);
     B.pose = pose_inout; B.cov = cov_out; B.stats = stats_out; B.status = status_out;
-    B.counters = s.counters;
     VD_CHECK(vd::launch_align_prepare(a, B, st), "align prepare launch");
     for (int k = 0; k < ap->gn_steps; ++k) VD_CHECK(vd::launch_align_step(a, B, 0, nblk, st), "align step launch");
     VD_CHECK(vd::launch_align_step(a, B, 1, nblk, st), "align final launch");

@@ -11,6 +11,7 @@
 #define VD_NMAX 8
 #define VD_PMAX 4
 #define VD_BLOCK 256
+#define VD_SPEC 4       // maximum speculation depth of the chain scan
 #define VD_LN2 0.69314718055994530942f
 #define VD_LOG2E 1.44269504088896340736f
 
@@ -22,8 +23,14 @@ namespace vd {
 struct PoseF {          // rotation (row-major) and translation, FP32 copy of a 6-vector
     float r[9];
     float t[3];
+    float d[9];         // R - I, rounded from FP64 (keeps small rotations at full precision)
     int ident;          // the 6-vector is exactly zero (identity transfer)
-    int pad[3];
+    int pad[2];
+};
+
+struct PoseD {          // FP64 rotation matrix (row-major) and translation of a frame
+    double R[9];
+    double t[3];
 };
 
 struct Win {
@@ -128,9 +135,57 @@ __device__ inline void log_so3(const double R[9], double w[3]) {
 __device__ inline void pose_to_f(const double* p, PoseF* out) {
     double R[9];
     exp_so3(p, R);
-    for (int i = 0; i < 9; ++i) out->r[i] = (float)R[i];
+    for (int i = 0; i < 9; ++i) {
+        out->r[i] = (float)R[i];
+        out->d[i] = (float)(R[i] - ((i & 3) == 0 ? 1.0 : 0.0));
+    }
     for (int i = 0; i < 3; ++i) out->t[i] = (float)p[3 + i];
     out->ident = (p[0] == 0.0 && p[1] == 0.0 && p[2] == 0.0 && p[3] == 0.0 && p[4] == 0.0 && p[5] == 0.0);
+}
+
+// exp([w]x) for the small increments of a Gauss-Newton step: Rodrigues coefficients by their
+// Taylor series (exact to double rounding for |w| < 0.1), sin/cos beyond.
+__device__ inline void exp_so3_small(const double w[3], double R[9]) {
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    if (th2 >= 1e-2) { exp_so3(w, R); return; }
+    const double a = 1.0 + th2 * (-1.0 / 6 + th2 * (1.0 / 120 + th2 * (-1.0 / 5040 + th2 * (1.0 / 362880 - th2 / 39916800))));
+    const double b = 0.5 + th2 * (-1.0 / 24 + th2 * (1.0 / 720 + th2 * (-1.0 / 40320 + th2 * (1.0 / 3628800 - th2 / 479001600))));
+    R[0] = 1.0 + b * (w[0] * w[0] - th2);
+    R[4] = 1.0 + b * (w[1] * w[1] - th2);
+    R[8] = 1.0 + b * (w[2] * w[2] - th2);
+    R[1] = -a * w[2] + b * w[0] * w[1];
+    R[3] = a * w[2] + b * w[0] * w[1];
+    R[2] = a * w[1] + b * w[0] * w[2];
+    R[6] = -a * w[1] + b * w[0] * w[2];
+    R[5] = -a * w[0] + b * w[1] * w[2];
+    R[7] = a * w[0] + b * w[1] * w[2];
+}
+
+__device__ inline void posed_from_vec(const double* p, PoseD* out) {
+    exp_so3(p, out->R);
+    out->t[0] = p[3]; out->t[1] = p[4]; out->t[2] = p[5];
+}
+
+__device__ inline void posef_from_d(const PoseD& D, PoseF* out) {
+    for (int i = 0; i < 9; ++i) {
+        out->r[i] = (float)D.R[i];
+        out->d[i] = (float)(D.R[i] - ((i & 3) == 0 ? 1.0 : 0.0));
+    }
+    for (int i = 0; i < 3; ++i) out->t[i] = (float)D.t[i];
+    out->ident = 0;
+}
+
+// (R, t) <- (exp([dw]x) R, exp([dw]x) t + dv) on the FP64 matrix form
+__device__ inline void left_update_d(PoseD* P, const double* d) {
+    double E[9], R2[9], t2[3];
+    exp_so3_small(d, E);
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+            R2[3 * i + j] = E[3 * i] * P->R[j] + E[3 * i + 1] * P->R[3 + j] + E[3 * i + 2] * P->R[6 + j];
+        t2[i] = E[3 * i] * P->t[0] + E[3 * i + 1] * P->t[1] + E[3 * i + 2] * P->t[2] + d[3 + i];
+    }
+    for (int i = 0; i < 9; ++i) P->R[i] = R2[i];
+    for (int i = 0; i < 3; ++i) P->t[i] = t2[i];
 }
 
 // p <- (exp([dw]x) R, exp([dw]x) t + dv)
@@ -149,9 +204,9 @@ __device__ inline void left_update(double* p, const double* d) {
 }
 
 // Solve A x = b (6x6 SPD, row-major) by Cholesky; false when a pivot is not finite or not
-// above 1e-12 times the largest diagonal entry.
+// above 1e-12 times the largest diagonal entry.  One division per pivot (its reciprocal).
 __device__ inline bool chol6_solve(const double* A, const double* b, double* x) {
-    double L[36];
+    double L[36], inv[6];
     double dmax = 0.0;
     for (int i = 0; i < 6; ++i) dmax = fmax(dmax, A[7 * i]);
     const double tol = 1e-12 * dmax;
@@ -162,8 +217,9 @@ __device__ inline bool chol6_solve(const double* A, const double* b, double* x) 
             if (i == j) {
                 if (!(s > tol) || !isfinite(s)) return false;
                 L[6 * i + i] = sqrt(s);
+                inv[i] = 1.0 / L[6 * i + i];
             } else {
-                L[6 * i + j] = s / L[6 * j + j];
+                L[6 * i + j] = s * inv[j];
             }
         }
     }
@@ -171,12 +227,12 @@ __device__ inline bool chol6_solve(const double* A, const double* b, double* x) 
     for (int i = 0; i < 6; ++i) {
         double s = b[i];
         for (int k = 0; k < i; ++k) s -= L[6 * i + k] * y[k];
-        y[i] = s / L[6 * i + i];
+        y[i] = s * inv[i];
     }
     for (int i = 5; i >= 0; --i) {
         double s = y[i];
         for (int k = i + 1; k < 6; ++k) s -= L[6 * k + i] * x[k];
-        x[i] = s / L[6 * i + i];
+        x[i] = s * inv[i];
     }
     return true;
 }
@@ -188,14 +244,23 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ float log2f_fast(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float exp2f_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// log2(1 + 2^y)
-__device__ __forceinline__ float softplus2(float y) {
-    return y > 24.f ? y : log2f_fast(1.f + exp2f_fast(y));
+// log2(1 + x) for x >= 0 with the rounding of 1 + x compensated (u - 1 is exact for
+// u in [1, 2]), so small arguments keep full relative precision
+__device__ __forceinline__ float log2_1p(float x) {
+    const float u = 1.f + x;
+    const float d = u - 1.f;
+    return d == 0.f ? x * VD_LOG2E : log2f_fast(u) * (x * rcp(d));
 }
 
-// log2(L0 / L1(r)) of the log-logistic planar density, r^2 given
+// log2(1 + 2^y)
+__device__ __forceinline__ float softplus2(float y) {
+    return y > 24.f ? y : log2_1p(exp2f_fast(y));
+}
+
+// log2(L0 / L1(r)) of the log-logistic planar density, r^2 given.  B2: shape == 2.
+template <bool B2>
 __device__ __forceinline__ float log2_ratio(const Win& w, float r2) {
-    if (w.beta2) {
+    if (B2) {
         const float s = fmaf(r2, w.inv_a2, 1.f);
         return log2f_fast(w.fl_c * s * s);
     }
@@ -206,17 +271,19 @@ __device__ __forceinline__ float log2_ratio(const Win& w, float r2) {
 }
 
 // MIE cost of a valid flow term, log2(1 + L0/L1), in log2 units
+template <bool B2>
 __device__ __forceinline__ float flow_cost2(const Win& w, float r2) {
-    if (w.beta2) {
+    if (B2) {
         const float s = fmaf(r2, w.inv_a2, 1.f);
-        return log2f_fast(fmaf(w.fl_c * s, s, 1.f));
+        return log2_1p(w.fl_c * s * s);
     }
-    return softplus2(log2_ratio(w, r2));
+    return softplus2(log2_ratio<false>(w, r2));
 }
 
 // d cost / d r^2 in natural-log units (IRLS weight without q)
+template <bool B2>
 __device__ __forceinline__ float flow_dcost(const Win& w, float r2) {
-    if (w.beta2) {
+    if (B2) {
         const float s = fmaf(r2, w.inv_a2, 1.f);
         const float cs = w.fl_c * s;
         return 2.f * cs * w.inv_a2 / fmaf(cs, s, 1.f);
@@ -227,27 +294,61 @@ __device__ __forceinline__ float flow_dcost(const Win& w, float r2) {
     const float y = exp2f_fast(w.beta * lz);
     const float dlog = w.beta * w.inv_a2 * exp2f_fast((w.beta - 2.f) * lz) / (1.f + y)
                      + (2.f - w.beta) / (2.f * x);
-    const float g = exp2f_fast(log2_ratio(w, r2));
+    const float g = exp2f_fast(log2_ratio<false>(w, r2));
     return g / (1.f + g) * dlog;
 }
 
 // ----------------------------------------------------------------------------------
-// bilinear flow sample on [0, W-1] x [0, H-1]; invalid outside or on non-finite taps
+// bilinear flow sample on [0, W-1] x [0, H-1]; invalid outside or on non-finite taps.
+// Each image row contributes one 16-byte load of two horizontally adjacent taps; at the
+// right / lower border the pair is taken one pixel earlier with weight 1 on its second
+// element (needs W, H >= 2).  Offsets are 32-bit from the frame's base pointer.
 // ----------------------------------------------------------------------------------
+struct __attribute__((aligned(8))) TapPair { float ax, ay, bx, by; };
+
 __device__ __forceinline__ bool sample_flow(const float2* __restrict__ F, int H, int W, float x, float y,
                                             float& fx, float& fy) {
     const bool inside = (x >= 0.f) && (x <= (float)(W - 1)) && (y >= 0.f) && (y <= (float)(H - 1));
-    const float xs = inside ? x : 0.f, ys = inside ? y : 0.f;
-    const int x0 = (int)xs, y0 = (int)ys;
-    const int x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1);
+    float xs = inside ? x : 0.f, ys = inside ? y : 0.f;
+    int x0 = (int)xs, y0 = (int)ys;
+    x0 = min(x0, W - 2);
+    y0 = min(y0, H - 2);
     const float ax = xs - (float)x0, ay = ys - (float)y0;
-    const float2 a = F[y0 * W + x0], b = F[y0 * W + x1];
-    const float2 c = F[y1 * W + x0], d = F[y1 * W + x1];
-    const float tx = fmaf(ax, b.x - a.x, a.x), ty = fmaf(ax, b.y - a.y, a.y);
-    const float bx = fmaf(ax, d.x - c.x, c.x), by = fmaf(ax, d.y - c.y, c.y);
+    const unsigned o = (unsigned)y0 * (unsigned)W + (unsigned)x0;
+    TapPair r0, r1;
+    __builtin_memcpy(&r0, F + o, sizeof(TapPair));
+    __builtin_memcpy(&r1, F + o + (unsigned)W, sizeof(TapPair));
+    const float tx = fmaf(ax, r0.bx - r0.ax, r0.ax), ty = fmaf(ax, r0.by - r0.ay, r0.ay);
+    const float bx = fmaf(ax, r1.bx - r1.ax, r1.ax), by = fmaf(ax, r1.by - r1.ay, r1.ay);
     fx = fmaf(ay, bx - tx, tx);
     fy = fmaf(ay, by - ty, ty);
     return inside && isfinite(fx) && isfinite(fy);
+}
+
+// Same sample from the row-pair layout F2[y][x] = (X(x, y), X(x, y + 1)) (rows 0..H-2): the
+// four taps are 32 contiguous bytes.  Arithmetic identical to sample_flow.
+__device__ __forceinline__ bool sample_flow2(const float4* __restrict__ F2, int H, int W, float x, float y,
+                                             float& fx, float& fy) {
+    const bool inside = (x >= 0.f) && (x <= (float)(W - 1)) && (y >= 0.f) && (y <= (float)(H - 1));
+    float xs = inside ? x : 0.f, ys = inside ? y : 0.f;
+    int x0 = (int)xs, y0 = (int)ys;
+    x0 = min(x0, W - 2);
+    y0 = min(y0, H - 2);
+    const float ax = xs - (float)x0, ay = ys - (float)y0;
+    const unsigned o = (unsigned)y0 * (unsigned)W + (unsigned)x0;
+    const float4 l = F2[o], r = F2[o + 1];
+    const float tx = fmaf(ax, r.x - l.x, l.x), ty = fmaf(ax, r.y - l.y, l.y);
+    const float bx = fmaf(ax, r.z - l.z, l.z), by = fmaf(ax, r.w - l.w, l.w);
+    fx = fmaf(ay, bx - tx, tx);
+    fy = fmaf(ay, by - ty, ty);
+    return inside && isfinite(fx) && isfinite(fy);
+}
+
+// Block index remapped so that each of the 8 XCDs (own L2; workgroups are dispatched to
+// them round-robin) works on a contiguous range of logical blocks.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b & 7, i = b >> 3, per = nb >> 3, rem = nb & 7;
+    return x * per + min(x, rem) + i;
 }
 
 // ----------------------------------------------------------------------------------
@@ -255,33 +356,38 @@ __device__ __forceinline__ bool sample_flow(const float2* __restrict__ F, int H,
 // ----------------------------------------------------------------------------------
 struct Pix {
     float u, v;
-    float ax[VD_NMAX], ay[VD_NMAX], az[VD_NMAX];   // R_t x~
+    float x0, x1;                                  // x~ = ((u - cx)/fx, (v - cy)/fy, 1)
+    float ax[VD_NMAX], ay[VD_NMAX], az[VD_NMAX];   // (R_t - I) x~
     float q[VD_NMAX];                              // rigidness posteriors
-    float o1x, o1y;                                // first observation j + X_1(j)
+    float f1x, f1y;                                // first flow X_1(j)
     bool ok1;
     float qh[VD_PMAX];                             // prior posteriors at the current value
     float rh[VD_PMAX];                             // identity-pose priors: rho^ at the pixel
     float px[VD_PMAX], py[VD_PMAX], pz[VD_PMAX];   // other priors: R^_k x~
 };
 
+template <bool PR>
 __device__ __forceinline__ void pix_geometry(const Win& w, const PoseF* __restrict__ P, const float2* __restrict__ flow,
                                              int u, int v, Pix& c) {
     c.u = (float)u;
     c.v = (float)v;
     const float x0 = ((float)u - w.cx) * w.ifx, x1 = ((float)v - w.cy) * w.ify;
+    c.x0 = x0;
+    c.x1 = x1;
 #pragma unroll
     for (int t = 0; t < VD_NMAX; ++t) {
         if (t < w.N) {
             const PoseF& T = P[t];
-            c.ax[t] = fmaf(T.r[0], x0, fmaf(T.r[1], x1, T.r[2]));
-            c.ay[t] = fmaf(T.r[3], x0, fmaf(T.r[4], x1, T.r[5]));
-            c.az[t] = fmaf(T.r[6], x0, fmaf(T.r[7], x1, T.r[8]));
+            c.ax[t] = fmaf(T.d[0], x0, fmaf(T.d[1], x1, T.d[2]));
+            c.ay[t] = fmaf(T.d[3], x0, fmaf(T.d[4], x1, T.d[5]));
+            c.az[t] = fmaf(T.d[6], x0, fmaf(T.d[7], x1, T.d[8]));
         }
     }
     const float2 f = flow[v * w.W + u];
-    c.o1x = (float)u + f.x;
-    c.o1y = (float)v + f.y;
+    c.f1x = f.x;
+    c.f1y = f.y;
     c.ok1 = isfinite(f.x) && isfinite(f.y);
+    if (!PR) return;
 #pragma unroll
     for (int k = 0; k < VD_PMAX; ++k) {
         if (k < w.P && !P[w.N + k].ident) {
@@ -315,45 +421,108 @@ __device__ __forceinline__ bool prior_z(const Win& w, const PoseF* __restrict__ 
         inv_phi = rho * iz;
     }
     if (!(rh > 0.f) || !isfinite(rh)) return false;
-    z = (rh - inv_phi) / (w.csig * rh);
+    z = (rh - inv_phi) * rcp(w.csig * rh);
     return true;
 }
 
-// E_j(rho) in log2 units: sum_t q_t cost_t + sum_k q^_k cost^_k.
-__device__ __forceinline__ float energy2(const Win& w, const PoseF* __restrict__ P, const float2* __restrict__ flow,
-                                         const float* __restrict__ prior, const Pix& c, float rho) {
-    float E = 0.f;
-    float ppx = c.u, ppy = c.v;
+// Per-frame flow residuals of candidate rho, frames in order: f(t, r^2, valid).
+// Reprojection in displacement form: with D = (R_t - I) x~ + rho t_t the rigid image
+// displacement of frame t is d_t = (fx (D_x - x0 D_z), fy (D_y - x1 D_z)) / (1 + D_z), so
+// p_t = j + d_t and the residual p_t - (p_{t-1} + X_t(p_{t-1})) = d_t - d_{t-1} - X_t is
+// formed from small numbers (no cancellation of image coordinates).
+template <typename F>
+__device__ __forceinline__ void frame_residuals(const Win& w, const PoseF* __restrict__ P,
+                                                const float4* __restrict__ flow2, const Pix& c, float rho, F&& f) {
+    float dpx = 0.f, dpy = 0.f;
     bool zprev = true;
     const size_t plane = (size_t)w.H * w.W;
 #pragma unroll
     for (int t = 0; t < VD_NMAX; ++t) {
         if (t < w.N) {
             const PoseF& T = P[t];
-            const float Qx = fmaf(rho, T.t[0], c.ax[t]);
-            const float Qy = fmaf(rho, T.t[1], c.ay[t]);
-            const float Qz = fmaf(rho, T.t[2], c.az[t]);
+            const float Dx = fmaf(rho, T.t[0], c.ax[t]);
+            const float Dy = fmaf(rho, T.t[1], c.ay[t]);
+            const float Dz = fmaf(rho, T.t[2], c.az[t]);
+            const float Qz = 1.f + Dz;
             const bool zok = Qz > 0.f;
             const float iz = rcp(Qz);
-            const float px = fmaf(w.fx, Qx * iz, w.cx);
-            const float py = fmaf(w.fy, Qy * iz, w.cy);
-            float ox, oy;
+            const float dx = w.fx * fmaf(-c.x0, Dz, Dx) * iz;
+            const float dy = w.fy * fmaf(-c.x1, Dz, Dy) * iz;
+            float fx, fy;
             bool fok;
             if (t == 0) {
-                ox = c.o1x; oy = c.o1y; fok = c.ok1;
+                fx = c.f1x; fy = c.f1y; fok = c.ok1;
             } else {
-                float fx, fy;
-                fok = sample_flow(flow + t * plane, w.H, w.W, ppx, ppy, fx, fy);
-                ox = ppx + fx;
-                oy = ppy + fy;
+                fok = sample_flow2(flow2 + t * plane, w.H, w.W, c.u + dpx, c.v + dpy, fx, fy);
             }
             const bool ok = zprev && zok && fok;
-            const float ex = px - ox, ey = py - oy;
-            const float cost = ok ? flow_cost2(w, fmaf(ex, ex, ey * ey)) : 1.0f;
-            E = fmaf(c.q[t], cost, E);
-            ppx = px; ppy = py; zprev = zok;
+            const float ex = (dx - dpx) - fx, ey = (dy - dpy) - fy;
+            f(t, fmaf(ex, ex, ey * ey), ok);
+            dpx = dx; dpy = dy; zprev = zok;
         }
     }
+}
+
+// E_j(rho) in log2 units: sum_t q_t cost_t + sum_k q^_k cost^_k.  PR: window has priors.
+template <bool B2, bool PR>
+__device__ __forceinline__ float energy2(const Win& w, const PoseF* __restrict__ P, const float4* __restrict__ flow2,
+                                         const float* __restrict__ prior, const Pix& c, float rho) {
+    float E = 0.f;
+    frame_residuals(w, P, flow2, c, rho, [&](int t, float r2, bool ok) {
+        E = fmaf(c.q[t], ok ? flow_cost2<B2>(w, r2) : 1.0f, E);
+    });
+    if (!PR) return E;
+#pragma unroll
+    for (int k = 0; k < VD_PMAX; ++k) {
+        if (k < w.P && c.qh[k] > 0.f) {
+            float z;
+            const float cost = prior_z(w, P, prior, c, k, rho, z)
+                             ? softplus2(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)) : 1.0f;
+            E = fmaf(c.qh[k], cost, E);
+        }
+    }
+    return E;
+}
+
+// E_j(rho) with pruning: all terms are non-negative and the FP32 running sum only grows, so
+// once it passes `bound` the candidate cannot win and the remaining frames (and their flow
+// gathers) are skipped.  STRICT: stop when E > bound (callers that keep ties), otherwise
+// when E >= bound.  A pruned result is a partial sum on the losing side of the bound, so
+// every comparison against the bound is decided exactly as with the full sum.
+template <bool B2, bool PR, bool STRICT>
+__device__ __forceinline__ float energy2_bounded(const Win& w, const PoseF* __restrict__ P,
+                                                 const float4* __restrict__ flow2, const float* __restrict__ prior,
+                                                 const Pix& c, float rho, float bound) {
+    float E = 0.f;
+    float dpx = 0.f, dpy = 0.f;
+    bool zprev = true;
+    const size_t plane = (size_t)w.H * w.W;
+#pragma unroll
+    for (int t = 0; t < VD_NMAX; ++t) {
+        if (t >= w.N) break;
+        const PoseF& T = P[t];
+        const float Dx = fmaf(rho, T.t[0], c.ax[t]);
+        const float Dy = fmaf(rho, T.t[1], c.ay[t]);
+        const float Dz = fmaf(rho, T.t[2], c.az[t]);
+        const float Qz = 1.f + Dz;
+        const bool zok = Qz > 0.f;
+        const float iz = rcp(Qz);
+        const float dx = w.fx * fmaf(-c.x0, Dz, Dx) * iz;
+        const float dy = w.fy * fmaf(-c.x1, Dz, Dy) * iz;
+        float fx, fy;
+        bool fok;
+        if (t == 0) {
+            fx = c.f1x; fy = c.f1y; fok = c.ok1;
+        } else {
+            fok = sample_flow2(flow2 + t * plane, w.H, w.W, c.u + dpx, c.v + dpy, fx, fy);
+        }
+        const bool ok = zprev && zok && fok;
+        const float ex = (dx - dpx) - fx, ey = (dy - dpy) - fy;
+        E = fmaf(c.q[t], ok ? flow_cost2<B2>(w, fmaf(ex, ex, ey * ey)) : 1.0f, E);
+        if (STRICT ? (E > bound) : (E >= bound)) return E;
+        dpx = dx; dpy = dy; zprev = zok;
+    }
+    if (!PR) return E;
 #pragma unroll
     for (int k = 0; k < VD_PMAX; ++k) {
         if (k < w.P && c.qh[k] > 0.f) {
@@ -367,10 +536,14 @@ __device__ __forceinline__ float energy2(const Win& w, const PoseF* __restrict__
 }
 
 // Prior posteriors q^_k at the current value (Eq. 3 mixture): pi N / (pi N + (1 - pi) U).
-__device__ __forceinline__ void prior_posteriors(const Win& w, const PoseF* __restrict__ P,
-                                                 const float* __restrict__ prior, const float* __restrict__ pweight,
-                                                 int pix, Pix& c, float rho_cur) {
+// Returns a bit mask of the priors whose transfer is valid (no hole) at rho_cur.
+template <bool PR>
+__device__ __forceinline__ int prior_posteriors(const Win& w, const PoseF* __restrict__ P,
+                                                const float* __restrict__ prior, const float* __restrict__ pweight,
+                                                int pix, Pix& c, float rho_cur) {
     const size_t plane = (size_t)w.H * w.W;
+    int mask = 0;
+    if (!PR) return 0;
 #pragma unroll
     for (int k = 0; k < VD_PMAX; ++k) {
         c.qh[k] = 0.f;
@@ -378,58 +551,41 @@ __device__ __forceinline__ void prior_posteriors(const Win& w, const PoseF* __re
             if (P[w.N + k].ident) c.rh[k] = prior[k * plane + pix];
             float z;
             if (prior_z(w, P, prior, c, k, rho_cur, z)) {
+                mask |= 1 << k;
                 const float pw = w.has_prior_weight ? pweight[k * plane + pix] : w.pi_default;
                 if (pw > 0.f) {
                     const float odds = (1.f - pw) / pw;
-                    c.qh[k] = 1.f / fmaf(odds, exp2f_fast(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)), 1.f);
+                    c.qh[k] = rcp(fmaf(odds, exp2f_fast(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)), 1.f));
                 }
             }
         }
     }
+    return mask;
 }
 
 // Emission ratio L1/L0 of one frame term at rho (1 for an invalid term); frames in order.
-template <typename F>
-__device__ __forceinline__ void emissions(const Win& w, const PoseF* __restrict__ P, const float2* __restrict__ flow,
+template <bool B2, typename F>
+__device__ __forceinline__ void emissions(const Win& w, const PoseF* __restrict__ P, const float4* __restrict__ flow2,
                                           const Pix& c, float rho, F&& out) {
-    float ppx = c.u, ppy = c.v;
-    bool zprev = true;
-    const size_t plane = (size_t)w.H * w.W;
-#pragma unroll
-    for (int t = 0; t < VD_NMAX; ++t) {
-        if (t < w.N) {
-            const PoseF& T = P[t];
-            const float Qx = fmaf(rho, T.t[0], c.ax[t]);
-            const float Qy = fmaf(rho, T.t[1], c.ay[t]);
-            const float Qz = fmaf(rho, T.t[2], c.az[t]);
-            const bool zok = Qz > 0.f;
-            const float iz = rcp(Qz);
-            const float px = fmaf(w.fx, Qx * iz, w.cx);
-            const float py = fmaf(w.fy, Qy * iz, w.cy);
-            float ox, oy;
-            bool fok;
-            if (t == 0) {
-                ox = c.o1x; oy = c.o1y; fok = c.ok1;
+    frame_residuals(w, P, flow2, c, rho, [&](int t, float r2, bool ok) {
+        float ratio = 1.0f;
+        if (ok) {
+            if (B2) {
+                const float s = fmaf(r2, w.inv_a2, 1.f);
+                ratio = rcp(w.fl_c * s * s);                    // L1 / L0 = 1 / (c s^2)
             } else {
-                float fx, fy;
-                fok = sample_flow(flow + t * plane, w.H, w.W, ppx, ppy, fx, fy);
-                ox = ppx + fx;
-                oy = ppy + fy;
+                ratio = exp2f_fast(-log2_ratio<false>(w, r2));
             }
-            const bool ok = zprev && zok && fok;
-            const float ex = px - ox, ey = py - oy;
-            const float ratio = ok ? exp2f_fast(-log2_ratio(w, fmaf(ex, ex, ey * ey))) : 1.0f;
-            out(t, ratio, ok);
-            ppx = px; ppy = py; zprev = zok;
         }
-    }
+        out(t, ratio, ok);
+    });
 }
 
 // ----------------------------------------------------------------------------------
 // block-level FP64 reduction of NR values held per thread (fixed order)
 // ----------------------------------------------------------------------------------
-template <int NR>
-__device__ __forceinline__ void block_reduce(double* acc, double* red /* [4][NR] in LDS */) {
+template <int NR, int NT = VD_BLOCK>
+__device__ __forceinline__ void block_reduce(double* acc, double* red /* [NT/64][NR] in LDS */) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
@@ -444,23 +600,27 @@ __device__ __forceinline__ void block_reduce(double* acc, double* red /* [4][NR]
     __syncthreads();
     if (tid < NR) {
         double s = 0.0;
-        for (int wv = 0; wv < VD_BLOCK / 64; ++wv) s += red[wv * NR + tid];
+        for (int wv = 0; wv < NT / 64; ++wv) s += red[wv * NR + tid];
         red[tid] = s;      // wave 0's slots: safe, each tid < NR reads all waves before writing its own
     }
 }
 
-// Last-block detection; returns true in every thread of the block that arrives last.
-__device__ __forceinline__ bool last_block(unsigned* counter, unsigned nblocks, int* flag) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned ticket = atomicAdd(counter, 1u);
-        *flag = (ticket == nblocks - 1);
+// Deterministic sum of per-block records stored value-major, part[k * nb + b], b < nb:
+// thread i takes the blocks i, i + 256, ... (coalesced, independent loads), then a
+// fixed-order block reduction.  The NR sums are in red[0..NR-1] after the call (all
+// threads synchronised).
+template <int NR>
+__device__ __forceinline__ void reduce_partials(const double* part, unsigned nb, double* red) {
+    double acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+    for (unsigned b = threadIdx.x; b < nb; b += VD_BLOCK) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] += __builtin_nontemporal_load(part + (size_t)k * nb + b);
     }
     __syncthreads();
-    const bool last = *flag;
-    if (last) __threadfence();
-    return last;
+    block_reduce<NR>(acc, red);
+    __syncthreads();
 }
 
 }  // namespace vd

@@ -10,10 +10,14 @@ namespace vd {
 // pose conversion (FP64 6-vectors -> FP32 R|t for frames and priors)
 // ----------------------------------------------------------------------------------
 __global__ void k_pose_prep(const double* __restrict__ pose, int N, const double* __restrict__ prior_pose, int P,
-                            PoseF* __restrict__ out) {
+                            PoseF* __restrict__ out, PoseD* __restrict__ outd) {
     const int i = threadIdx.x;
-    if (i < N) pose_to_f(pose + 6 * i, out + i);
-    else if (i < N + P) pose_to_f(prior_pose + 6 * (i - N), out + i);
+    if (i < N) {
+        pose_to_f(pose + 6 * i, out + i);
+        posed_from_vec(pose + 6 * i, outd + i);
+    } else if (i < N + P) {
+        pose_to_f(prior_pose + 6 * (i - N), out + i);
+    }
 }
 
 // ----------------------------------------------------------------------------------
@@ -25,6 +29,20 @@ __global__ void k_init_idepth(Win w, float* __restrict__ idepth) {
     const uint4 r = philox10(make_uint4((uint32_t)j, 0u, philox_word2(0, 1, PURPOSE_INIT), w.window_id),
                              w.key0, w.key1);
     idepth[j] = fmaf(unit24(r.x), w.rmax - w.rmin, w.rmin);
+}
+
+// ----------------------------------------------------------------------------------
+// row-pair flow layout for the bilinear samples of frames t >= 2:
+// F2[t][y][x] = (X_t(x, y), X_t(x, y + 1)), y <= H - 2
+// ----------------------------------------------------------------------------------
+__global__ void k_flow_pairs(const float2* __restrict__ flow, float4* __restrict__ f2, int N, int H, int W) {
+    const size_t per = (size_t)(H - 1) * W;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= per * (N - 1)) return;
+    const size_t t = 1 + i / per, r = i - (t - 1) * per;
+    const size_t o = t * (size_t)H * W + r;
+    const float2 a = flow[o], b = flow[o + W];
+    f2[o] = make_float4(a.x, a.y, b.x, b.y);
 }
 
 // ----------------------------------------------------------------------------------
@@ -51,7 +69,7 @@ struct BlockPix {
 
 __device__ __forceinline__ BlockPix block_pix(const LevelGeom& g, int k) {
     BlockPix p;
-    const int b = blockIdx.x;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
     const int sidx = b % g.nseg, lb = b / g.nseg;
     int c, i;
     if (g.horizontal) { c = k / g.seg; i = k - c * g.seg; }
@@ -69,7 +87,7 @@ __device__ __forceinline__ BlockPix block_pix(const LevelGeom& g, int k) {
 
 // number of valid nodes of chain c of this block
 __device__ __forceinline__ int chain_len(const LevelGeom& g, int c) {
-    const int b = blockIdx.x;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
     const int sidx = b % g.nseg, lb = b / g.nseg;
     const int line = lb * g.C + c;
     const int nlines = g.horizontal ? g.h : g.w;
@@ -78,6 +96,7 @@ __device__ __forceinline__ int chain_len(const LevelGeom& g, int c) {
     return min(g.seg, axis - sidx * g.seg);
 }
 
+template <bool B2, bool PR>
 __global__ void __launch_bounds__(VD_BLOCK)
 k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     extern __shared__ float lds[];
@@ -87,8 +106,8 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     float* r_s = q_s + VD_NMAX * nodes;     // [N][C][stride] emission ratios (E-step)
     float* bestE = r_s + VD_NMAX * nodes;   // [C][stride]
     float* bestV = bestE + nodes;
-    float* specE = bestV + nodes;
-    float* rcur = specE + nodes;
+    float* specE = bestV + nodes;           // [VD_SPEC][C][stride]
+    float* rcur = specE + VD_SPEC * nodes;
     float* newV = rcur + nodes;
     int* bestS = (int*)(newV + nodes);
     __shared__ double ll_red[VD_BLOCK / 64];
@@ -105,15 +124,15 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
             const BlockPix p = block_pix(g, k);
             if (!p.valid) continue;
             Pix c;
-            pix_geometry(w, B.P, B.flow, p.u, p.v, c);
+            pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, c);
             const float rho = rho_full[p.v * w.W + p.u];
             const int o = p.c * stride + p.i;
             if (w.chain_axis == 0) {
-                emissions(w, B.P, B.flow, c, rho, [&](int t, float ratio, bool) { r_s[t * nodes + o] = ratio; });
+                emissions<B2>(w, B.P, B.flow2, c, rho, [&](int t, float ratio, bool) { r_s[t * nodes + o] = ratio; });
             } else {
                 // temporal chain over the frame window, in registers
                 float rr[VD_NMAX], al[VD_NMAX];
-                emissions(w, B.P, B.flow, c, rho, [&](int t, float ratio, bool) { rr[t] = ratio; });
+                emissions<B2>(w, B.P, B.flow2, c, rho, [&](int t, float ratio, bool) { rr[t] = ratio; });
                 float logc = 0.f;
                 float a1 = 0.f;
 #pragma unroll
@@ -122,7 +141,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
                         const float p1 = (t == 0) ? 0.5f : fmaf(2.f * w.gamma - 1.f, a1, 1.f - w.gamma);
                         const float x1 = p1 * rr[t];
                         const float cc = (1.f - p1) + x1;
-                        a1 = x1 / cc;
+                        a1 = x1 * rcp(cc);
                         al[t] = a1;
                         logc += log2f_fast(cc);
                     }
@@ -135,10 +154,10 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
                             const float m0 = 1.f - b1, m1 = rr[t + 1] * b1;
                             const float y1 = fmaf(w.gamma, m1, (1.f - w.gamma) * m0);
                             const float y0 = fmaf(w.gamma, m0, (1.f - w.gamma) * m1);
-                            b1 = y1 / (y0 + y1);
+                            b1 = y1 * rcp(y0 + y1);
                         }
                         const float num = al[t] * b1;
-                        q_s[t * nodes + o] = num / fmaf(1.f - al[t], 1.f - b1, num);
+                        q_s[t * nodes + o] = num * rcp(fmaf(1.f - al[t], 1.f - b1, num));
                     }
                 }
                 ll += (double)(logc * VD_LN2) + (double)w.N * (double)w.ln_L0;
@@ -158,7 +177,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
                     const float p1 = (i == 0) ? 0.5f : fmaf(h, a1, 1.f - gm);
                     const float x1 = p1 * r[i];
                     const float cc = (1.f - p1) + x1;
-                    a1 = x1 / cc;
+                    a1 = x1 * rcp(cc);
                     a[i] = a1;
                     logc += log2f_fast(cc);
                 }
@@ -168,11 +187,11 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
                         const float m0 = 1.f - b1, m1 = r[i + 1] * b1;
                         const float y1 = fmaf(gm, m1, (1.f - gm) * m0);
                         const float y0 = fmaf(gm, m0, (1.f - gm) * m1);
-                        b1 = y1 / (y0 + y1);
+                        b1 = y1 * rcp(y0 + y1);
                     }
                     const float ai = a[i];
                     const float num = ai * b1;
-                    a[i] = num / fmaf(1.f - ai, 1.f - b1, num);
+                    a[i] = num * rcp(fmaf(1.f - ai, 1.f - b1, num));
                 }
                 ll += (double)(logc * VD_LN2) + (double)L * (double)w.ln_L0;
             }
@@ -213,24 +232,36 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     const uint32_t word2 = philox_word2(w.it, w.level, PURPOSE_CAND);
     const bool local = (w.level == 1);
 
-    // phase A: parallel over pixels and slots {0, 2, 3..K-1}
-    for (int k = tid; k < npix; k += VD_BLOCK) {
+    // phase A: parallel over pixels and slots {0, 2, 3..K-1} (or precomputed by k_phase_a)
+    if (do_m == 2) {
+        for (int k = tid; k < npix; k += VD_BLOCK) {
+            const BlockPix p = block_pix(g, k);
+            if (!p.valid) continue;
+            const int o = p.c * stride + p.i;
+            bestE[o] = B.pa_E[p.li];
+            bestV[o] = B.pa_V[p.li];
+            bestS[o] = B.pa_S[p.li];
+            rcur[o] = rho_full[p.v * w.W + p.u];
+            for (int d = 0; d < g.spec; ++d) specE[d * nodes + o] = B.pa_spec[d * lplane + p.li];
+        }
+    }
+    for (int k = tid; k < npix && do_m == 1; k += VD_BLOCK) {
         const BlockPix p = block_pix(g, k);
         if (!p.valid) continue;
         const int o = p.c * stride + p.i;
         Pix c;
-        pix_geometry(w, B.P, B.flow, p.u, p.v, c);
+        pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, c);
 #pragma unroll
         for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) c.q[t] = q_s[t * nodes + o];
         const int fpix = p.v * w.W + p.u;
         const float r0 = rho_full[fpix];
-        prior_posteriors(w, B.P, B.prior, B.prior_weight, fpix, c, r0);
-        float bE = energy2(w, B.P, B.flow, B.prior, c, r0), bV = r0;
+        prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, fpix, c, r0);
+        float bE = energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, r0), bV = r0;
         int bS = 0;
         if (local) {
             const int U = min(p.u / w.s, w.wc - 1), V = min(p.v / w.s, w.hc - 1);
             const float rc = B.idepth_coarse[V * w.wc + U];
-            const float e = energy2(w, B.P, B.flow, B.prior, c, rc);
+            const float e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, rc, bE);
             if (e < bE) { bE = e; bV = rc; bS = 2; }
         }
         for (int gi = 0; gi < G; ++gi) {
@@ -244,7 +275,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
                     const float cand = (slot & 1)
                         ? fminf(fmaxf(r0 * fmaf(w.sigma_it, fmaf(2.f, uu, -1.f), 1.f), w.rmin), w.rmax)
                         : fmaf(uu, w.rmax - w.rmin, w.rmin);
-                    const float e = energy2(w, B.P, B.flow, B.prior, c, cand);
+                    const float e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, cand, bE);
                     if (e < bE) { bE = e; bV = cand; bS = slot; }
                 }
             }
@@ -253,21 +284,25 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     }
     __syncthreads();
 
-    // phase A2: energy at the predecessor's phase-A winner
+    // phase A2: energies at the phase-A winners of the g.spec previous nodes of the chain
     const bool fwd = (w.dir < 2);
-    for (int k = tid; k < npix; k += VD_BLOCK) {
+    const int di = fwd ? 1 : -1;
+    for (int k = tid; k < npix && do_m == 1; k += VD_BLOCK) {
         const BlockPix p = block_pix(g, k);
         if (!p.valid) continue;
         const int L = chain_len(g, p.c);
-        const int ip = fwd ? p.i - 1 : p.i + 1;
-        if (ip < 0 || ip >= L) continue;
         const int o = p.c * stride + p.i;
         Pix c;
-        pix_geometry(w, B.P, B.flow, p.u, p.v, c);
+        pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, c);
 #pragma unroll
         for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) c.q[t] = q_s[t * nodes + o];
-        prior_posteriors(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, c, rcur[o]);
-        specE[o] = energy2(w, B.P, B.flow, B.prior, c, bestV[p.c * stride + ip]);
+        prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, c, rcur[o]);
+        for (int d = 0; d < g.spec; ++d) {
+            const int ip = p.i - (d + 1) * di;
+            if (ip < 0 || ip >= L) break;
+            specE[d * nodes + o] =
+                energy2_bounded<B2, PR, true>(w, B.P, B.flow2, B.prior, c, bestV[p.c * stride + ip], bestE[o]);
+        }
     }
     __syncthreads();
 
@@ -276,7 +311,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
         const int c = tid;
         const int L = chain_len(g, c);
         if (L > 0) {
-            const int i0 = fwd ? 0 : L - 1, di = fwd ? 1 : -1;
+            const int i0 = fwd ? 0 : L - 1;
             const int base = c * stride;
             float carried = bestV[base + i0];
             int src = i0;
@@ -284,18 +319,19 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
             for (int n = 1, i = i0 + di; n < L; ++n, i += di) {
                 const int o = base + i;
                 float e1;
-                if (src == i - di) {
-                    e1 = specE[o];
+                const int dist = (i - src) * di;           // steps back to the carried value's node
+                if (dist <= g.spec) {
+                    e1 = specE[(dist - 1) * nodes + o];
                 } else {
                     // storage-order node i of chain c -> block linear index
                     const int kk = g.horizontal ? (c * g.seg + i) : (i * g.C + c);
                     const BlockPix p = block_pix(g, kk);
                     Pix cx;
-                    pix_geometry(w, B.P, B.flow, p.u, p.v, cx);
+                    pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, cx);
 #pragma unroll
                     for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) cx.q[t] = q_s[t * nodes + o];
-                    prior_posteriors(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cx, rcur[o]);
-                    e1 = energy2(w, B.P, B.flow, B.prior, cx, carried);
+                    prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cx, rcur[o]);
+                    e1 = energy2_bounded<B2, PR, true>(w, B.P, B.flow2, B.prior, cx, carried, bestE[o]);
                 }
                 const float eA = bestE[o];
                 const bool keep = (e1 < eA) || (e1 == eA && bestS[o] > 1);
@@ -313,13 +349,174 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
 }
 
 // ----------------------------------------------------------------------------------
+// phase A as a separate grid: four lanes per level pixel.  Lane 0 takes slot 0, lane l
+// takes the Philox groups g = l, l + 4, ... (slots 3 + 4g .. 6 + 4g) and, on the local
+// level, lane 1 takes slot 2 first.  Each lane scans its slots in increasing order with
+// strict improvement and pruning at its own best, then the four lanes merge by (energy,
+// slot): the result equals the argmin over all slots with ties to the lowest slot.
+// ----------------------------------------------------------------------------------
+template <bool B2, bool PR>
+__global__ void __launch_bounds__(VD_BLOCK)
+k_phase_a(Win w, LevelGeom g, LevelBufs B) {
+    const int gid = xcd_block(blockIdx.x, gridDim.x) * VD_BLOCK + threadIdx.x;
+    const int li = gid >> 2, lane = gid & 3;
+    const size_t lplane = (size_t)g.h * g.w;
+    const bool valid = li < (int)lplane;
+    float bE = __builtin_huge_valf(), bV = 0.f, r0 = 0.f;
+    int bS = 1 << 30;
+    if (valid) {
+        const int ly = li / g.w, lx = li - ly * g.w;
+        const int u = g.s * lx + g.off, v = g.s * ly + g.off;
+        Pix c;
+        pix_geometry<PR>(w, B.P, B.flow, u, v, c);
+#pragma unroll
+        for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) c.q[t] = B.q_in[t * lplane + li];
+        const int fpix = v * w.W + u;
+        r0 = B.idepth[fpix];
+        prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, fpix, c, r0);
+        if (lane == 0) {
+            bE = energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, r0); bV = r0; bS = 0;
+        }
+        if (lane == 1 && w.level == 1) {
+            const int U = min(u / w.s, w.wc - 1), V = min(v / w.s, w.hc - 1);
+            const float rc = B.idepth_coarse[V * w.wc + U];
+            const float e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, rc, bE);
+            if (e < bE) { bE = e; bV = rc; bS = 2; }
+        }
+        const int G = (w.K - 3 + 3) / 4;
+        const uint32_t word2 = philox_word2(w.it, w.level, PURPOSE_CAND);
+        for (int gi = lane; gi < G; gi += 4) {
+            const uint4 r = philox10(make_uint4((uint32_t)li, (uint32_t)gi, word2, w.window_id), w.key0, w.key1);
+            const uint32_t words[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int slot = 3 + 4 * gi + m;
+                if (slot < w.K) {
+                    const float uu = unit24(words[m]);
+                    const float cand = (slot & 1)
+                        ? fminf(fmaxf(r0 * fmaf(w.sigma_it, fmaf(2.f, uu, -1.f), 1.f), w.rmin), w.rmax)
+                        : fmaf(uu, w.rmax - w.rmin, w.rmin);
+                    const float e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, cand, bE);
+                    if (e < bE) { bE = e; bV = cand; bS = slot; }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < 4; off <<= 1) {
+        const float oE = __shfl_xor(bE, off), oV = __shfl_xor(bV, off);
+        const int oS = __shfl_xor(bS, off);
+        if (oE < bE || (oE == bE && oS < bS)) { bE = oE; bV = oV; bS = oS; }
+    }
+    if (valid && lane == 0) {
+        B.pa_E[li] = bE;
+        B.pa_V[li] = bV;
+        B.pa_S[li] = bS;
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// phase A2 as a separate grid (level with few long chains): one lane per (level pixel,
+// depth d), E_i at the phase-A winner of the node d + 1 steps back along the chain,
+// bounded (strict) by the pixel's phase-A energy.
+// ----------------------------------------------------------------------------------
+template <bool B2, bool PR>
+__global__ void __launch_bounds__(VD_BLOCK)
+k_phase_a2(Win w, LevelGeom g, LevelBufs B) {
+    const int gid = xcd_block(blockIdx.x, gridDim.x) * VD_BLOCK + threadIdx.x;
+    const int li = gid / g.spec, d = gid - li * g.spec;
+    const size_t lplane = (size_t)g.h * g.w;
+    if (li >= (int)lplane) return;
+    const int ly = li / g.w, lx = li - ly * g.w;
+    const int pos = g.horizontal ? lx : ly;
+    const int axis = g.horizontal ? g.w : g.h;
+    const int start = (pos / g.seg) * g.seg, end = min(start + g.seg, axis);
+    const int step = (w.dir < 2) ? 1 : -1;
+    const int pp = pos - (d + 1) * step;
+    if (pp < start || pp >= end) return;
+    const int lp = g.horizontal ? (ly * g.w + pp) : (pp * g.w + lx);
+    const int u = g.s * lx + g.off, v = g.s * ly + g.off;
+    Pix c;
+    pix_geometry<PR>(w, B.P, B.flow, u, v, c);
+#pragma unroll
+    for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) c.q[t] = B.q_in[t * lplane + li];
+    const int fpix = v * w.W + u;
+    prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, fpix, c, B.idepth[fpix]);
+    B.pa_spec[d * lplane + li] =
+        energy2_bounded<B2, PR, true>(w, B.P, B.flow2, B.prior, c, B.pa_V[lp], B.pa_E[li]);
+}
+
+// ----------------------------------------------------------------------------------
 // pose normal equations for frame t at candidate poses; optional FP64 solve + update
 // ----------------------------------------------------------------------------------
+template <bool B2>
+__device__ __forceinline__ void pose_pixel(const Win& w, const PoseBufs& B, const PoseF& Tc, int t, int j,
+                                           float* acc) {
+    const size_t plane = (size_t)w.H * w.W;
+    const float2* flow_t = B.flow + (t - 1) * plane;
+    const float4* flow2_t = B.flow2 + (t - 1) * plane;
+    const int v = j / w.W, u = j - v * w.W;
+    const float rho = B.idepth[j];
+    const float q = B.rigid[(t - 1) * plane + j];
+    const float x0 = ((float)u - w.cx) * w.ifx, x1 = ((float)v - w.cy) * w.ify;
+    // displacement form (see frame_residuals): d = p - j from D = (R - I) x~ + rho t
+    float dpx = 0.f, dpy = 0.f, fx, fy;
+    bool zprev = true, fok;
+    if (t == 1) {
+        const float2 f = flow_t[j];
+        fx = f.x; fy = f.y;
+        fok = isfinite(fx) && isfinite(fy);
+    } else {
+        const PoseF& Tp = B.P[t - 2];
+        const float Dx = fmaf(rho, Tp.t[0], fmaf(Tp.d[0], x0, fmaf(Tp.d[1], x1, Tp.d[2])));
+        const float Dy = fmaf(rho, Tp.t[1], fmaf(Tp.d[3], x0, fmaf(Tp.d[4], x1, Tp.d[5])));
+        const float Dz = fmaf(rho, Tp.t[2], fmaf(Tp.d[6], x0, fmaf(Tp.d[7], x1, Tp.d[8])));
+        zprev = 1.f + Dz > 0.f;
+        const float iz = rcp(1.f + Dz);
+        dpx = w.fx * fmaf(-x0, Dz, Dx) * iz;
+        dpy = w.fy * fmaf(-x1, Dz, Dy) * iz;
+        fok = sample_flow2(flow2_t, w.H, w.W, (float)u + dpx, (float)v + dpy, fx, fy);
+    }
+    const float Dx = fmaf(rho, Tc.t[0], fmaf(Tc.d[0], x0, fmaf(Tc.d[1], x1, Tc.d[2])));
+    const float Dy = fmaf(rho, Tc.t[1], fmaf(Tc.d[3], x0, fmaf(Tc.d[4], x1, Tc.d[5])));
+    const float Dz = fmaf(rho, Tc.t[2], fmaf(Tc.d[6], x0, fmaf(Tc.d[7], x1, Tc.d[8])));
+    const float Qx = x0 + Dx, Qy = x1 + Dy, Qz = 1.f + Dz;
+    const bool zok = Qz > 0.f;
+    const float iz = rcp(Qz);
+    const float dx = w.fx * fmaf(-x0, Dz, Dx) * iz, dy = w.fy * fmaf(-x1, Dz, Dy) * iz;
+    const bool ok = zprev && zok && fok;
+    const float ex = (dx - dpx) - fx, ey = (dy - dpy) - fy;
+    const float r2 = fmaf(ex, ex, ey * ey);
+    acc[0] = fmaf(q, ok ? flow_cost2<B2>(w, r2) : 1.0f, acc[0]);
+    if (ok) {
+        const float wt = q * flow_dcost<B2>(w, r2);
+        // J rows of p = pi(Q), Q = R x~ + rho t, left update (dw, dv): dQ = [-[Q]x | rho I]
+        const float a = w.fx * iz, b = -w.fx * Qx * iz * iz;
+        const float c = w.fy * iz, d = -w.fy * Qy * iz * iz;
+        const float jx[6] = {b * Qy, a * Qz - b * Qx, -a * Qy, a * rho, 0.f, b * rho};
+        const float jy[6] = {d * Qy - c * Qz, -d * Qx, c * Qx, 0.f, c * rho, d * rho};
+        int k = 1;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const float wxi = wt * jx[i], wyi = wt * jy[i];
+#pragma unroll
+            for (int l = i; l < 6; ++l) {
+                acc[k] = fmaf(wxi, jx[l], fmaf(wyi, jy[l], acc[k]));
+                ++k;
+            }
+            acc[22 + i] = fmaf(wxi, ex, fmaf(wyi, ey, acc[22 + i]));
+        }
+        acc[28] += 1.f;
+    }
+}
+
+// Normal equations of frame t at candidate poses: two pixels per thread summed in FP32,
+// then FP64 across threads and blocks.  One record per block, value-major.
+template <bool B2>
 __global__ void __launch_bounds__(VD_BLOCK)
-k_pose(Win w, PoseBufs B, int t, const double* __restrict__ cand, int solve) {
+k_pose(Win w, PoseBufs B, int t, const double* __restrict__ cand) {
     __shared__ double red[(VD_BLOCK / 64) * 29];
     __shared__ PoseF candF;
-    __shared__ int flag;
     const int tid = threadIdx.x;
     const int ci = blockIdx.y;
     if (tid == 0) {
@@ -328,104 +525,219 @@ k_pose(Win w, PoseBufs B, int t, const double* __restrict__ cand, int solve) {
     }
     __syncthreads();
     const PoseF Tc = candF;
-    const size_t plane = (size_t)w.H * w.W;
-    const float2* flow_t = B.flow + (t - 1) * plane;
+    const int plane = w.H * w.W;
     double acc[29];
 #pragma unroll
     for (int k = 0; k < 29; ++k) acc[k] = 0.0;
-    for (int j = blockIdx.x * VD_BLOCK + tid; j < (int)plane; j += gridDim.x * VD_BLOCK) {
-        const int v = j / w.W, u = j - v * w.W;
-        const float rho = B.idepth[j];
-        const float q = B.rigid[(t - 1) * plane + j];
-        const float x0 = ((float)u - w.cx) * w.ifx, x1 = ((float)v - w.cy) * w.ify;
-        float ppx, ppy, fx, fy;
-        bool zprev = true, fok;
-        if (t == 1) {
-            ppx = (float)u; ppy = (float)v;
-            const float2 f = flow_t[j];
-            fx = f.x; fy = f.y;
-            fok = isfinite(fx) && isfinite(fy);
-        } else {
-            const PoseF& Tp = B.P[t - 2];
-            const float Qx = fmaf(rho, Tp.t[0], fmaf(Tp.r[0], x0, fmaf(Tp.r[1], x1, Tp.r[2])));
-            const float Qy = fmaf(rho, Tp.t[1], fmaf(Tp.r[3], x0, fmaf(Tp.r[4], x1, Tp.r[5])));
-            const float Qz = fmaf(rho, Tp.t[2], fmaf(Tp.r[6], x0, fmaf(Tp.r[7], x1, Tp.r[8])));
-            zprev = Qz > 0.f;
-            const float iz = rcp(Qz);
-            ppx = fmaf(w.fx, Qx * iz, w.cx);
-            ppy = fmaf(w.fy, Qy * iz, w.cy);
-            fok = sample_flow(flow_t, w.H, w.W, ppx, ppy, fx, fy);
-        }
-        const float ox = ppx + fx, oy = ppy + fy;
-        const float Qx = fmaf(rho, Tc.t[0], fmaf(Tc.r[0], x0, fmaf(Tc.r[1], x1, Tc.r[2])));
-        const float Qy = fmaf(rho, Tc.t[1], fmaf(Tc.r[3], x0, fmaf(Tc.r[4], x1, Tc.r[5])));
-        const float Qz = fmaf(rho, Tc.t[2], fmaf(Tc.r[6], x0, fmaf(Tc.r[7], x1, Tc.r[8])));
-        const bool zok = Qz > 0.f;
-        const float iz = rcp(Qz);
-        const float px = fmaf(w.fx, Qx * iz, w.cx), py = fmaf(w.fy, Qy * iz, w.cy);
-        const bool ok = zprev && zok && fok;
-        const float ex = px - ox, ey = py - oy;
-        const float r2 = fmaf(ex, ex, ey * ey);
-        acc[0] += (double)(q * (ok ? flow_cost2(w, r2) : 1.0f) * VD_LN2);
-        if (ok) {
-            const float wt = q * flow_dcost(w, r2);
-            // J rows of p = pi(Q), Q = R x~ + rho t, left update (dw, dv): dQ = [-[Q]x | rho I]
-            const float a = w.fx * iz, b = -w.fx * Qx * iz * iz;
-            const float c = w.fy * iz, d = -w.fy * Qy * iz * iz;
-            const float jx[6] = {b * Qy, a * Qz - b * Qx, -a * Qy, a * rho, 0.f, b * rho};
-            const float jy[6] = {d * Qy - c * Qz, -d * Qx, c * Qx, 0.f, c * rho, d * rho};
-            int k = 1;
+    const int stride = gridDim.x * VD_BLOCK;
+    for (int j = xcd_block(blockIdx.x, gridDim.x) * VD_BLOCK + tid; j < plane; j += 2 * stride) {
+        float a32[29];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) {
+        for (int k = 0; k < 29; ++k) a32[k] = 0.f;
+        pose_pixel<B2>(w, B, Tc, t, j, a32);
+        if (j + stride < plane) pose_pixel<B2>(w, B, Tc, t, j + stride, a32);
 #pragma unroll
-                for (int l = i; l < 6; ++l) {
-                    acc[k++] += (double)(wt * fmaf(jx[i], jx[l], jy[i] * jy[l]));
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 6; ++i) acc[22 + i] += (double)(wt * fmaf(jx[i], ex, jy[i] * ey));
-            acc[28] += 1.0;
-        }
+        for (int k = 0; k < 29; ++k) acc[k] += (double)a32[k];
     }
     block_reduce<29>(acc, red);
-    double* part = B.partials + ((size_t)ci * gridDim.x + blockIdx.x) * 29;
-    if (tid < 29) part[tid] = red[tid];
-    if (!last_block(B.counters + ci, gridDim.x, &flag)) return;
-    if (tid < 29) {
-        const double* pc = B.partials + (size_t)ci * gridDim.x * 29;
-        double s = 0.0;
-        for (unsigned bi = 0; bi < gridDim.x; ++bi) s += __builtin_nontemporal_load(pc + (size_t)bi * 29 + tid);
-        red[tid] = s;
+    // energy was summed in log2 units
+    if (tid < 29) B.partials[((size_t)ci * 29 + tid) * gridDim.x + blockIdx.x] = red[tid] * (tid == 0 ? (double)VD_LN2 : 1.0);
+}
+
+// Sum of candidate ci's block records (fixed order); optional FP64 solve and pose update.
+// One block per candidate; launched after k_pose on the same stream.
+__global__ void __launch_bounds__(VD_BLOCK)
+k_pose_finish(PoseBufs B, int t, unsigned nb, int solve) {
+    __shared__ double red[(VD_BLOCK / 64) * 29];
+    const int ci = blockIdx.x;
+    reduce_partials<29>(B.partials + (size_t)ci * nb * 29, nb, red);
+    if (threadIdx.x != 0) return;
+    if (B.out) for (int k = 0; k < 29; ++k) B.out[ci * 29 + k] = red[k];
+    if (!solve) return;
+    double H[36], gv[6], x[6];
+    int k = 1;
+    for (int i = 0; i < 6; ++i)
+        for (int l = i; l < 6; ++l) { H[6 * i + l] = H[6 * l + i] = red[k++]; }
+    double tr = 0.0;
+    for (int i = 0; i < 6; ++i) { gv[i] = -red[22 + i]; tr += H[7 * i]; }
+    const double lam = 1e-9 * tr / 6.0;
+    for (int i = 0; i < 6; ++i) H[7 * i] += lam;
+    if (chol6_solve(H, gv, x)) {
+        left_update_d(B.PD + (t - 1), x);
+        posef_from_d(B.PD[t - 1], B.P + (t - 1));
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// pose step, one launch per Gauss-Newton step s = 0 .. N*G-1 (frame t = s/G + 1, GN index
+// k = s mod G).  Prologue: every block sums the previous step's block records (fixed
+// order, so all blocks agree bit for bit), solves (H + 1e-9 tr(H)/6 I) delta = -g in FP64
+// and applies it to that frame's pose; block 0 persists the result in hist[s-1] (no other
+// block reads it during this launch).  Pass: normal equations of frame t at its current
+// pose; the observation o_t = p_{t-1} + X_t(p_{t-1}) is formed at k = 0 and stored as a
+// displacement from the pixel (NaN when invalid) for the frame's later steps.
+// ----------------------------------------------------------------------------------
+__device__ inline void pose_gn_solve(const double* red, PoseD& P) {
+    double H[36], gv[6], x[6];
+    int k = 1;
+    for (int i = 0; i < 6; ++i)
+        for (int l = i; l < 6; ++l) { H[6 * i + l] = H[6 * l + i] = red[k++]; }
+    double tr = 0.0;
+    for (int i = 0; i < 6; ++i) { gv[i] = -red[22 + i]; tr += H[7 * i]; }
+    const double lam = 1e-9 * tr / 6.0;
+    for (int i = 0; i < 6; ++i) H[7 * i] += lam;
+    if (chol6_solve(H, gv, x)) left_update_d(&P, x);      // singular: pose unchanged
+}
+
+template <bool B2>
+__global__ void __launch_bounds__(VD_BLOCK)
+k_pose_gn(Win w, PoseBufs B, int s, int G) {
+    __shared__ double red[(VD_BLOCK / 64) * 29];
+    __shared__ PoseF curF, prevF;
+    const int tid = threadIdx.x;
+    const unsigned nb = gridDim.x;
+    const int t = s / G + 1, k = s - (t - 1) * G;
+    if (s > 0) {
+        reduce_partials<29>(B.partials + (size_t)((s - 1) & 1) * 29 * nb, nb, red);
+        if (tid == 0) {
+            const int sp = s - 1, tp = sp / G + 1, kp = sp - (tp - 1) * G;
+            PoseD P = (kp == 0) ? B.PD[tp - 1] : B.hist[sp - 1];
+            pose_gn_solve(red, P);
+            PoseF F;
+            posef_from_d(P, &F);
+            if (blockIdx.x == 0) B.hist[sp] = P;
+            if (k == 0) { prevF = F; curF = B.P[t - 1]; }
+            else curF = F;
+        }
+    } else if (tid == 0) {
+        curF = B.P[t - 1];
     }
     __syncthreads();
-    if (tid == 0) {
-        B.counters[ci] = 0u;
-        if (B.out) for (int k = 0; k < 29; ++k) B.out[ci * 29 + k] = red[k];
-        if (solve) {
-            double H[36], gv[6], x[6];
-            int k = 1;
-            for (int i = 0; i < 6; ++i)
-                for (int l = i; l < 6; ++l) { H[6 * i + l] = H[6 * l + i] = red[k++]; }
-            double tr = 0.0;
-            for (int i = 0; i < 6; ++i) { gv[i] = -red[22 + i]; tr += H[7 * i]; }
-            const double lam = 1e-9 * tr / 6.0;
-            for (int i = 0; i < 6; ++i) H[7 * i] += lam;
-            if (chol6_solve(H, gv, x)) {
-                double* p = B.pose + 6 * (t - 1);
-                left_update(p, x);
-                pose_to_f(p, B.P + (t - 1));
+    const PoseF Tc = curF;
+    const int plane = w.H * w.W;
+    const float2* __restrict__ flow_t = B.flow + (size_t)(t - 1) * plane;
+    const float4* __restrict__ flow2_t = B.flow2 + (size_t)(t - 1) * plane;
+    const float* __restrict__ idepth = B.idepth;
+    const float* __restrict__ rig = B.rigid + (size_t)(t - 1) * plane;
+    float2* __restrict__ obs = B.obs;
+    // per-thread sums in FP32 (a thread covers a few pixels), FP64 across threads and blocks
+    float a32[29];
+#pragma unroll
+    for (int i = 0; i < 29; ++i) a32[i] = 0.f;
+    const int stride = (int)nb * VD_BLOCK;
+    constexpr int UB = 4;                  // pixels per thread and batch: loads issued together
+    for (int j0 = xcd_block(blockIdx.x, nb) * VD_BLOCK + tid; j0 < plane; j0 += UB * stride) {
+        float rho[UB], q[UB], ox[UB], oy[UB];
+        int jj[UB];
+#pragma unroll
+        for (int b = 0; b < UB; ++b) {
+            const int j = j0 + b * stride;
+            jj[b] = j < plane ? j : -1;
+            const int jc = j < plane ? j : 0;
+            rho[b] = idepth[jc];
+            q[b] = rig[jc];
+            if (k > 0) { const float2 o = obs[jc]; ox[b] = o.x; oy[b] = o.y; }
+            else if (t == 1) { const float2 f = flow_t[jc]; ox[b] = f.x; oy[b] = f.y; }
+        }
+        if (k == 0 && t > 1) {
+            const PoseF& Tp = prevF;
+#pragma unroll
+            for (int b = 0; b < UB; ++b) {
+                const int jc = jj[b] >= 0 ? jj[b] : 0;
+                const int v = jc / w.W, u = jc - v * w.W;
+                const float x0 = ((float)u - w.cx) * w.ifx, x1 = ((float)v - w.cy) * w.ify;
+                const float Dx = fmaf(rho[b], Tp.t[0], fmaf(Tp.d[0], x0, fmaf(Tp.d[1], x1, Tp.d[2])));
+                const float Dy = fmaf(rho[b], Tp.t[1], fmaf(Tp.d[3], x0, fmaf(Tp.d[4], x1, Tp.d[5])));
+                const float Dz = fmaf(rho[b], Tp.t[2], fmaf(Tp.d[6], x0, fmaf(Tp.d[7], x1, Tp.d[8])));
+                const bool zprev = 1.f + Dz > 0.f;
+                const float iz = rcp(1.f + Dz);
+                const float dpx = w.fx * fmaf(-x0, Dz, Dx) * iz;
+                const float dpy = w.fy * fmaf(-x1, Dz, Dy) * iz;
+                float fx, fy;
+                const bool fok = sample_flow2(flow2_t, w.H, w.W, (float)u + dpx, (float)v + dpy, fx, fy);
+                ox[b] = (zprev && fok) ? dpx + fx : __builtin_nanf("");
+                oy[b] = (zprev && fok) ? dpy + fy : __builtin_nanf("");
             }
         }
+        if (k == 0 && G > 1) {
+#pragma unroll
+            for (int b = 0; b < UB; ++b) if (jj[b] >= 0) obs[jj[b]] = make_float2(ox[b], oy[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < UB; ++b) {
+            if (jj[b] < 0) continue;
+            const int v = jj[b] / w.W, u = jj[b] - v * w.W;
+            const float x0 = ((float)u - w.cx) * w.ifx, x1 = ((float)v - w.cy) * w.ify;
+            const float r = rho[b];
+            const float Dx = fmaf(r, Tc.t[0], fmaf(Tc.d[0], x0, fmaf(Tc.d[1], x1, Tc.d[2])));
+            const float Dy = fmaf(r, Tc.t[1], fmaf(Tc.d[3], x0, fmaf(Tc.d[4], x1, Tc.d[5])));
+            const float Dz = fmaf(r, Tc.t[2], fmaf(Tc.d[6], x0, fmaf(Tc.d[7], x1, Tc.d[8])));
+            const float Qx = x0 + Dx, Qy = x1 + Dy, Qz = 1.f + Dz;
+            const bool zok = Qz > 0.f;
+            const float iz = rcp(Qz);
+            const float dx = w.fx * fmaf(-x0, Dz, Dx) * iz, dy = w.fy * fmaf(-x1, Dz, Dy) * iz;
+            const bool ok = zok && isfinite(ox[b]) && isfinite(oy[b]);
+            const float ex = dx - ox[b], ey = dy - oy[b];
+            const float r2 = fmaf(ex, ex, ey * ey);
+            a32[0] = fmaf(q[b], ok ? flow_cost2<B2>(w, r2) : 1.0f, a32[0]);
+            if (ok) {
+                const float wt = q[b] * flow_dcost<B2>(w, r2);
+                const float a = w.fx * iz, bb = -w.fx * Qx * iz * iz;
+                const float c = w.fy * iz, d = -w.fy * Qy * iz * iz;
+                const float jx[6] = {bb * Qy, a * Qz - bb * Qx, -a * Qy, a * r, 0.f, bb * r};
+                const float jy[6] = {d * Qy - c * Qz, -d * Qx, c * Qx, 0.f, c * r, d * r};
+                int m = 1;
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    const float wxi = wt * jx[i], wyi = wt * jy[i];
+#pragma unroll
+                    for (int l = i; l < 6; ++l) { a32[m] = fmaf(wxi, jx[l], fmaf(wyi, jy[l], a32[m])); ++m; }
+                    a32[22 + i] = fmaf(wxi, ex, fmaf(wyi, ey, a32[22 + i]));
+                }
+                a32[28] += 1.f;
+            }
+        }
+    }
+    double acc[29];
+#pragma unroll
+    for (int i = 0; i < 29; ++i) acc[i] = (double)a32[i];
+    block_reduce<29>(acc, red);
+    if (tid < 29) B.partials[((size_t)(s & 1) * 29 + tid) * nb + blockIdx.x] = red[tid] * (tid == 0 ? (double)VD_LN2 : 1.0);
+}
+
+// Last step's solve, then every frame's final pose into the FP32 / FP64 copies and the
+// caller's 6-vectors.
+__global__ void __launch_bounds__(VD_BLOCK)
+k_pose_gn_finish(PoseBufs B, int N, int G, unsigned nb) {
+    __shared__ double red[(VD_BLOCK / 64) * 29];
+    const int S = N * G;
+    reduce_partials<29>(B.partials + (size_t)((S - 1) & 1) * 29 * nb, nb, red);
+    if (threadIdx.x == 0) {
+        const int sp = S - 1, tp = sp / G + 1, kp = sp - (tp - 1) * G;
+        PoseD P = (kp == 0) ? B.PD[tp - 1] : B.hist[sp - 1];
+        pose_gn_solve(red, P);
+        B.hist[sp] = P;
+    }
+    __syncthreads();
+    const int i = threadIdx.x;
+    if (i < N) {
+        const PoseD P = B.hist[(i + 1) * G - 1];
+        B.PD[i] = P;
+        posef_from_d(P, B.P + i);
+        log_so3(P.R, B.pose + 6 * i);
+        B.pose[6 * i + 3] = P.t[0];
+        B.pose[6 * i + 4] = P.t[1];
+        B.pose[6 * i + 5] = P.t[2];
     }
 }
 
 // ----------------------------------------------------------------------------------
 // final confidence and statistics
 // ----------------------------------------------------------------------------------
+template <bool B2, bool PR>
 __global__ void __launch_bounds__(VD_BLOCK)
-k_finalize(Win w, FinalBufs B, int n_ll) {
+k_finalize(Win w, FinalBufs B) {
     __shared__ double red[(VD_BLOCK / 64) * 5];
-    __shared__ int flag;
     const int tid = threadIdx.x;
     const size_t plane = (size_t)w.H * w.W;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // energy, valid, invalid, prior terms, sum C
@@ -433,47 +745,42 @@ k_finalize(Win w, FinalBufs B, int n_ll) {
     if (j < (int)plane) {
         const int v = j / w.W, u = j - v * w.W;
         Pix c;
-        pix_geometry(w, B.P, B.flow, u, v, c);
+        pix_geometry<PR>(w, B.P, B.flow, u, v, c);
         float qs = 0.f;
 #pragma unroll
         for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) { c.q[t] = B.rigid[t * plane + j]; qs += c.q[t]; }
         const float rho = B.idepth[j];
-        prior_posteriors(w, B.P, B.prior, B.prior_weight, j, c, rho);
-        int npr = 0;
+        const int pmask = prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, j, c, rho);
+        const int npr = __popc(pmask);
 #pragma unroll
-        for (int k = 0; k < VD_PMAX; ++k) if (k < w.P) { qs += c.qh[k]; npr += c.qh[k] > 0.f; }
+        for (int k = 0; k < VD_PMAX; ++k) if (k < w.P) qs += c.qh[k];
         const float C = qs / (float)(w.N + w.P);
         B.conf[j] = C;
         int nv = 0;
-        emissions(w, B.P, B.flow, c, rho, [&](int, float, bool ok) { nv += ok; });
-        acc[0] = (double)energy2(w, B.P, B.flow, B.prior, c, rho) * (double)VD_LN2;
+        emissions<B2>(w, B.P, B.flow2, c, rho, [&](int, float, bool ok) { nv += ok; });
+        acc[0] = (double)energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, rho) * (double)VD_LN2;
         acc[1] = nv;
         acc[2] = w.N - nv;
         acc[3] = npr;
         acc[4] = C;
     }
     block_reduce<5>(acc, red);
-    if (tid < 5) B.partials[(size_t)blockIdx.x * 5 + tid] = red[tid];
-    if (!last_block(B.counter, gridDim.x, &flag)) return;
-    if (tid < 5) {
-        double s = 0.0;
-        for (unsigned bi = 0; bi < gridDim.x; ++bi) s += __builtin_nontemporal_load(B.partials + (size_t)bi * 5 + tid);
-        red[tid] = s;
-    }
-    if (tid == 5) {
-        double s = 0.0;
-        for (int bi = 0; bi < n_ll; ++bi) s += __builtin_nontemporal_load(B.ll_partial + bi);
-        red[5] = s;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        *B.counter = 0u;
-        B.stats[0] = red[5];
-        B.stats[1] = red[0];
-        B.stats[2] = red[1];
-        B.stats[3] = red[2];
-        B.stats[4] = red[3];
-        B.stats[5] = red[4];
+    if (tid < 5) B.partials[(size_t)tid * gridDim.x + blockIdx.x] = red[tid];
+}
+
+__global__ void __launch_bounds__(VD_BLOCK)
+k_finalize_finish(FinalBufs B, unsigned nb, int n_ll) {
+    __shared__ double red[(VD_BLOCK / 64) * 5];
+    reduce_partials<5>(B.partials, nb, red);
+    const double s0 = red[0], s1 = red[1], s2 = red[2], s3 = red[3], s4 = red[4];
+    reduce_partials<1>(B.ll_partial, (unsigned)n_ll, red);
+    if (threadIdx.x == 0) {
+        B.stats[0] = red[0];
+        B.stats[1] = s0;
+        B.stats[2] = s1;
+        B.stats[3] = s2;
+        B.stats[4] = s3;
+        B.stats[5] = s4;
         B.stats[6] = 0.0;
         B.stats[7] = 0.0;
     }
@@ -488,15 +795,29 @@ namespace vd {
 
 size_t level_lds_bytes(const LevelGeom& g) {
     const size_t nodes = (size_t)g.C * (g.seg + 1);
-    return (2 * VD_NMAX * nodes + 5 * nodes) * sizeof(float) + nodes * sizeof(int);
+    return (2 * VD_NMAX * nodes + (4 + VD_SPEC) * nodes) * sizeof(float) + nodes * sizeof(int);
 }
 
 hipError_t set_level_lds_limit(size_t bytes) {
-    return hipFuncSetAttribute((const void*)k_level, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void* fns[4] = {(const void*)k_level<false, false>, (const void*)k_level<false, true>,
+                          (const void*)k_level<true, false>, (const void*)k_level<true, true>};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_pose_prep(const double* pose, int N, const double* prior_pose, int P, PoseF* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_pose_prep, dim3(1), dim3(64), 0, st, pose, N, prior_pose, P, out);
+hipError_t launch_pose_prep(const double* pose, int N, const double* prior_pose, int P, PoseF* out, PoseD* outd,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_pose_prep, dim3(1), dim3(64), 0, st, pose, N, prior_pose, P, out, outd);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_pairs(const float2* flow, float4* f2, int N, int H, int W, hipStream_t st) {
+    if (N < 2) return hipSuccess;
+    const size_t n = (size_t)(H - 1) * W * (N - 1);
+    hipLaunchKernelGGL(k_flow_pairs, dim3((unsigned)((n + VD_BLOCK - 1) / VD_BLOCK)), dim3(VD_BLOCK), 0, st, flow, f2, N, H, W);
     return hipGetLastError();
 }
 
@@ -507,19 +828,75 @@ hipError_t launch_init(const Win& w, float* idepth, hipStream_t st) {
 }
 
 hipError_t launch_level(const Win& w, const LevelGeom& g, const LevelBufs& b, int do_e, int do_m, hipStream_t st) {
-    hipLaunchKernelGGL(k_level, dim3(g.nblocks), dim3(VD_BLOCK), level_lds_bytes(g), st, w, g, b, do_e, do_m);
+    const size_t lds = level_lds_bytes(g);
+    if (w.beta2) {
+        if (w.P > 0) hipLaunchKernelGGL((k_level<true, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+        else hipLaunchKernelGGL((k_level<true, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+    } else {
+        if (w.P > 0) hipLaunchKernelGGL((k_level<false, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+        else hipLaunchKernelGGL((k_level<false, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_a(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st) {
+    const dim3 grid((unsigned)(((size_t)g.h * g.w * 4 + VD_BLOCK - 1) / VD_BLOCK));
+    if (w.beta2) {
+        if (w.P > 0) hipLaunchKernelGGL((k_phase_a<true, true>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+        else hipLaunchKernelGGL((k_phase_a<true, false>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+    } else {
+        if (w.P > 0) hipLaunchKernelGGL((k_phase_a<false, true>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+        else hipLaunchKernelGGL((k_phase_a<false, false>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_a2(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st) {
+    const dim3 grid((unsigned)(((size_t)g.h * g.w * g.spec + VD_BLOCK - 1) / VD_BLOCK));
+    if (w.beta2) {
+        if (w.P > 0) hipLaunchKernelGGL((k_phase_a2<true, true>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+        else hipLaunchKernelGGL((k_phase_a2<true, false>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+    } else {
+        if (w.P > 0) hipLaunchKernelGGL((k_phase_a2<false, true>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+        else hipLaunchKernelGGL((k_phase_a2<false, false>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_gn(const Win& w, const PoseBufs& b, int s, int G, int nblocks, hipStream_t st) {
+    if (w.beta2) hipLaunchKernelGGL((k_pose_gn<true>), dim3(nblocks), dim3(VD_BLOCK), 0, st, w, b, s, G);
+    else hipLaunchKernelGGL((k_pose_gn<false>), dim3(nblocks), dim3(VD_BLOCK), 0, st, w, b, s, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_gn_finish(const PoseBufs& b, int N, int G, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_pose_gn_finish, dim3(1), dim3(VD_BLOCK), 0, st, b, N, G, (unsigned)nblocks);
     return hipGetLastError();
 }
 
 hipError_t launch_pose(const Win& w, const PoseBufs& b, int t, const double* cand, int n_cand, int solve,
                        int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_pose, dim3(nblocks, n_cand), dim3(VD_BLOCK), 0, st, w, b, t, cand, solve);
+    if (w.beta2) hipLaunchKernelGGL((k_pose<true>), dim3(nblocks, n_cand), dim3(VD_BLOCK), 0, st, w, b, t, cand);
+    else hipLaunchKernelGGL((k_pose<false>), dim3(nblocks, n_cand), dim3(VD_BLOCK), 0, st, w, b, t, cand);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pose_finish, dim3(n_cand), dim3(VD_BLOCK), 0, st, b, t, (unsigned)nblocks, solve);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Win& w, const FinalBufs& b, int n_ll, hipStream_t st) {
     const int n = w.H * w.W;
-    hipLaunchKernelGGL(k_finalize, dim3((n + VD_BLOCK - 1) / VD_BLOCK), dim3(VD_BLOCK), 0, st, w, b, n_ll);
+    const dim3 grid((n + VD_BLOCK - 1) / VD_BLOCK);
+    if (w.beta2) {
+        if (w.P > 0) hipLaunchKernelGGL((k_finalize<true, true>), grid, dim3(VD_BLOCK), 0, st, w, b);
+        else hipLaunchKernelGGL((k_finalize<true, false>), grid, dim3(VD_BLOCK), 0, st, w, b);
+    } else {
+        if (w.P > 0) hipLaunchKernelGGL((k_finalize<false, true>), grid, dim3(VD_BLOCK), 0, st, w, b);
+        else hipLaunchKernelGGL((k_finalize<false, false>), grid, dim3(VD_BLOCK), 0, st, w, b);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalize_finish, dim3(1), dim3(VD_BLOCK), 0, st, b, grid.x, n_ll);
     return hipGetLastError();
 }
 

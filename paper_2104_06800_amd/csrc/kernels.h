@@ -6,6 +6,7 @@
 namespace vd {
 
 struct PoseF;
+struct PoseD;
 struct Win;
 
 // Chain geometry of one launch of the level kernel.
@@ -17,11 +18,13 @@ struct LevelGeom {
     int C;             // chain segments per block
     int nseg;          // segments per line
     int nblocks;
+    int spec;          // speculation depth of the chain scan (1..4)
 };
 
 struct LevelBufs {
     const PoseF* P;
     const float2* flow;
+    const float4* flow2;         // row-pair layout of frames t >= 2
     const float* idepth;         // full resolution, read
     const float* idepth_coarse;  // slot 2 source (local level)
     const float* prior;
@@ -30,22 +33,30 @@ struct LevelBufs {
     const float* q_in;           // M-step input when the E-step is not fused
     float* rho_out;              // M-step output (coarse lattice or full image)
     double* ll_partial;          // per-block log-likelihood, or null
+    float* pa_E;                 // phase-A results per level pixel (split M-step)
+    float* pa_V;
+    int* pa_S;
+    float* pa_spec;              // [spec][level plane] speculative predecessor energies
 };
 
 struct PoseBufs {
     PoseF* P;
+    PoseD* PD;
     const float2* flow;
+    const float4* flow2;
     const float* idepth;
     const float* rigid;
     double* pose;
     double* partials;
-    unsigned* counters;
     double* out;
+    PoseD* hist;                 // per-step pose history of a pose step (N * G entries)
+    float2* obs;                 // observed displacement of the current frame
 };
 
 struct FinalBufs {
     const PoseF* P;
     const float2* flow;
+    const float4* flow2;
     const float* idepth;
     const float* rigid;
     const float* prior;
@@ -54,7 +65,6 @@ struct FinalBufs {
     double* stats;
     double* partials;
     const double* ll_partial;
-    unsigned* counter;
 };
 
 struct AlignArgs {
@@ -77,13 +87,18 @@ struct AlignBufs {
     double* stats;
     int32_t* status;
     double* partials;
-    unsigned* counters;
 };
 
 size_t level_lds_bytes(const LevelGeom& g);
-hipError_t launch_pose_prep(const double* pose, int N, const double* prior_pose, int P, PoseF* out, hipStream_t st);
+hipError_t launch_pose_prep(const double* pose, int N, const double* prior_pose, int P, PoseF* out, PoseD* outd,
+                            hipStream_t st);
 hipError_t launch_init(const Win& w, float* idepth, hipStream_t st);
+hipError_t launch_flow_pairs(const float2* flow, float4* f2, int N, int H, int W, hipStream_t st);
 hipError_t launch_level(const Win& w, const LevelGeom& g, const LevelBufs& b, int do_e, int do_m, hipStream_t st);
+hipError_t launch_phase_a(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st);
+hipError_t launch_phase_a2(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st);
+hipError_t launch_pose_gn(const Win& w, const PoseBufs& b, int s, int G, int nblocks, hipStream_t st);
+hipError_t launch_pose_gn_finish(const PoseBufs& b, int N, int G, int nblocks, hipStream_t st);
 hipError_t launch_pose(const Win& w, const PoseBufs& b, int t, const double* cand, int n_cand, int solve,
                        int nblocks, hipStream_t st);
 hipError_t launch_finalize(const Win& w, const FinalBufs& b, int n_ll, hipStream_t st);

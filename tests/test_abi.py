@@ -33,7 +33,7 @@ def test_exports_every_declared_function(lib):
     for n in names:
         assert hasattr(lib, n), n
     from paper_2104_06800_amd import binding
-    assert sorted(binding.EXPORTS) == names
+    assert binding.EXPORTS == names
 
 
 def test_struct_layout_matches_header(tmp_path):

@@ -1,8 +1,8 @@
 """GPU parity: every C-ABI entry point against the FP64 oracle on identical seeded inputs.
 
 Tolerances (FP32 kernels vs FP64 oracle):
-  init_idepth            bit-exact (Philox words are integers; u * range + min in FP32 vs FP64
-                         differ by < 1 ulp of FP32, so the oracle value is rounded to FP32)
+  init_idepth            rel 1e-6 (the Philox words agree bit for bit; u * range + min is
+                         evaluated in FP32 on the GPU and in FP64 by the oracle)
   rigidness posteriors   |dq| <= 1e-3 on >= 99.5% of values, <= 1e-2 on all valid chains
   inverse depth (M-step) |drho|/rho <= 1e-3 on >= 99.5% of pixels
   log-likelihood         rel 1e-4
@@ -55,14 +55,14 @@ def frac_close_rel(a, b, rel=1e-3):
 
 
 # ----------------------------------------------------------------------------- init
-def test_init_idepth_bit_exact(lib):
+def test_init_idepth(lib):
     w = window(1, 0)
     p = w["params"]
     b = lib.alloc(p, w["flow"], w["pose_init"])
     lib.init_idepth(p, b)
     ob = oracle_bufs(p, w)
     ogem.init_idepth(p, ob)
-    assert np.array_equal(np_(b["idepth"]), ob["idepth"].astype(np.float32))
+    np.testing.assert_allclose(np_(b["idepth"]), ob["idepth"], rtol=1e-6)
 
 
 # ----------------------------------------------------------------------------- E-step
@@ -194,13 +194,21 @@ def test_gem_step_one_iteration(lib):
 
 
 def test_gem_end_to_end_config1(lib):
-    """Config 1 (64x48, N=3, K=16, 5 iterations) from random init."""
+    """Config 1 (64x48, N=3, K=16, 5 iterations) from random init, both sides run
+    independently; agreement is reported after every iteration."""
     w = window(1, 0)
     p = w["params"]
     b = lib.alloc(p, w["flow"], w["pose_init"])
-    lib.run(p, b)
     ob = oracle_bufs(p, w)
-    ogem.run(p, ob)
+    lib.init_idepth(p, b)
+    ogem.init_idepth(p, ob)
+    for it in range(p["iters"]):
+        lib.gem_step(p, b, it)
+        ogem.gem_step(p, ob, it)
+        print(f"it {it}: rho frac {frac_close_rel(np_(b['idepth']), ob['idepth']):.4f} "
+              f"pose {np.abs(np_(b['pose']) - ob['pose']).max():.2e}")
+    lib.finalize(p, b, p["iters"] - 1)
+    ogem.finalize(p, ob, p["iters"] - 1)
     rho, q, pose, st = np_(b["idepth"]), np_(b["rigid"]), np_(b["pose"]), np_(b["stats"])
     print("e2e: rho frac", frac_close_rel(rho, ob["idepth"]), "q frac", np.mean(np.abs(q - ob["rigid"]) <= 1e-3),
           "pose", np.abs(pose - ob["pose"]).max(), "loglik", st[0], ob["stats"][0])
@@ -282,3 +290,34 @@ def test_invalid_arguments_rejected(lib):
                 lib.gem_step(q, dict(b, flow=torch.zeros((9, 48, 64, 2), device=b["flow"].device)), 0)
             else:
                 lib.gem_step(q, b, 0)
+
+
+# ----------------------------------------------------------------------------- ties, determinism
+@pytest.mark.parametrize("level", [0, 1])
+def test_depth_update_ties_keep_current(lib, level):
+    """q = 0 makes every slot cost 0: the lowest slot (the current value) must win."""
+    w = window(1, 6)
+    p = w["params"]
+    b = lib.alloc(p, w["flow"], w["pose_init"])
+    lib.init_idepth(p, b)
+    rho0 = np_(b["idepth"]).copy()
+    b["rigid"].zero_()
+    b["rigid_coarse"].zero_()
+    lib.depth_update(p, b, 3, level)
+    if level == 1:
+        assert np.array_equal(np_(b["idepth"]), rho0)
+    else:
+        s = p["coarse_stride"]
+        assert np.array_equal(np_(b["idepth_coarse"]), rho0[s // 2::s, s // 2::s])
+
+
+def test_repeat_runs_bitwise_identical(lib):
+    w = window(3, 3, H=64, W=80, N=5)
+    p = w["params"]
+    outs = []
+    for _ in range(2):
+        b = lib.alloc(p, w["flow"], w["pose_init"], w["prior_idepth"], w["prior_pose"])
+        lib.run(p, b, iters=4)
+        outs.append([np_(b[k]).copy() for k in ("idepth", "rigid", "pose", "conf", "stats")])
+    for a, c in zip(*outs):
+        assert np.array_equal(a, c)
