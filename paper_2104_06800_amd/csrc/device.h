@@ -352,12 +352,12 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // ----------------------------------------------------------------------------------
-// per-pixel context of the energy E_j(rho) and its evaluation
+// per-pixel context of the energy E_j(rho) and its evaluation.  (R_t - I) x~ is recomputed
+// per frame from x~ (6 FMAs) rather than cached in 3N registers.
 // ----------------------------------------------------------------------------------
 struct Pix {
     float u, v;
     float x0, x1;                                  // x~ = ((u - cx)/fx, (v - cy)/fy, 1)
-    float ax[VD_NMAX], ay[VD_NMAX], az[VD_NMAX];   // (R_t - I) x~
     float q[VD_NMAX];                              // rigidness posteriors
     float f1x, f1y;                                // first flow X_1(j)
     bool ok1;
@@ -374,15 +374,6 @@ __device__ __forceinline__ void pix_geometry(const Win& w, const PoseF* __restri
     const float x0 = ((float)u - w.cx) * w.ifx, x1 = ((float)v - w.cy) * w.ify;
     c.x0 = x0;
     c.x1 = x1;
-#pragma unroll
-    for (int t = 0; t < VD_NMAX; ++t) {
-        if (t < w.N) {
-            const PoseF& T = P[t];
-            c.ax[t] = fmaf(T.d[0], x0, fmaf(T.d[1], x1, T.d[2]));
-            c.ay[t] = fmaf(T.d[3], x0, fmaf(T.d[4], x1, T.d[5]));
-            c.az[t] = fmaf(T.d[6], x0, fmaf(T.d[7], x1, T.d[8]));
-        }
-    }
     const float2 f = flow[v * w.W + u];
     c.f1x = f.x;
     c.f1y = f.y;
@@ -440,9 +431,9 @@ __device__ __forceinline__ void frame_residuals(const Win& w, const PoseF* __res
     for (int t = 0; t < VD_NMAX; ++t) {
         if (t < w.N) {
             const PoseF& T = P[t];
-            const float Dx = fmaf(rho, T.t[0], c.ax[t]);
-            const float Dy = fmaf(rho, T.t[1], c.ay[t]);
-            const float Dz = fmaf(rho, T.t[2], c.az[t]);
+            const float Dx = fmaf(rho, T.t[0], fmaf(T.d[0], c.x0, fmaf(T.d[1], c.x1, T.d[2])));
+            const float Dy = fmaf(rho, T.t[1], fmaf(T.d[3], c.x0, fmaf(T.d[4], c.x1, T.d[5])));
+            const float Dz = fmaf(rho, T.t[2], fmaf(T.d[6], c.x0, fmaf(T.d[7], c.x1, T.d[8])));
             const float Qz = 1.f + Dz;
             const bool zok = Qz > 0.f;
             const float iz = rcp(Qz);
@@ -501,9 +492,9 @@ __device__ __forceinline__ float energy2_bounded(const Win& w, const PoseF* __re
     for (int t = 0; t < VD_NMAX; ++t) {
         if (t >= w.N) break;
         const PoseF& T = P[t];
-        const float Dx = fmaf(rho, T.t[0], c.ax[t]);
-        const float Dy = fmaf(rho, T.t[1], c.ay[t]);
-        const float Dz = fmaf(rho, T.t[2], c.az[t]);
+        const float Dx = fmaf(rho, T.t[0], fmaf(T.d[0], c.x0, fmaf(T.d[1], c.x1, T.d[2])));
+        const float Dy = fmaf(rho, T.t[1], fmaf(T.d[3], c.x0, fmaf(T.d[4], c.x1, T.d[5])));
+        const float Dz = fmaf(rho, T.t[2], fmaf(T.d[6], c.x0, fmaf(T.d[7], c.x1, T.d[8])));
         const float Qz = 1.f + Dz;
         const bool zok = Qz > 0.f;
         const float iz = rcp(Qz);
