@@ -9,14 +9,20 @@ before the timed region.  The unit of work is one (reference pixel, frame) pair 
 through one GEM iteration: 1216 * 352 * 6 * 10 = 25.68 M units per window.
 
 Also reported, on the same JSON line:
-  roofline      the dominant kernel (the fused local-level E+M pass), timed live with HIP
-                events on the stream it is launched on, against the FP32 vector ALU peak;
+  roofline      the dominant kernel (the fused local-level E+M pass): its launches inside the
+                timed steps are bracketed with HIP events on their launch stream by the
+                library's timers; achieved = algorithmic FP32 flops per launch / average
+                launch duration, against the FP32 vector ALU peak.  traffic = HBM-side bytes
+                per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary committed under
+                profiles/ (null when the library sources changed since it was taken);
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same window (GEM iteration 0
                 on the full image), timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +40,32 @@ FLOPS_ESTEP_PER_PIXEL_FRAME = 65.0
 # Non-packed FP32 vector peak: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz.  Packed FP32
 # instructions are disabled in this build, which halves the 157.3 TFLOP/s published peak.
 PEAK_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# Algorithmic bytes of one local-level launch per pixel: per frame the flow (8 B) and the
+# rigidness written (4 B); inverse depth read and written (8 B); the coarse value (4 B per
+# lattice cell of s*s = 16 pixels).
+BYTES_PER_PIXEL_FRAME = 12.0
+BYTES_PER_PIXEL = 8.0 + 4.0 / 16
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_level_local_1216x352_n6_k32_hbm_bytes.txt")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2104_06800_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM-side bytes per launch of the local-level kernel from the committed counter summary,
+    or None when it is absent or was taken on other library sources."""
+    try:
+        rows = dict(l.split(":", 1) for l in open(TRAFFIC_SUMMARY) if ":" in l and not l.startswith(" "))
+        if rows["source_sha256_16"].strip() != source_hash():
+            return None
+        return float(rows["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -46,7 +78,6 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -69,7 +100,7 @@ def main():
         return
 
     from paper_2104_06800_amd import synth
-    from paper_2104_06800_amd.binding import LOCAL, Voldor
+    from paper_2104_06800_amd.binding import TIMER_COARSE, TIMER_LOCAL, TIMER_POSE, Voldor
 
     t0 = time.time()
     w = synth.make_window(2, 0)
@@ -88,11 +119,15 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    lib.timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    timers = {name: lib.timing_read(t) for name, t in (("local", TIMER_LOCAL), ("coarse", TIMER_COARSE),
+                                                        ("pose", TIMER_POSE))}
+    lib.timing(False)
     units = H * W * N * I
     value = units / (ms / 1e3)
     stats = b["stats"].cpu().numpy()
@@ -101,25 +136,28 @@ def main():
     err = np.abs(rho - w["idepth_gt"]) / w["idepth_gt"]
     log(f"window: {ms:.3f} ms  ->  {value / 1e9:.3f} G pixel-frame updates/s; "
         f"median static inverse-depth rel error {np.median(err[static]):.4f}; loglik {stats[0]:.6g}")
+    per_window = {k: v[0] * 1e3 / args.steps for k, v in timers.items()}
+    log("per window: " + ", ".join(f"{k} {v:.0f} us ({timers[k][1] // args.steps} brackets)"
+                                   for k, v in per_window.items()))
 
-    # dominant kernel: fused local-level pass, timed with events on the launch stream
-    stream = torch.cuda.current_stream()
-    lib.level_step(p, b, 5, LOCAL)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for r in range(args.kernel_reps):
-        lib.level_step(p, b, 4 + (r % 4), LOCAL)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    k_ms = e0.elapsed_time(e1) / args.kernel_reps
+    # dominant kernel: the fused local-level pass, every launch of it in the timed steps
+    k_ms_total, k_n = timers["local"]
+    k_ms = k_ms_total / k_n
     flops = H * W * N * (K * FLOPS_PER_CAND_FRAME + FLOPS_ESTEP_PER_PIXEL_FRAME)
+    alg_bytes = H * W * (N * BYTES_PER_PIXEL_FRAME + BYTES_PER_PIXEL)
     achieved = flops / (k_ms / 1e3) / 1e12
-    log(f"local level pass: {k_ms * 1e3:.1f} us/launch, {flops / 1e9:.2f} GFLOP algorithmic, "
-        f"{achieved:.2f} TFLOP/s")
+    traffic = measured_traffic()
+    log(f"local level pass: {k_ms * 1e3:.1f} us/launch over {k_n} launches, {flops / 1e9:.2f} GFLOP "
+        f"algorithmic, {achieved:.2f} TFLOP/s; algorithmic bytes {alg_bytes / 1e6:.1f} MB "
+        f"({alg_bytes / (k_ms / 1e3) / 1e9:.0f} GB/s); counted traffic "
+        f"{'n/a' if traffic is None else f'{traffic / 1e6:.1f} MB'}")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "kernel": "k_level (local level, fused E+M)", "kernel_us": round(k_ms * 1e3, 2)}
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "traffic_unit": "bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE)",
+                "algorithmic_bytes": round(alg_bytes), "kernel": "k_level (local level, fused E+M)",
+                "kernel_us": round(k_ms * 1e3, 2), "launches": k_n,
+                "window_us": {k: round(v, 1) for k, v in per_window.items()}}
 
     cpu = None
     if not args.no_cpu_baseline:

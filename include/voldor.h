@@ -157,6 +157,37 @@ int voldor_gem_step(voldor_ctx ctx, const voldor_window* win, const voldor_buffe
 int voldor_finalize(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
                     int iter, void* stream);
 
+/* Flags of voldor_run / voldor_batch_run. */
+#define VOLDOR_RUN_INIT 1          /* start from voldor_init_idepth's random inverse depth  */
+
+/* A whole GEM window (sec. III-A, the iteration of Fig. 2's GEM block): optional random
+ * initial depth (flags & VOLDOR_RUN_INIT), iterations 0..n_iters-1 of voldor_gem_step and
+ * voldor_finalize at iteration n_iters-1.  Same results, bit for bit, as that sequence of
+ * calls; the flow layout the kernels read is built once per window rather than once per
+ * call.  n_iters >= 1. */
+int voldor_run(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
+               int n_iters, int flags, void* stream);
+
+/* n_windows independent windows (wins[i] with bufs[i]; shapes may differ), each as
+ * voldor_run with the same n_iters and flags, enqueued on one stream.  Results equal those
+ * of n_windows voldor_run calls.  Scratch is sized for the largest window.  1 <= n_windows
+ * <= 4096; every window is validated before anything is launched. */
+int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, const voldor_buffers* bufs,
+                     int n_iters, int flags, void* stream);
+
+/* Launch timers (measurement).  While enabled, the library brackets launches of each timer
+ * class with HIP events on the launch stream: VOLDOR_TIMER_LOCAL = the fused local-level
+ * E+M kernel, VOLDOR_TIMER_COARSE = a coarse-level pass (its E-step and M-step launches),
+ * VOLDOR_TIMER_POSE = a pose step (all its Gauss-Newton launches).  voldor_timing(ctx, 1)
+ * starts afresh and discards earlier records; voldor_timing(ctx, 0) stops recording.
+ * voldor_timing_read waits for the recorded events of one class, returns the summed
+ * duration (ms) and the number of bracketed launches, and clears that class. */
+#define VOLDOR_TIMER_LOCAL  0
+#define VOLDOR_TIMER_COARSE 1
+#define VOLDOR_TIMER_POSE   2
+int voldor_timing(voldor_ctx ctx, int enable);
+int voldor_timing_read(voldor_ctx ctx, int timer, double* total_ms, int64_t* launches);
+
 /* Keyframe-alignment parameters (sec. III-B, Eqs. 10, 12). */
 typedef struct {
     int32_t H, W;

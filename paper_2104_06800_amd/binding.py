@@ -13,6 +13,8 @@ from .build import LIB
 
 OK, EINVAL, ENOMEM, EDEVICE, ESINGULAR = 0, 1, 2, 3, 4
 COARSE, LOCAL = 0, 1
+RUN_INIT = 1
+TIMER_LOCAL, TIMER_COARSE, TIMER_POSE = 0, 1, 2
 SCORE_LEN = 29
 STATS_LEN = 8
 MAX_FRAMES, MAX_PRIORS = 8, 4
@@ -51,6 +53,7 @@ class AlignParams(ctypes.Structure):
 EXPORTS = sorted(["voldor_ctx_create", "voldor_ctx_destroy", "voldor_last_error", "voldor_lattice_shape",
                   "voldor_init_idepth", "voldor_rigidness_fb", "voldor_depth_update", "voldor_level_step",
                   "voldor_pose_score", "voldor_pose_step", "voldor_gem_step", "voldor_finalize",
+                  "voldor_run", "voldor_batch_run", "voldor_timing", "voldor_timing_read",
                   "voldor_align_p2p"])
 
 
@@ -75,6 +78,10 @@ def load_library(path=LIB):
     lib.voldor_pose_step.argtypes = [V, W, B, V]
     lib.voldor_gem_step.argtypes = [V, W, B, I, V]
     lib.voldor_finalize.argtypes = [V, W, B, I, V]
+    lib.voldor_run.argtypes = [V, W, B, I, I, V]
+    lib.voldor_batch_run.argtypes = [V, I, W, B, I, I, V]
+    lib.voldor_timing.argtypes = [V, I]
+    lib.voldor_timing_read.argtypes = [V, I, P(ctypes.c_double), P(ctypes.c_int64)]
     lib.voldor_align_p2p.argtypes = [V, P(AlignParams), I, V, V, V, V, V, V, V, V]
     for n in EXPORTS:
         if n not in ("voldor_ctx_destroy", "voldor_last_error"):
@@ -215,13 +222,27 @@ class Voldor:
                     "voldor_finalize")
 
     def run(self, p, b, iters=None, init=True, stream=None):
-        """Plain GEM: random init, iterations 0..I-1, finalize (all on the stream)."""
+        """Plain GEM window in one call: random init, iterations 0..I-1, finalize."""
         iters = p.get("iters", 5) if iters is None else iters
-        if init:
-            self.init_idepth(p, b, stream)
-        for it in range(iters):
-            self.gem_step(p, b, it, stream)
-        self.finalize(p, b, iters - 1, stream)
+        self._check(_LIB.voldor_run(self._h, make_window(p), self._bufs(p, b), iters, RUN_INIT if init else 0,
+                                    _stream(stream)), "voldor_run")
+
+    def batch_run(self, windows, iters, init=True, stream=None):
+        """windows: list of (params, buffers); every window runs iters iterations."""
+        n = len(windows)
+        wins = (Window * n)(*[make_window(p) for p, _ in windows])
+        bufs = (Buffers * n)(*[self._bufs(p, b) for p, b in windows])
+        self._check(_LIB.voldor_batch_run(self._h, n, wins, bufs, iters, RUN_INIT if init else 0, _stream(stream)),
+                    "voldor_batch_run")
+
+    def timing(self, enable):
+        self._check(_LIB.voldor_timing(self._h, 1 if enable else 0), "voldor_timing")
+
+    def timing_read(self, timer):
+        """(total ms, launches) of one timer class since the last read; waits for them."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(_LIB.voldor_timing_read(self._h, timer, ctypes.byref(ms), ctypes.byref(n)), "voldor_timing_read")
+        return ms.value, n.value
 
     def align_p2p(self, ap, idepth1, idepth2, conf2, pose_inout, stream=None):
         """Returns (cov [n][36], stats [n][4], status [n]); pose_inout is updated in place."""

@@ -6,10 +6,14 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/voldor.h"
 #include "device.h"
 #include "kernels.h"
+
+constexpr int kTimers = 3;
 
 struct voldor_ctx_s {
     int device = 0;
@@ -17,6 +21,9 @@ struct voldor_ctx_s {
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
     int n_cu = 256;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;                                   // idle events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[kTimers];    // recorded brackets
 };
 
 namespace {
@@ -49,6 +56,49 @@ int hip_fail(voldor_ctx ctx, hipError_t e, const char* what) {
     } while (0)
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---- launch timers: an event pair per bracketed launch, recycled through a pool
+hipError_t take_event(voldor_ctx ctx, hipEvent_t* e) {
+    if (!ctx->ev_pool.empty()) {
+        *e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Start of a bracket: *a stays null when timing is off.
+hipError_t timer_start(voldor_ctx ctx, hipStream_t st, hipEvent_t* a) {
+    *a = nullptr;
+    if (!ctx->timing) return hipSuccess;
+    hipError_t e = take_event(ctx, a);
+    if (e == hipSuccess) e = hipEventRecord(*a, st);
+    return e;
+}
+
+hipError_t timer_stop(voldor_ctx ctx, int which, hipStream_t st, hipEvent_t a) {
+    if (!a) return hipSuccess;
+    hipEvent_t b = nullptr;
+    hipError_t e = take_event(ctx, &b);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e != hipSuccess) {
+        ctx->ev_pool.push_back(a);
+        if (b) ctx->ev_pool.push_back(b);
+        return e;
+    }
+    ctx->ev_rec[which].emplace_back(a, b);
+    return hipSuccess;
+}
+
+void timers_discard(voldor_ctx ctx) {
+    for (auto& r : ctx->ev_rec) {
+        for (auto& p : r) {
+            ctx->ev_pool.push_back(p.first);
+            ctx->ev_pool.push_back(p.second);
+        }
+        r.clear();
+    }
+}
 
 // Scratch layout: [FP32 poses | FP64 poses | work region]; grown on demand.
 struct Scratch {
@@ -263,6 +313,10 @@ int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll)
     B.pa_V = L.pa_V;
     B.pa_S = L.pa_S;
     B.pa_spec = L.pa_spec;
+    hipEvent_t t0 = nullptr;
+    const int timer = level == VOLDOR_LEVEL_COARSE ? VOLDOR_TIMER_COARSE : VOLDOR_TIMER_LOCAL;
+    const bool timed = level == VOLDOR_LEVEL_COARSE || (do_e && do_m);
+    if (timed) VD_CHECK(timer_start(ctx, L.st, &t0), "timer event");
     if (level == VOLDOR_LEVEL_COARSE && do_m) {
         // few long chains: E-step per chain, phase A over the whole lattice, then the
         // per-chain speculation + scan from the stored phase-A results
@@ -270,9 +324,10 @@ int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll)
         VD_CHECK(vd::launch_phase_a(w, g, B, L.st), "phase A launch");
         VD_CHECK(vd::launch_phase_a2(w, g, B, L.st), "phase A2 launch");
         VD_CHECK(vd::launch_level(w, g, B, 0, 2, L.st), "level kernel launch");
-        return VOLDOR_OK;
+    } else {
+        VD_CHECK(vd::launch_level(w, g, B, do_e, do_m, L.st), "level kernel launch");
     }
-    VD_CHECK(vd::launch_level(w, g, B, do_e, do_m, L.st), "level kernel launch");
+    if (timed) VD_CHECK(timer_stop(ctx, timer, L.st, t0), "timer event");
     return VOLDOR_OK;
 }
 
@@ -293,18 +348,69 @@ int run_pose_step(GemLaunch& L) {
     B.obs = L.obs;
     const int G = L.v->pose_gn_steps;
     if (G == 0) return VOLDOR_OK;
+    hipEvent_t t0 = nullptr;
+    VD_CHECK(timer_start(ctx, L.st, &t0), "timer event");
     for (int s = 0; s < L.v->N * G; ++s)
         VD_CHECK(vd::launch_pose_gn(w, B, s, G, L.gn_blocks, L.st), "pose step launch");
     VD_CHECK(vd::launch_pose_gn_finish(B, L.v->N, G, L.gn_blocks, L.st), "pose finish launch");
+    VD_CHECK(timer_stop(ctx, VOLDOR_TIMER_POSE, L.st, t0), "timer event");
     return VOLDOR_OK;
 }
 
-int prep_poses(GemLaunch& L) {
+// FP32/FP64 pose tables from the caller's 6-vectors; with layout, also the row-pair flow
+// layout (needed once per window: the flows do not change within it).
+int prep_poses(GemLaunch& L, bool layout = true) {
     voldor_ctx ctx = L.ctx;
     VD_CHECK(vd::launch_pose_prep(L.b->pose, L.v->N, L.b->prior_pose, L.v->P, L.s.poses, L.s.posed, L.st),
              "pose prep launch");
-    VD_CHECK(vd::launch_flow_pairs((const float2*)L.b->flow, L.flow2, L.v->N, L.v->H, L.v->W, L.st), "flow layout launch");
+    if (layout)
+        VD_CHECK(vd::launch_flow_pairs((const float2*)L.b->flow, L.flow2, L.v->N, L.v->H, L.v->W, L.st),
+                 "flow layout launch");
     return VOLDOR_OK;
+}
+
+// Final local E-step + confidence and statistics (poses already prepared).
+int run_finalize(GemLaunch& L, int iter) {
+    voldor_ctx ctx = L.ctx;
+    int rc;
+    if ((rc = run_level(L, iter, VOLDOR_LEVEL_LOCAL, 1, 0, true))) return rc;
+    const vd::Win w = make_win(L.v, iter, 1, L.b);
+    const vd::LevelGeom g = make_geom(L.v, w, 1, iter);
+    vd::FinalBufs B;
+    B.P = L.s.poses;
+    B.flow = (const float2*)L.b->flow;
+    B.flow2 = L.flow2;
+    B.idepth = L.b->idepth;
+    B.rigid = L.b->rigid;
+    B.prior = L.b->prior_idepth;
+    B.prior_weight = L.b->prior_weight;
+    B.conf = L.b->conf;
+    B.stats = L.b->stats;
+    B.partials = L.pose_partials;
+    B.ll_partial = L.ll_partial;
+    VD_CHECK(vd::launch_finalize(w, B, g.nblocks, L.st), "finalize launch");
+    return VOLDOR_OK;
+}
+
+// One GEM iteration on a prepared launch; the pose tables are refreshed from the 6-vectors
+// first, as a separate voldor_gem_step call would.
+int run_iteration(GemLaunch& L, int it, bool layout) {
+    int rc;
+    if ((rc = prep_poses(L, layout))) return rc;
+    if ((rc = run_level(L, it, VOLDOR_LEVEL_COARSE, 1, 1, false))) return rc;
+    if ((rc = run_level(L, it, VOLDOR_LEVEL_LOCAL, 1, 1, false))) return rc;
+    return run_pose_step(L);
+}
+
+// A whole window on a prepared launch.
+int run_window(GemLaunch& L, int n_iters, int flags) {
+    voldor_ctx ctx = L.ctx;
+    int rc;
+    if (flags & VOLDOR_RUN_INIT) VD_CHECK(vd::launch_init(make_win(L.v, 0, 1), L.b->idepth, L.st), "init launch");
+    for (int it = 0; it < n_iters; ++it)
+        if ((rc = run_iteration(L, it, it == 0))) return rc;
+    if ((rc = prep_poses(L, false))) return rc;
+    return run_finalize(L, n_iters - 1);
 }
 
 }  // namespace
@@ -337,11 +443,11 @@ int voldor_ctx_create(voldor_ctx* out, int device_ordinal) {
 
 void voldor_ctx_destroy(voldor_ctx ctx) {
     if (!ctx) return;
-    if (ctx->scratch) {
-        (void)hipSetDevice(ctx->device);
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->scratch);
-    }
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    timers_discard(ctx);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -450,10 +556,7 @@ int voldor_gem_step(voldor_ctx ctx, const voldor_window* v, const voldor_buffers
     VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
     GemLaunch L;
     if ((rc = gem_prepare(ctx, v, b, st, L))) return rc;
-    if ((rc = prep_poses(L))) return rc;
-    if ((rc = run_level(L, iter, VOLDOR_LEVEL_COARSE, 1, 1, false))) return rc;
-    if ((rc = run_level(L, iter, VOLDOR_LEVEL_LOCAL, 1, 1, false))) return rc;
-    return run_pose_step(L);
+    return run_iteration(L, iter, true);
 }
 
 int voldor_finalize(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int iter, void* stream) {
@@ -466,22 +569,65 @@ int voldor_finalize(voldor_ctx ctx, const voldor_window* v, const voldor_buffers
     GemLaunch L;
     if ((rc = gem_prepare(ctx, v, b, st, L))) return rc;
     if ((rc = prep_poses(L))) return rc;
-    if ((rc = run_level(L, iter, VOLDOR_LEVEL_LOCAL, 1, 0, true))) return rc;
-    const vd::Win w = make_win(v, iter, 1, b);
-    const vd::LevelGeom g = make_geom(v, w, 1, iter);
-    vd::FinalBufs B;
-    B.P = L.s.poses;
-    B.flow = (const float2*)b->flow;
-    B.flow2 = L.flow2;
-    B.idepth = b->idepth;
-    B.rigid = b->rigid;
-    B.prior = b->prior_idepth;
-    B.prior_weight = b->prior_weight;
-    B.conf = b->conf;
-    B.stats = b->stats;
-    B.partials = L.pose_partials;
-    B.ll_partial = L.ll_partial;
-    VD_CHECK(vd::launch_finalize(w, B, g.nblocks, st), "finalize launch");
+    return run_finalize(L, iter);
+}
+
+int voldor_run(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int n_iters, int flags,
+               void* stream) {
+    return voldor_batch_run(ctx, 1, v, b, n_iters, flags, stream);
+}
+
+int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, const voldor_buffers* bufs,
+                     int n_iters, int flags, void* stream) {
+    if (!ctx) return VOLDOR_EINVAL;
+    if (n_windows < 1 || n_windows > (int)kMaxBatch || !wins || !bufs)
+        return fail(ctx, VOLDOR_EINVAL, "bad window batch");
+    if (n_iters < 1 || n_iters > 0xffffff) return fail(ctx, VOLDOR_EINVAL, "n_iters must be >= 1");
+    if (flags & ~VOLDOR_RUN_INIT) return fail(ctx, VOLDOR_EINVAL, "unknown flags 0x%x", flags);
+    int rc;
+    for (int i = 0; i < n_windows; ++i) {
+        if ((rc = check_window(ctx, &wins[i], &bufs[i]))) return rc;
+        if (!bufs[i].conf || !bufs[i].stats) return fail(ctx, VOLDOR_EINVAL, "null conf/stats pointer (window %d)", i);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    // size the scratch for the largest window before the first launch
+    GemLaunch L;
+    for (int i = 0; i < n_windows; ++i)
+        if ((rc = gem_prepare(ctx, &wins[i], &bufs[i], st, L))) return rc;
+    for (int i = 0; i < n_windows; ++i) {
+        if ((rc = gem_prepare(ctx, &wins[i], &bufs[i], st, L))) return rc;
+        if ((rc = run_window(L, n_iters, flags))) return rc;
+    }
+    return VOLDOR_OK;
+}
+
+int voldor_timing(voldor_ctx ctx, int enable) {
+    if (!ctx) return VOLDOR_EINVAL;
+    timers_discard(ctx);
+    ctx->timing = enable != 0;
+    return VOLDOR_OK;
+}
+
+int voldor_timing_read(voldor_ctx ctx, int timer, double* total_ms, int64_t* launches) {
+    if (!ctx) return VOLDOR_EINVAL;
+    if (timer < 0 || timer >= kTimers || !total_ms || !launches) return fail(ctx, VOLDOR_EINVAL, "bad timer query");
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    double sum = 0.0;
+    auto& rec = ctx->ev_rec[timer];
+    for (auto& p : rec) {
+        float ms = 0.f;
+        VD_CHECK(hipEventSynchronize(p.second), "hipEventSynchronize");
+        VD_CHECK(hipEventElapsedTime(&ms, p.first, p.second), "hipEventElapsedTime");
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = (int64_t)rec.size();
+    for (auto& p : rec) {
+        ctx->ev_pool.push_back(p.first);
+        ctx->ev_pool.push_back(p.second);
+    }
+    rec.clear();
     return VOLDOR_OK;
 }
 

@@ -1,0 +1,121 @@
+"""GPU: the whole-window entry points and the launch timers.
+
+voldor_run and voldor_batch_run promise the results of the equivalent sequence of
+per-step calls bit for bit (same kernels, same launch order, the flow layout built once
+instead of per call), so these tests compare with exact equality.  Their parity with the
+oracle follows from the per-step parity tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2104_06800_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("idepth", "rigid", "pose", "conf", "stats", "idepth_coarse", "rigid_coarse")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2104_06800_amd.binding import Voldor
+    v = Voldor(0)
+    yield v
+    v.close()
+
+
+def alloc(lib, w):
+    p = w["params"]
+    return lib.alloc(p, w["flow"], w["pose_init"], w.get("prior_idepth"), w.get("prior_pose"),
+                     w.get("prior_weight"))
+
+
+def host(b):
+    torch.cuda.synchronize()
+    return {k: b[k].detach().cpu().numpy().copy() for k in KEYS}
+
+
+def assert_same(a, b):
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def windows():
+    out = [synth.make_window(1, 0), synth.make_window(3, 1, H=53, W=70, N=4),
+           synth.make_window(1, 2, H=40, W=61, N=5)]
+    out[2]["params"]["tile"] = 16
+    return out
+
+
+def test_run_equals_step_sequence(lib):
+    w = synth.make_window(1, 3)
+    p = w["params"]
+    a, b = alloc(lib, w), alloc(lib, w)
+    I = p["iters"]
+    print(f"run vs steps: {p['W']}x{p['H']} N={p['N']} iters={I}", flush=True)
+    lib.run(p, a, iters=I)
+    lib.init_idepth(p, b)
+    for it in range(I):
+        lib.gem_step(p, b, it)
+    lib.finalize(p, b, I - 1)
+    assert_same(host(a), host(b))
+
+
+def test_run_without_init_continues_from_given_depth(lib):
+    w = synth.make_window(1, 4)
+    p = w["params"]
+    a, b = alloc(lib, w), alloc(lib, w)
+    for t in (a, b):
+        t["idepth"].copy_(torch.as_tensor(w["idepth_gt"], dtype=torch.float32).cuda())
+    lib.run(p, a, iters=2, init=False)
+    for it in range(2):
+        lib.gem_step(p, b, it)
+    lib.finalize(p, b, 1)
+    assert_same(host(a), host(b))
+
+
+def test_batch_run_equals_individual_runs(lib):
+    ws = windows()
+    iters = 3
+    batch = [(w["params"], alloc(lib, w)) for w in ws]
+    single = [(w["params"], alloc(lib, w)) for w in ws]
+    print("batch of", [(p["W"], p["H"], p["N"], p.get("P", 0)) for p, _ in batch], flush=True)
+    lib.batch_run(batch, iters)
+    for p, b in single:
+        lib.run(p, b, iters=iters)
+    for (_, x), (_, y) in zip(batch, single):
+        hx = host(x)
+        assert_same(hx, host(y))
+        assert np.isfinite(hx["stats"]).all()
+
+
+def test_batch_run_rejects_bad_arguments(lib):
+    from paper_2104_06800_amd.binding import VoldorError
+    ws = windows()[:2]
+    batch = [(w["params"], alloc(lib, w)) for w in ws]
+    with pytest.raises(VoldorError):
+        lib.batch_run(batch, 0)
+    with pytest.raises(VoldorError):
+        lib.batch_run([], 1)
+    bad = dict(ws[1]["params"])
+    bad["n_candidates"] = 2
+    with pytest.raises(VoldorError):
+        lib.batch_run([batch[0], (bad, batch[1][1])], 1)
+
+
+def test_timers_count_bracketed_launches(lib):
+    from paper_2104_06800_amd.binding import TIMER_COARSE, TIMER_LOCAL, TIMER_POSE
+    w = synth.make_window(1, 0)
+    p = w["params"]
+    b = alloc(lib, w)
+    lib.timing(True)
+    lib.run(p, b, iters=3)
+    lib.level_step(p, b, 1, 1)
+    got = {t: lib.timing_read(t) for t in (TIMER_LOCAL, TIMER_COARSE, TIMER_POSE)}
+    lib.timing(False)
+    # local: 3 fused passes + the level_step; the final E-step alone is not bracketed
+    assert got[TIMER_LOCAL][1] == 4 and got[TIMER_COARSE][1] == 3 and got[TIMER_POSE][1] == 3
+    assert all(ms > 0 for ms, _ in got.values())
+    assert lib.timing_read(TIMER_LOCAL) == (0.0, 0)
+    lib.run(p, b, iters=1)
+    assert lib.timing_read(TIMER_LOCAL) == (0.0, 0)
