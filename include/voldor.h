@@ -130,7 +130,9 @@ int voldor_depth_update(voldor_ctx ctx, const voldor_window* win, const voldor_b
  * equations H = sum w J^T J (upper triangle, row-major, 21 values) and g = sum w J^T e of
  * the residual e = p_t - o_t with IRLS weight w = q d cost / d r^2 and J the derivative
  * w.r.t. a left update (dw, dv), and the count of valid terms.  o_t uses the current pose
- * of frame t-1.  cand_pose: [n_cand][6] device FP64; out: [n_cand][29] device FP64. */
+ * of frame t-1.  A term is valid where the point is in front of cameras t-1 and t, the
+ * flow sample at p_{t-1} exists and p_t lies inside frame t's image.
+ * cand_pose: [n_cand][6] device FP64; out: [n_cand][29] device FP64. */
 int voldor_pose_score(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
                       int t, int n_cand, const double* cand_pose, double* out, void* stream);
 

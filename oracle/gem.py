@@ -364,7 +364,12 @@ def pose_score(win, bufs, t, cand):
     sum_j q_t^j cost_t^j, the IRLS normal equations H = sum w J^T J, g = sum w J^T e of
     the residual e = p_t - o_t with w = q d cost / d(r^2), and the number of valid terms.
     o_t uses the current pose of frame t-1.  Returns [n_cand, 29]:
-    energy, H upper triangle row-major (21), g (6), count."""
+    energy, H upper triangle row-major (21), g (6), count.
+
+    Reading of the pose step's term set: a term counts only where the reprojection p_t lies
+    inside frame t's image (a flow end point is observed nowhere else); otherwise it is
+    invalid like any other (cost q log 2, no weight).  Without this, points that pass just
+    in front of camera t (Q_z -> 0+) enter with weight ~ 1/Q_z^2 and decide the step."""
     w = Window(win, bufs)
     cand = np.atleast_2d(np.asarray(cand, dtype=np.float64))
     V, U = np.mgrid[0:w.H, 0:w.W]
@@ -388,7 +393,8 @@ def pose_score(win, bufs, t, cand):
         R, tt = geo.pose_rt(pc)
         Q = geo.scaled_point(R, tt, xt, rho)
         px, py, zok = geo.project(Q, *w.intr)
-        ok = zprev & zok & fv
+        inside = (px >= 0) & (px <= w.W - 1) & (py >= 0) & (py <= w.H - 1)
+        ok = zprev & zok & fv & inside
         e = np.stack([px - ox, py - oy], -1)
         r2 = np.where(ok, (e * e).sum(-1), 0.0)
         r2f = w._floor_r2(r2)

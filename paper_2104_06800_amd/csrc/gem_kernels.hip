@@ -449,6 +449,14 @@ k_phase_a2(Win w, LevelGeom g, LevelBufs B) {
 // ----------------------------------------------------------------------------------
 // pose normal equations for frame t at candidate poses; optional FP64 solve + update
 // ----------------------------------------------------------------------------------
+// Pose-step terms exist only where the reprojection lands inside frame t's image: a flow
+// end point is observed nowhere else, and points passing just in front of camera t
+// (Q_z -> 0+, far outside the image) would otherwise dominate the normal equations with
+// weight ~ 1/Q_z^2.  NaN coordinates fail the test.
+__device__ __forceinline__ bool in_frame(const Win& w, float px, float py) {
+    return px >= 0.f && px <= (float)(w.W - 1) && py >= 0.f && py <= (float)(w.H - 1);
+}
+
 template <bool B2>
 __device__ __forceinline__ void pose_pixel(const Win& w, const PoseBufs& B, const PoseF& Tc, int t, int j,
                                            float* acc) {
@@ -484,7 +492,7 @@ __device__ __forceinline__ void pose_pixel(const Win& w, const PoseBufs& B, cons
     const bool zok = Qz > 0.f;
     const float iz = rcp(Qz);
     const float dx = w.fx * fmaf(-x0, Dz, Dx) * iz, dy = w.fy * fmaf(-x1, Dz, Dy) * iz;
-    const bool ok = zprev && zok && fok;
+    const bool ok = zprev && zok && fok && in_frame(w, (float)u + dx, (float)v + dy);
     const float ex = (dx - dpx) - fx, ey = (dy - dpy) - fy;
     const float r2 = fmaf(ex, ex, ey * ey);
     acc[0] = fmaf(q, ok ? flow_cost2<B2>(w, r2) : 1.0f, acc[0]);
@@ -676,7 +684,7 @@ k_pose_gn(Win w, PoseBufs B, int s, int G) {
             const bool zok = Qz > 0.f;
             const float iz = rcp(Qz);
             const float dx = w.fx * fmaf(-x0, Dz, Dx) * iz, dy = w.fy * fmaf(-x1, Dz, Dy) * iz;
-            const bool ok = zok && isfinite(ox[b]) && isfinite(oy[b]);
+            const bool ok = zok && isfinite(ox[b]) && isfinite(oy[b]) && in_frame(w, (float)u + dx, (float)v + dy);
             const float ex = dx - ox[b], ey = dy - oy[b];
             const float r2 = fmaf(ex, ex, ey * ey);
             a32[0] = fmaf(q[b], ok ? flow_cost2<B2>(w, r2) : 1.0f, a32[0]);

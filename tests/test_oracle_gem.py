@@ -240,6 +240,49 @@ def test_pose_score_gradient_and_hessian_by_finite_differences():
         assert np.all(np.linalg.eigvalsh(H) >= -1e-9 * np.trace(H))
 
 
+def test_pose_score_counts_only_reprojections_inside_frame_t():
+    """Brute force per pixel: a term is valid iff its point is in front of both cameras, the
+    flow sample of frame t-1 exists, and the reprojection into frame t lies in the image."""
+    w, win = small_window(N=2, H=20, W=28, tile=8)
+    b = gem.alloc_buffers(win, w["flow"], w["pose_init"])
+    b["idepth"][...] = w["idepth_gt"]
+    b["rigid"][...] = 0.7
+    fx, fy, cx, cy = win["fx"], win["fy"], win["cx"], win["cy"]
+    t = 2
+    # a candidate that rotates part of the image out of frame t
+    cand = geo.left_update(b["pose"][t - 1], np.array([0.0, 0.25, 0.0, 0.0, 0.0, 0.0]))
+    Rp, tp = geo.pose_rt(b["pose"][t - 2])
+    Rc, tc = geo.pose_rt(cand)
+    count = seen = 0
+    for v in range(win["H"]):
+        for u in range(win["W"]):
+            X = np.array([(u - cx) / fx, (v - cy) / fy, 1.0]) / w["idepth_gt"][v, u]
+            Qp, Qc = Rp @ X + tp, Rc @ X + tc
+            if Qp[2] <= 0 or Qc[2] <= 0:
+                continue
+            pu, pv = fx * Qp[0] / Qp[2] + cx, fy * Qp[1] / Qp[2] + cy
+            if not (0 <= pu <= win["W"] - 1 and 0 <= pv <= win["H"] - 1):
+                continue
+            seen += 1
+            cu, cv = fx * Qc[0] / Qc[2] + cx, fy * Qc[1] / Qc[2] + cy
+            count += (0 <= cu <= win["W"] - 1) and (0 <= cv <= win["H"] - 1)
+    row = gem.pose_score(win, b, t, cand[None])[0]
+    assert 0 < count < seen - 20          # the rule removes a good share of the terms
+    assert row[28] == count
+
+
+def test_pose_score_of_a_view_away_from_the_scene_is_uninformative():
+    w, win = small_window(N=2, H=20, W=28, tile=8)
+    b = gem.alloc_buffers(win, w["flow"], w["pose_init"])
+    b["idepth"][...] = w["idepth_gt"]
+    rng = np.random.default_rng(3)
+    b["rigid"][...] = rng.uniform(0.0, 1.0, b["rigid"].shape)
+    cand = geo.left_update(b["pose"][0], np.array([0.0, np.pi / 2, 0.0, 0.0, 0.0, 0.0]))
+    row = gem.pose_score(win, b, 1, cand[None])[0]
+    assert row[28] == 0 and np.all(row[1:28] == 0)
+    assert row[0] == pytest.approx(np.log(2) * b["rigid"][0].sum(), rel=1e-12)
+
+
 def test_pose_jacobian_by_finite_differences():
     win = synth.default_params(10, 12, 1, (30.0, 30.0, 6.0, 5.0))
     rng = np.random.default_rng(4)
