@@ -190,6 +190,70 @@ int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, c
 int voldor_timing(voldor_ctx ctx, int enable);
 int voldor_timing_read(voldor_ctx ctx, int timer, double* total_ms, int64_t* launches);
 
+/* ---------------------------------------------------------------------------------
+ * Learned depth / rigidness proposal.  The paper initialises depth at random (sec. III-A);
+ * this project adds a small convolutional encoder-decoder that maps the flow stack of a
+ * window to an initial inverse depth and initial rigidness maps, while plain GEM stays the
+ * fallback and the judge of its error.  BF16 weights and activations, FP32 accumulation on
+ * the matrix cores, FP32 master weights and Adam.
+ *
+ * Layers (3x3, zero padding 1, NHWC; stored channel counts):
+ *   c1 16 -> 64, c2 64 -> 128 stride 2, c3 128 -> 128, c4 128 -> 128, all ReLU;
+ *   c5 128 -> 64 on the 2x nearest upsampling of c4's output, + c1's output, ReLU;
+ *   c6 64 -> 32 linear.
+ * Input channel 2(t-1)+c = X_t[c] / 16 (non-finite -> 0; N <= 8, the rest 0).  Outputs:
+ * idepth = clip(softplus(o_0) / tnorm, idepth_min, idepth_max), where tnorm = |t| of frame
+ * 1's initial pose (flows fix depth only up to that scale); rigid_t = sigmoid(o_t).
+ * H and W must be even (the stride-2 / upsampling pair).
+ * ------------------------------------------------------------------------------- */
+#define VOLDOR_NET_PARAMS 470560   /* FP32 parameters: per layer c1..c6, w [Cout][3][3][Cin], b [Cout] */
+
+typedef struct {
+    float*    params;        /* [VOLDOR_NET_PARAMS] FP32 master parameters                  */
+    uint16_t* wbf16;         /* [VOLDOR_NET_PARAMS] BF16 copy of params (the kernels' weights) */
+    uint16_t* wt_bf16;       /* [VOLDOR_NET_PARAMS] BF16 weights transposed to [Cin][3][3][Cout]
+                                per layer (training; NULL for inference)                    */
+    float*    adam_m;        /* [VOLDOR_NET_PARAMS] Adam moments (training; else NULL)       */
+    float*    adam_v;
+    float*    grads;         /* [VOLDOR_NET_PARAMS] gradients of the last training step      */
+} voldor_net;
+
+/* Rewrites wbf16 (and wt_bf16 when set) from params; call after changing params. */
+int voldor_net_refresh(voldor_ctx ctx, const voldor_net* net, void* stream);
+
+/* Inference on one window: flow [N][H][W][2] FP32 -> idepth_out [H][W], rigid_out [N][H][W]
+ * (either may be NULL) and, when logits_out is set, the linear output [H][W][32] FP32. */
+int voldor_proposal_forward(voldor_ctx ctx, const voldor_net* net, int32_t H, int32_t W, int32_t N,
+                            const float* flow, float tnorm, float idepth_min, float idepth_max,
+                            float* idepth_out, float* rigid_out, float* logits_out, void* stream);
+
+/* One training step on one window: forward, loss
+ *   L = mean over mask of |softplus(o_0) - idepth_target * tnorm|
+ *       + lam * mean over pixels and frames of BCE(sigmoid(o_t), rigid_target_t),
+ * backward (gradients into net->grads) and an Adam step (lr, beta 0.9 / 0.999, eps 1e-8;
+ * step counts from 1).  loss_out (device, FP64 [3]) receives L, its depth part and its BCE
+ * part.  Needs every training pointer of net. */
+int voldor_proposal_train_step(voldor_ctx ctx, const voldor_net* net, int32_t H, int32_t W, int32_t N,
+                               const float* flow, float tnorm, const float* idepth_target,
+                               const float* rigid_target, const uint8_t* mask, float lam, float lr,
+                               int32_t step, double* loss_out, void* stream);
+
+/* One 3x3 convolution layer (the network's building block): input x [H][W][Cin] BF16 (its 2x
+ * nearest upsampling when up = 1), weights w [Cout][3][3][Cin] BF16, bias [Cout] FP32 (or
+ * NULL), optional skip [Ho][Wo][Cout] BF16 added before the optional ReLU; output y BF16
+ * and/or yf FP32, [Ho][Wo][Cout] with Ho = (H' - 1) / stride + 1 on the (upsampled) input
+ * H'.  Cin a multiple of 16, Cout of 32; stride 1 or 2 (not with up). */
+int voldor_conv3x3_bf16(voldor_ctx ctx, int32_t H, int32_t W, int32_t Cin, int32_t Cout, int32_t stride,
+                        int32_t up, int32_t relu, const uint16_t* x, const uint16_t* w, const float* bias,
+                        const uint16_t* skip, uint16_t* y, float* yf, void* stream);
+
+/* Gradients of that layer (without its activation) for an upstream gradient dy
+ * [Ho][Wo][Cout] BF16: dx [H][W][Cin], dw [Cout][3][3][Cin], db [Cout], all FP32 (each
+ * may be NULL).  w_t is the BF16 weight transposed to [Cin][3][3][Cout]. */
+int voldor_conv3x3_bf16_backward(voldor_ctx ctx, int32_t H, int32_t W, int32_t Cin, int32_t Cout,
+                                 int32_t stride, int32_t up, const uint16_t* x, const uint16_t* w_t,
+                                 const uint16_t* dy, float* dx, float* dw, float* db, void* stream);
+
 /* Keyframe-alignment parameters (sec. III-B, Eqs. 10, 12). */
 typedef struct {
     int32_t H, W;

@@ -15,6 +15,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESINGULAR = 0, 1, 2, 3, 4
 COARSE, LOCAL = 0, 1
 RUN_INIT = 1
 TIMER_LOCAL, TIMER_COARSE, TIMER_POSE = 0, 1, 2
+NET_PARAMS = 470560
 SCORE_LEN = 29
 STATS_LEN = 8
 MAX_FRAMES, MAX_PRIORS = 8, 4
@@ -43,6 +44,10 @@ class Buffers(ctypes.Structure):
                  "prior_idepth", "prior_pose", "prior_weight", "conf", "stats")]
 
 
+class Net(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("params", "wbf16", "wt_bf16", "adam_m", "adam_v", "grads")]
+
+
 class AlignParams(ctypes.Structure):
     _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32),
                 ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
@@ -54,6 +59,8 @@ EXPORTS = sorted(["voldor_ctx_create", "voldor_ctx_destroy", "voldor_last_error"
                   "voldor_init_idepth", "voldor_rigidness_fb", "voldor_depth_update", "voldor_level_step",
                   "voldor_pose_score", "voldor_pose_step", "voldor_gem_step", "voldor_finalize",
                   "voldor_run", "voldor_batch_run", "voldor_timing", "voldor_timing_read",
+                  "voldor_net_refresh", "voldor_proposal_forward", "voldor_proposal_train_step",
+                  "voldor_conv3x3_bf16", "voldor_conv3x3_bf16_backward",
                   "voldor_align_p2p"])
 
 
@@ -82,6 +89,12 @@ def load_library(path=LIB):
     lib.voldor_batch_run.argtypes = [V, I, W, B, I, I, V]
     lib.voldor_timing.argtypes = [V, I]
     lib.voldor_timing_read.argtypes = [V, I, P(ctypes.c_double), P(ctypes.c_int64)]
+    F = ctypes.c_float
+    lib.voldor_net_refresh.argtypes = [V, P(Net), V]
+    lib.voldor_proposal_forward.argtypes = [V, P(Net), I, I, I, V, F, F, F, V, V, V, V]
+    lib.voldor_proposal_train_step.argtypes = [V, P(Net), I, I, I, V, F, V, V, V, F, F, I, V, V]
+    lib.voldor_conv3x3_bf16.argtypes = [V, I, I, I, I, I, I, I, V, V, V, V, V, V, V]
+    lib.voldor_conv3x3_bf16_backward.argtypes = [V, I, I, I, I, I, I, V, V, V, V, V, V, V]
     lib.voldor_align_p2p.argtypes = [V, P(AlignParams), I, V, V, V, V, V, V, V, V]
     for n in EXPORTS:
         if n not in ("voldor_ctx_destroy", "voldor_last_error"):
@@ -243,6 +256,71 @@ class Voldor:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         self._check(_LIB.voldor_timing_read(self._h, timer, ctypes.byref(ms), ctypes.byref(n)), "voldor_timing_read")
         return ms.value, n.value
+
+    # -- learned proposal -------------------------------------------------------
+    def net_alloc(self, params, train=False):
+        """Device buffers of the proposal network from FP32 parameters [NET_PARAMS]."""
+        dev = torch.device("cuda", self.device)
+        p = torch.as_tensor(params, dtype=torch.float32).to(dev).contiguous()
+        if p.numel() != NET_PARAMS:
+            raise VoldorError(f"need {NET_PARAMS} parameters, got {p.numel()}")
+        z16 = lambda: torch.zeros(NET_PARAMS, dtype=torch.int16, device=dev)
+        net = dict(params=p, wbf16=z16(), wt_bf16=z16() if train else None,
+                   adam_m=torch.zeros_like(p) if train else None, adam_v=torch.zeros_like(p) if train else None,
+                   grads=torch.zeros_like(p) if train else None)
+        self.net_refresh(net)
+        return net
+
+    @staticmethod
+    def _net(net):
+        return Net(*[_ptr(net.get(n)) for n, _ in Net._fields_])
+
+    def net_refresh(self, net, stream=None):
+        self._check(_LIB.voldor_net_refresh(self._h, ctypes.byref(self._net(net)), _stream(stream)),
+                    "voldor_net_refresh")
+
+    def proposal_forward(self, net, flow, tnorm, idepth_min, idepth_max, logits=False, stream=None):
+        """flow [N][H][W][2] FP32 device tensor -> (idepth [H][W], rigid [N][H][W], logits or None)."""
+        N, H, W, _ = flow.shape
+        dev = flow.device
+        rho = torch.empty((H, W), dtype=torch.float32, device=dev)
+        q = torch.empty((N, H, W), dtype=torch.float32, device=dev)
+        o = torch.empty((H, W, 32), dtype=torch.float32, device=dev) if logits else None
+        self._check(_LIB.voldor_proposal_forward(self._h, ctypes.byref(self._net(net)), H, W, N, _ptr(flow),
+                                                 float(tnorm), float(idepth_min), float(idepth_max), _ptr(rho),
+                                                 _ptr(q), _ptr(o), _stream(stream)), "voldor_proposal_forward")
+        return rho, q, o
+
+    def proposal_train_step(self, net, flow, tnorm, idepth_t, rigid_t, mask, lam, lr, step, loss_out, stream=None):
+        N, H, W, _ = flow.shape
+        self._check(_LIB.voldor_proposal_train_step(
+            self._h, ctypes.byref(self._net(net)), H, W, N, _ptr(flow), float(tnorm), _ptr(idepth_t), _ptr(rigid_t),
+            _ptr(mask), float(lam), float(lr), int(step), _ptr(loss_out), _stream(stream)), "voldor_proposal_train_step")
+
+    def conv3x3_bf16(self, x, w, bias=None, skip=None, stride=1, up=0, relu=0, want_y=True, stream=None):
+        """x [H][W][Cin], w [Cout][3][3][Cin] as int16 tensors of BF16 bits -> (y bits, y FP32)."""
+        H, W, Cin = x.shape
+        Cout = w.shape[0]
+        Hs, Ws = (2 * H, 2 * W) if up else (H, W)
+        Ho, Wo = (Hs - 1) // stride + 1, (Ws - 1) // stride + 1
+        y = torch.empty((Ho, Wo, Cout), dtype=torch.int16, device=x.device) if want_y else None
+        yf = torch.empty((Ho, Wo, Cout), dtype=torch.float32, device=x.device)
+        self._check(_LIB.voldor_conv3x3_bf16(self._h, H, W, Cin, Cout, stride, up, relu, _ptr(x), _ptr(w),
+                                             _ptr(bias), _ptr(skip), _ptr(y), _ptr(yf), _stream(stream)),
+                    "voldor_conv3x3_bf16")
+        return y, yf
+
+    def conv3x3_bf16_backward(self, x, w_t, dy, stride=1, up=0, stream=None):
+        """-> (dx [H][W][Cin], dw [Cout][3][3][Cin], db [Cout]) FP32."""
+        H, W, Cin = x.shape
+        Cout = dy.shape[2]
+        dx = torch.empty((H, W, Cin), dtype=torch.float32, device=x.device)
+        dw = torch.empty((Cout, 3, 3, Cin), dtype=torch.float32, device=x.device)
+        db = torch.empty(Cout, dtype=torch.float32, device=x.device)
+        self._check(_LIB.voldor_conv3x3_bf16_backward(self._h, H, W, Cin, Cout, stride, up, _ptr(x), _ptr(w_t),
+                                                      _ptr(dy), _ptr(dx), _ptr(dw), _ptr(db), _stream(stream)),
+                    "voldor_conv3x3_bf16_backward")
+        return dx, dw, db
 
     def align_p2p(self, ap, idepth1, idepth2, conf2, pose_inout, stream=None):
         """Returns (cov [n][36], stats [n][4], status [n]); pose_inout is updated in place."""

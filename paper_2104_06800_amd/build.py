@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libvoldor.so")
-SOURCES = ["api.hip", "gem_kernels.hip", "align_kernels.hip"]
+SOURCES = ["api.hip", "gem_kernels.hip", "align_kernels.hip", "proposal_kernels.hip", "proposal_api.hip"]
 ARCH = os.environ.get("VOLDOR_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -10,50 +10,17 @@
 #include <vector>
 
 #include "../../include/voldor.h"
+#include "ctx.h"
 #include "device.h"
 #include "kernels.h"
 
-constexpr int kTimers = 3;
-
-struct voldor_ctx_s {
-    int device = 0;
-    std::string err;
-    void* scratch = nullptr;
-    size_t scratch_bytes = 0;
-    int n_cu = 256;
-    bool timing = false;
-    std::vector<hipEvent_t> ev_pool;                                   // idle events
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[kTimers];    // recorded brackets
-};
+using vdc::fail;
+using vdc::hip_fail;
 
 namespace {
 
-thread_local std::string g_create_err;
-
 constexpr size_t kMaxBatch = 4096;         // candidates per pose_score call / pairs per align call
 constexpr size_t kLevelLdsMax = 150 * 1024;
-
-int fail(voldor_ctx ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
-int fail(voldor_ctx ctx, int code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    if (ctx) ctx->err = buf;
-    else g_create_err = buf;
-    return code;
-}
-
-int hip_fail(voldor_ctx ctx, hipError_t e, const char* what) {
-    return fail(ctx, VOLDOR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
-#define VD_CHECK(call, what)                                   \
-    do {                                                       \
-        hipError_t e_ = (call);                                \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, what);  \
-    } while (0)
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -415,6 +382,49 @@ int run_window(GemLaunch& L, int n_iters, int flags) {
 
 }  // namespace
 
+namespace vdc {
+
+namespace {
+thread_local std::string g_create_err;
+}
+
+const char* create_error() { return g_create_err.c_str(); }
+
+int fail(voldor_ctx ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_create_err = buf;
+    return code;
+}
+
+int hip_fail(voldor_ctx ctx, hipError_t e, const char* what) {
+    return fail(ctx, VOLDOR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int ensure_buffer(voldor_ctx ctx, void** buf, size_t* cap, size_t need, hipStream_t st) {
+    if (need <= *cap) return VOLDOR_OK;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    if (*buf) {
+        VD_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
+        VD_CHECK(hipFree(*buf), "hipFree");
+        *buf = nullptr;
+        *cap = 0;
+    }
+    const size_t bytes = need + need / 4;
+    if (hipMalloc(buf, bytes) != hipSuccess) {
+        *buf = nullptr;
+        return fail(ctx, VOLDOR_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
+    }
+    *cap = bytes;
+    return VOLDOR_OK;
+}
+
+}  // namespace vdc
+
 // ======================================================================================
 extern "C" {
 
@@ -446,13 +456,14 @@ void voldor_ctx_destroy(voldor_ctx ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->net_ws) (void)hipFree(ctx->net_ws);
     timers_discard(ctx);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
 const char* voldor_last_error(voldor_ctx ctx) {
-    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+    return ctx ? ctx->err.c_str() : vdc::create_error();
 }
 
 int voldor_lattice_shape(int32_t H, int32_t W, int32_t stride, int32_t* Hc, int32_t* Wc) {

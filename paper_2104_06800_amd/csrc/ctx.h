@@ -1,0 +1,44 @@
+// Library context shared by the C-ABI translation units: device, last error message,
+// scratch / workspace buffers and launch timers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/voldor.h"
+
+constexpr int kTimers = 3;
+
+struct voldor_ctx_s {
+    int device = 0;
+    std::string err;
+    void* scratch = nullptr;          // GEM scratch (pose tables, flow layout, partials)
+    size_t scratch_bytes = 0;
+    void* net_ws = nullptr;           // proposal-network workspace (activations, gradients)
+    size_t net_ws_bytes = 0;
+    int n_cu = 256;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;                                   // idle events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[kTimers];    // recorded brackets
+};
+
+namespace vdc {
+
+// Records the message on ctx (or as the thread's context-creation error when ctx is null)
+// and returns code.
+int fail(voldor_ctx ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int hip_fail(voldor_ctx ctx, hipError_t e, const char* what);
+const char* create_error();
+// Grows *buf (device memory on ctx's device) to at least need bytes; the old contents are
+// not kept.  Waits for st before freeing a smaller buffer.
+int ensure_buffer(voldor_ctx ctx, void** buf, size_t* cap, size_t need, hipStream_t st);
+
+}  // namespace vdc
+
+#define VD_CHECK(call, what)                                        \
+    do {                                                            \
+        hipError_t e_ = (call);                                     \
+        if (e_ != hipSuccess) return vdc::hip_fail(ctx, e_, what);  \
+    } while (0)

@@ -1,0 +1,435 @@
+// Learned depth / rigidness proposal on gfx950: BF16 3x3 convolutions as implicit GEMMs on
+// the matrix cores (v_mfma_f32_32x32x16_bf16), FP32 accumulation, NHWC activations.
+//
+//   k_conv<NT, MODE>  MODE 0: y = act(conv3x3(x) + b [+ skip])    (stride 1 or 2, optional 2x
+//                              nearest upsampling of the input)
+//                     MODE 1: data gradient dx = conv3x3^T(dy) with the transposed weights
+//                              [Cin][3][3][Cout], optional "+ add" and "* (mask > 0)" epilogue
+//                     GEMM view: M = output pixels, N = output channels, K = 9 * input
+//                     channels.  A wave owns 32 pixels x 32 NT channels (NT accumulators of
+//                     32x32); a block of 4 waves owns 128 consecutive pixels.  Cin is a
+//                     multiple of 16, Cout of 16 (a partial channel tile reads zero weights).
+//   k_wgrad           dW[co][tap][ci] = sum_m dy[m][co] x_tap(m)[ci] per pixel chunk (FP32
+//                     partials), k_sum_chunks reduces them in a fixed order
+//   k_features, k_pool2, k_heads, k_loss (+ finish), k_adam: the element-wise rest.
+//
+// MFMA operand layout (32x32x16, wave64): lane l supplies A[i = l%32][k = 8(l/32) .. +7] and
+// B[k = 8(l/32) .. +7][j = l%32]; the 16 accumulators of lane l hold D[i][j = l%32] for
+// i = 8(a/4) + 4(l/32) + a%4, a = 0..15.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "proposal.h"
+
+namespace vp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// round to nearest even; NaN stays NaN
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
+}
+
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u}); }
+
+// ---------------------------------------------------------------------------------------
+// input features: channel 2(t-1) + c = X_t[c] / FLOW_SCALE (non-finite -> 0), 16 channels
+// ---------------------------------------------------------------------------------------
+__global__ void k_features(const float2* __restrict__ flow, int N, int HW, uint16_t* __restrict__ x) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= HW) return;
+    uint16_t v[VP_C_IN];
+#pragma unroll
+    for (int c = 0; c < VP_C_IN; ++c) v[c] = 0;
+    for (int t = 0; t < N; ++t) {
+        const float2 f = flow[(size_t)t * HW + j];
+        v[2 * t] = isfinite(f.x) ? f2bf(f.x * (1.0f / VP_FLOW_SCALE)) : (uint16_t)0;
+        v[2 * t + 1] = isfinite(f.y) ? f2bf(f.y * (1.0f / VP_FLOW_SCALE)) : (uint16_t)0;
+    }
+    u32x4* out = reinterpret_cast<u32x4*>(x + (size_t)j * VP_C_IN);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        u32x4 w;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = (uint32_t)v[8 * q + 2 * e] | ((uint32_t)v[8 * q + 2 * e + 1] << 16);
+        out[q] = w;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// implicit-GEMM convolution
+// ---------------------------------------------------------------------------------------
+template <int NT, int MODE>
+__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Mpix = a.Ho * a.Wo;
+    const int m = (blockIdx.x * 4 + wave) * 32 + (lane & 31);   // A row of this lane
+    const int kb = lane >> 5;                                     // k sub-block (8 channels)
+    const int n0 = blockIdx.y * 32 * NT;
+    const bool mvalid = m < Mpix;
+    const int oy = mvalid ? m / a.Wo : 0, ox = mvalid ? m - oy * a.Wo : 0;
+    f32x16 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[nt][e] = 0.f;
+
+    // output channels beyond Cout (a 16-channel data gradient fills half a tile) read zeros
+    const uint16_t* wrow[NT];
+    bool nvalid[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int n = n0 + 32 * nt + (lane & 31);
+        nvalid[nt] = n < a.Cout;
+        wrow[nt] = a.w + (size_t)(nvalid[nt] ? n : 0) * 9 * a.Cin + 8 * kb;
+    }
+
+    for (int tap = 0; tap < 9; ++tap) {
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        int sy, sx;
+        bool ok = mvalid;
+        if (MODE == 0) {
+            sy = oy * a.stride + ky - 1;
+            sx = ox * a.stride + kx - 1;
+            ok = ok && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws;
+            if (a.up) { sy >>= 1; sx >>= 1; }
+        } else {
+            sy = oy + 1 - ky;
+            sx = ox + 1 - kx;
+            if (a.stride == 2) {
+                ok = ok && !(sy & 1) && !(sx & 1);
+                sy >>= 1;
+                sx >>= 1;
+            }
+            ok = ok && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws;
+        }
+        const uint16_t* xp = a.x + ((size_t)(ok ? sy : 0) * a.Wx + (ok ? sx : 0)) * a.Cin + 8 * kb;
+        const size_t woff = (size_t)tap * a.Cin;
+        for (int c0 = 0; c0 < a.Cin; c0 += 16) {
+            const bf16x8 A = ok ? load8(xp + c0) : zero8();
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const bf16x8 B = nvalid[nt] ? load8(wrow[nt] + woff + c0) : zero8();
+                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[nt], 0, 0, 0);
+            }
+        }
+    }
+
+    // epilogue: lane holds D[i][j = lane%32] for rows i = 8(e/4) + 4(lane/32) + e%4
+    const int mw = (blockIdx.x * 4 + wave) * 32;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int n = n0 + 32 * nt + (lane & 31);
+        if (n >= a.Cout) continue;
+        const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int mm = mw + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            if (mm >= Mpix) continue;
+            const size_t o = (size_t)mm * a.Cout + n;
+            float v = acc[nt][e] + bias;
+            if (a.skip) v += bf2f(a.skip[o]);
+            if (a.addf) v += a.addf[o];
+            if (a.relu) v = fmaxf(v, 0.f);
+            if (a.mask && !(bf2f(a.mask[o]) > 0.f)) v = 0.f;
+            if (a.y) a.y[o] = f2bf(v);
+            if (a.yf) a.yf[o] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// 2x2 sum pooling of an FP32 gradient on the upsampled grid, times the ReLU mask of the
+// pooled grid's activation, stored as BF16 (and FP32 when asked)
+// ---------------------------------------------------------------------------------------
+__global__ void k_pool2(const float* __restrict__ g, int H2, int W2, int C, const uint16_t* __restrict__ mask,
+                        uint16_t* __restrict__ out, float* __restrict__ outf) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int H = H2 / 2, W = W2 / 2;
+    if (i >= (size_t)H * W * C) return;
+    const int c = (int)(i % C);
+    const int p = (int)(i / C);
+    const int y = p / W, x = p - y * W;
+    const size_t b = ((size_t)(2 * y) * W2 + 2 * x) * C + c;
+    float v = (g[b] + g[b + C]) + (g[b + (size_t)W2 * C] + g[b + (size_t)W2 * C + C]);
+    if (mask && !(bf2f(mask[i]) > 0.f)) v = 0.f;
+    if (out) out[i] = f2bf(v);
+    if (outf) outf[i] = v;
+}
+
+// ---------------------------------------------------------------------------------------
+// weight gradient: block = (32 output channels) x (one tap, 32 input channels) x pixel chunk
+// D[co][ci] = sum_m dy[m][co] x_tap(m)[ci]; the 4 waves take interleaved 16-pixel steps of the
+// chunk and are summed through LDS.  A lane's 8 k-values are 8 consecutive pixels.
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
+    __shared__ float red[4][64][16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int co0 = blockIdx.x * 32;
+    const int ci_tiles = (a.Cin + 31) / 32;   // a 16-channel input uses half a tile
+    const int tap = blockIdx.y / ci_tiles, ci0 = (blockIdx.y - tap * ci_tiles) * 32;
+    const int ky = tap / 3, kx = tap - 3 * ky;
+    const int Mpix = a.Ho * a.Wo;
+    const int chunk = (Mpix + gridDim.z - 1) / gridDim.z;
+    const int mbeg = blockIdx.z * chunk, mend = min(Mpix, mbeg + chunk);
+    const int co = co0 + (lane & 31), ci = ci0 + (lane & 31);
+    const bool civ = ci < a.Cin;
+    f32x16 acc;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+    for (int m0 = mbeg + 16 * wave; m0 < mend; m0 += 64) {
+        bf16x8 A, B;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int m = m0 + 8 * (lane >> 5) + e;
+            uint16_t av = 0, bv = 0;
+            if (m < mend) {
+                av = a.dy[(size_t)m * a.Cout + co];
+                const int oy = m / a.Wo, ox = m - oy * a.Wo;
+                int sy = oy * a.stride + ky - 1, sx = ox * a.stride + kx - 1;
+                if (civ && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws) {
+                    if (a.up) { sy >>= 1; sx >>= 1; }
+                    bv = a.x[((size_t)sy * a.Wx + sx) * a.Cin + ci];
+                }
+            }
+            A[e] = __builtin_bit_cast(__bf16, av);
+            B[e] = __builtin_bit_cast(__bf16, bv);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) red[wave][lane][e] = acc[e];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const float s = (red[0][lane][e] + red[1][lane][e]) + (red[2][lane][e] + red[3][lane][e]);
+            const int i = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);     // co within tile
+            const int j = lane & 31;                                   // ci within tile
+            if (ci0 + j < a.Cin) a.part[(size_t)blockIdx.z * a.nparam + ((size_t)(co0 + i) * 9 + tap) * a.Cin + ci0 + j] = s;
+        }
+    }
+}
+
+// bias gradient partials: per (channel, pixel chunk)
+__global__ void k_bgrad(const uint16_t* __restrict__ dy, int Mpix, int C, int nchunks, float* __restrict__ part) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const int chunk = (Mpix + nchunks - 1) / nchunks;
+    const int mbeg = blockIdx.y * chunk, mend = min(Mpix, mbeg + chunk);
+    float s = 0.f;
+    for (int m = mbeg; m < mend; ++m) s += bf2f(dy[(size_t)m * C + c]);
+    part[(size_t)blockIdx.y * C + c] = s;
+}
+
+// out[i] = sum over chunks of part[chunk][i], fixed order
+__global__ void k_sum_chunks(const float* __restrict__ part, int n, int nchunks, float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * n + i];
+    out[i] = s;
+}
+
+// ---------------------------------------------------------------------------------------
+// heads: rho = clip(softplus(o_0) / |t_1|, rho_min, rho_max), q_t = sigmoid(o_t)
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+__device__ __forceinline__ float sigmoidf(float z) { return 0.5f * (1.f + tanhf(0.5f * z)); }
+
+__global__ void k_heads(const float* __restrict__ o, int HW, int N, float tnorm, float rmin, float rmax,
+                        float* __restrict__ rho, float* __restrict__ q) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= HW) return;
+    const float* oj = o + (size_t)j * VP_C_HEAD;
+    if (rho) rho[j] = fminf(fmaxf(softplusf(oj[0]) / tnorm, rmin), rmax);
+    if (q)
+        for (int t = 0; t < N; ++t) q[(size_t)t * HW + j] = sigmoidf(oj[1 + t]);
+}
+
+// ---------------------------------------------------------------------------------------
+// loss: L = mean_mask |softplus(o_0) - rho_t tnorm| + lam mean BCE(sigmoid(o_t), q_t); its
+// gradient w.r.t. o (BF16, zero on unused channels) and per-block FP64 partial sums
+// [L1 sum, mask count, BCE sum]
+// ---------------------------------------------------------------------------------------
+// 1 / max(1, number of masked pixels), one block
+__global__ void __launch_bounds__(1024) k_mask_count(const uint8_t* __restrict__ mask, int HW, float* __restrict__ inv) {
+    __shared__ int red[16];
+    int c = 0;
+    for (int j = threadIdx.x; j < HW; j += 1024) c += mask[j] != 0;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int i = 0; i < 16; ++i) s += red[i];
+        inv[0] = 1.0f / (float)max(s, 1);
+    }
+}
+
+__global__ void k_loss(const float* __restrict__ o, int HW, int N, float tnorm, const float* __restrict__ rho_t,
+                       const float* __restrict__ q_t, const uint8_t* __restrict__ mask, float lam,
+                       const float* __restrict__ inv_cnt_p, uint16_t* __restrict__ dout, double* __restrict__ part) {
+    __shared__ double red[3][4];
+    const float inv_cnt = inv_cnt_p[0];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    double l1 = 0.0, cnt = 0.0, bce = 0.0;
+    if (j < HW) {
+        const float* oj = o + (size_t)j * VP_C_HEAD;
+        uint16_t* dj = dout + (size_t)j * VP_C_HEAD;
+        const float s = softplusf(oj[0]);
+        const float d = s - rho_t[j] * tnorm;
+        const bool mk = mask[j] != 0;
+        float g0 = 0.f;
+        if (mk) {
+            l1 = fabs((double)d);
+            cnt = 1.0;
+            g0 = (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f)) * sigmoidf(oj[0]) * inv_cnt;
+        }
+        dj[0] = f2bf(g0);
+        const float inv_q = lam / (float)((size_t)N * HW);
+        for (int c = 1; c < VP_C_HEAD; ++c) {
+            float g = 0.f;
+            if (c <= N) {
+                const float z = oj[c], qt = q_t[(size_t)(c - 1) * HW + j];
+                bce += (double)(softplusf(z) - qt * z);
+                g = (sigmoidf(z) - qt) * inv_q;
+            }
+            dj[c] = f2bf(g);
+        }
+    }
+    double v[3] = {l1, cnt, bce};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    }
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 3; ++k) red[k][threadIdx.x >> 6] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        part[(size_t)k * gridDim.x + blockIdx.x] = (red[k][0] + red[k][1]) + (red[k][2] + red[k][3]);
+    }
+}
+
+// loss[0] = L, loss[1] = L1 part, loss[2] = BCE part (fixed-order sums of the partials)
+__global__ void k_loss_finish(const double* __restrict__ part, int nb, int N, int HW, float lam,
+                              double* __restrict__ loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 3; ++k)
+        for (int b = 0; b < nb; ++b) s[k] += part[(size_t)k * nb + b];
+    const double l1 = s[0] / fmax(s[1], 1.0), bce = s[2] / ((double)N * HW);
+    loss[0] = l1 + (double)lam * bce;
+    loss[1] = l1;
+    loss[2] = bce;
+}
+
+// ---------------------------------------------------------------------------------------
+// Adam on the FP32 master parameters; refreshes the BF16 weights and their transposed copy
+// ---------------------------------------------------------------------------------------
+__global__ void k_adam(AdamArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= VP_NPARAM) return;
+    float p = a.params[i];
+    if (a.grads) {
+        const float g = a.grads[i];
+        const float m = fmaf(a.b1, a.m[i], (1.f - a.b1) * g);
+        const float v = fmaf(a.b2, a.v[i], (1.f - a.b2) * g * g);
+        a.m[i] = m;
+        a.v[i] = v;
+        p -= a.lr * (m * a.inv_bc1) / (sqrtf(v * a.inv_bc2) + a.eps);
+        a.params[i] = p;
+    }
+    const uint16_t h = f2bf(p);
+    a.wbf[i] = h;
+    // transposed copy of a weight: [co][tap][ci] -> [ci][tap][co] within its layer
+    int L = 0;
+    while (L + 1 < VP_NLAYERS && i >= c_layer_off[L + 1]) ++L;
+    const int r = i - c_layer_off[L];
+    const int ci_n = c_layer_cin[L], co_n = c_layer_cout[L];
+    if (r < co_n * 9 * ci_n && a.wt) {
+        const int co = r / (9 * ci_n), rr = r - co * 9 * ci_n, tap = rr / ci_n, ci = rr - tap * ci_n;
+        a.wt[c_layer_off[L] + ((size_t)ci * 9 + tap) * co_n + co] = h;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+hipError_t launch_features(const float* flow, int N, int HW, uint16_t* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_features, dim3((HW + 255) / 256), dim3(256), 0, st, (const float2*)flow, N, HW, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t st) {
+    const int Mpix = a.Ho * a.Wo;
+    const int NT = (a.Cout % 64 == 0) ? 2 : 1;
+    const dim3 grid((unsigned)((Mpix + 127) / 128), (unsigned)((a.Cout + 32 * NT - 1) / (32 * NT)));
+    if (mode == 0) {
+        if (NT == 2) hipLaunchKernelGGL((k_conv<2, 0>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_conv<1, 0>), grid, dim3(256), 0, st, a);
+    } else {
+        if (NT == 2) hipLaunchKernelGGL((k_conv<2, 1>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_conv<1, 1>), grid, dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pool2(const float* g, int H2, int W2, int C, const uint16_t* mask, uint16_t* out, float* outf,
+                        hipStream_t st) {
+    const size_t n = (size_t)(H2 / 2) * (W2 / 2) * C;
+    hipLaunchKernelGGL(k_pool2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, H2, W2, C, mask, out, outf);
+    return hipGetLastError();
+}
+
+hipError_t launch_wgrad(const WgradArgs& a, int nchunks, hipStream_t st) {
+    const dim3 grid((unsigned)(a.Cout / 32), (unsigned)(9 * ((a.Cin + 31) / 32)), (unsigned)nchunks);
+    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bgrad(const uint16_t* dy, int Mpix, int C, int nchunks, float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_bgrad, dim3((unsigned)((C + 63) / 64), (unsigned)nchunks), dim3(64), 0, st, dy, Mpix, C,
+                       nchunks, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_chunks(const float* part, int n, int nchunks, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, n, nchunks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_heads(const float* o, int HW, int N, float tnorm, float rmin, float rmax, float* rho, float* q,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_heads, dim3((HW + 255) / 256), dim3(256), 0, st, o, HW, N, tnorm, rmin, rmax, rho, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(const float* o, int HW, int N, float tnorm, const float* rho_t, const float* q_t,
+                       const uint8_t* mask, float lam, float* inv_cnt, uint16_t* dout, double* part, double* loss,
+                       hipStream_t st) {
+    const int nb = (HW + 255) / 256;
+    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(1024), 0, st, mask, HW, inv_cnt);
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, st, o, HW, N, tnorm, rho_t, q_t, mask, lam,
+                       (const float*)inv_cnt, dout, part);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(64), 0, st, part, nb, N, HW, lam, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_adam, dim3((VP_NPARAM + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace vp

@@ -1,0 +1,195 @@
+"""GPU parity of the learned-proposal kernels against the FP64 oracle (oracle/proposal.py).
+
+Both sides see the same BF16 values (inputs, weights, upstream gradients); the kernels sum
+their products in FP32.  Bars:
+  one layer (forward, dx, dw, db)  |gpu - oracle| <= 1e-5 * (sum of |terms|) elementwise:
+                                   an FP32 sum of K <= 1152 terms errs by ~sqrt(K) 2^-24 of it
+  BF16 outputs                     exactly the round-to-nearest-even of the GPU's own FP32 value
+  whole network (logits)           6 layers with BF16 activations between them: a rounding that
+                                   lands on the other side of a midpoint moves one activation by
+                                   one BF16 ulp (2^-8 relative), so the logits may differ by
+                                   <= 1e-2 of their scale at a few pixels and <= 1e-4 on average
+  training step                    loss rel 1e-4; per-layer gradients ||gpu - oracle|| <= 2e-2
+                                   ||oracle|| (upstream gradients are stored in BF16 between
+                                   layers: 2^-9 relative per element, five stages); Adam on the
+                                   GPU's gradients rel 1e-5 of the step; BF16 copies exact
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import proposal as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2104_06800_amd.binding import Voldor
+    v = Voldor(0)
+    yield v
+    v.close()
+
+
+def bits(a):
+    """BF16 bit patterns (int16 tensor on the GPU) of the values a (rounded to nearest even)."""
+    f = P.bf16(a).astype(np.float32)
+    return torch.from_numpy((f.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)).cuda()
+
+
+def from_bits(t):
+    u = t.detach().cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def np_(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+CASES = [
+    dict(H=9, W=13, Cin=16, Cout=32, stride=1, up=0, relu=0, skip=False),
+    dict(H=9, W=13, Cin=64, Cout=64, stride=2, up=0, relu=1, skip=False),
+    dict(H=7, W=10, Cin=128, Cout=64, stride=1, up=1, relu=1, skip=True),
+    dict(H=33, W=40, Cin=64, Cout=128, stride=1, up=0, relu=1, skip=False),
+    dict(H=16, W=20, Cin=128, Cout=128, stride=2, up=0, relu=0, skip=False),
+]
+
+
+def case_data(c, seed):
+    rng = np.random.default_rng(seed)
+    x = P.bf16(rng.normal(size=(c["H"], c["W"], c["Cin"])))
+    w = P.bf16(rng.normal(scale=0.1, size=(c["Cout"], 3, 3, c["Cin"])))
+    b = rng.normal(scale=0.1, size=c["Cout"]).astype(np.float32).astype(np.float64)
+    return x, w, b, rng
+
+
+@pytest.mark.parametrize("c", CASES, ids=lambda c: f"{c['H']}x{c['W']}_{c['Cin']}to{c['Cout']}_s{c['stride']}_up{c['up']}")
+def test_conv_forward(lib, c):
+    x, w, b, rng = case_data(c, 1)
+    ref = P.conv3x3(x, w, b, c["stride"], bool(c["up"]))
+    scale = P.conv3x3(np.abs(x), np.abs(w), np.abs(b), c["stride"], bool(c["up"]))
+    skip_t = None
+    if c["skip"]:
+        skip = P.bf16(rng.normal(size=ref.shape))
+        ref, scale, skip_t = ref + skip, scale + np.abs(skip), bits(skip)
+    if c["relu"]:
+        ref = np.maximum(ref, 0.0)
+    y, yf = lib.conv3x3_bf16(bits(x), bits(w), torch.tensor(b, dtype=torch.float32).cuda(), skip_t,
+                             stride=c["stride"], up=c["up"], relu=c["relu"])
+    got = np_(yf)
+    assert got.shape == ref.shape
+    err = np.abs(got - ref) / (scale + 1e-30)
+    print(f"max error / sum|terms| = {err.max():.2e}")
+    assert err.max() <= 1e-5
+    np.testing.assert_array_equal(from_bits(y), P.bf16(got))
+
+
+@pytest.mark.parametrize("c", CASES, ids=lambda c: f"{c['H']}x{c['W']}_{c['Cin']}to{c['Cout']}_s{c['stride']}_up{c['up']}")
+def test_conv_backward(lib, c):
+    x, w, b, rng = case_data(c, 2)
+    y = P.conv3x3(x, w, b, c["stride"], bool(c["up"]))
+    dy = P.bf16(rng.normal(size=y.shape))
+    dx, dw, db = P.conv3x3_backward(x, w, dy, c["stride"], bool(c["up"]))
+    sx, sw, sb = P.conv3x3_backward(np.abs(x), np.abs(w), np.abs(dy), c["stride"], bool(c["up"]))
+    w_t = np.ascontiguousarray(np.transpose(w, (3, 1, 2, 0)))
+    gx, gw, gb = lib.conv3x3_bf16_backward(bits(x), bits(w_t), bits(dy), stride=c["stride"], up=c["up"])
+    for name, g, r, s in (("dx", gx, dx, sx), ("dw", gw, dw, sw), ("db", gb, db, sb)):
+        e = np.abs(np_(g) - r) / (s + 1e-30)
+        print(f"{name}: max error / sum|terms| = {e.max():.2e}")
+        assert e.max() <= 1e-5, name
+
+
+def params_and_window(seed=3, N=6, H=32, W=48):
+    rng = np.random.default_rng(seed)
+    params = P.init_params(seed, N)
+    for k in params:
+        if k.endswith(".b"):
+            params[k] = rng.normal(scale=0.05, size=params[k].shape)
+    params = {k: v.astype(np.float32).astype(np.float64) for k, v in params.items()}
+    flow = rng.normal(scale=6.0, size=(N, H, W, 2)).astype(np.float32)
+    flow[0, 3, 5, 0] = np.nan
+    return params, flow, rng
+
+
+def flat(params):
+    out = []
+    for name, _, _, _, _, _, _ in P.LAYERS:
+        out += [params[name + ".w"].ravel(), params[name + ".b"].ravel()]
+    return np.concatenate(out)
+
+
+def unflat(vec):
+    out, o = {}, 0
+    for name, ci, co, _, _, _, _ in P.LAYERS:
+        n = co * 9 * ci
+        out[name + ".w"] = vec[o:o + n].reshape(co, 3, 3, ci)
+        out[name + ".b"] = vec[o + n:o + n + co]
+        o += n + co
+    return out
+
+
+def test_network_forward(lib):
+    params, flow, _ = params_and_window()
+    N, H, W, _ = flow.shape
+    net = lib.net_alloc(flat(params))
+    rho, q, o = lib.proposal_forward(net, torch.from_numpy(flow).cuda(), 1.7, 0.005, 0.5, logits=True)
+    acts = P.forward(params, P.features(flow.astype(np.float64)), round_bf16=True)
+    ref = acts["o"]
+    got = np_(o)
+    scale = np.abs(ref).max()
+    d = np.abs(got - ref)
+    print(f"logits: max |d| {d.max() / scale:.2e} of scale, mean {d.mean() / scale:.2e}")
+    assert d.max() <= 1e-2 * scale and d.mean() <= 1e-4 * scale
+    rr, qr = P.heads(got.astype(np.float64), N, 1.7, 0.005, 0.5)
+    np.testing.assert_allclose(np_(rho), rr, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(np_(q), qr, rtol=1e-5, atol=1e-6)
+
+
+def test_training_step(lib):
+    params, flow, rng = params_and_window(seed=4, N=3, H=24, W=32)
+    N, H, W, _ = flow.shape
+    rho_t = rng.uniform(0.01, 0.4, size=(H, W)).astype(np.float32)
+    q_t = rng.uniform(0, 1, size=(N, H, W)).astype(np.float32)
+    mask = (rng.uniform(size=(H, W)) < 0.7)
+    tn, lam, lr = 1.3, 0.5, 1e-3
+    net = lib.net_alloc(flat(params), train=True)
+    loss = torch.zeros(3, dtype=torch.float64, device="cuda")
+    cu = lambda a, dt=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to(dt).cuda()
+    lib.proposal_train_step(net, cu(flow), tn, cu(rho_t), cu(q_t), cu(mask.astype(np.uint8), torch.uint8), lam, lr,
+                            1, loss)
+    acts = P.forward(params, P.features(flow.astype(np.float64)), round_bf16=True)
+    L, do = P.loss(acts["o"], rho_t.astype(np.float64), q_t.astype(np.float64), tn, mask, lam)
+    got_loss = np_(loss)
+    print("loss", got_loss, L)
+    assert got_loss[0] == pytest.approx(L, rel=1e-4)
+    rparams = {k: (P.bf16(v) if k.endswith(".w") else v) for k, v in params.items()}
+    grads = P.backward(rparams, acts, do)
+    g_gpu = unflat(np_(net["grads"]))
+    for k in grads:
+        rel = np.linalg.norm(g_gpu[k] - grads[k]) / max(np.linalg.norm(grads[k]), 1e-30)
+        print(f"grad {k}: relative error {rel:.2e}")
+        assert rel <= 2e-2, k
+    # Adam on the GPU's own gradients
+    p0 = {k: v.copy() for k, v in params.items()}
+    m = {k: np.zeros_like(v) for k, v in p0.items()}
+    v2 = {k: np.zeros_like(v) for k, v in p0.items()}
+    P.adam_step(p0, g_gpu, m, v2, 1, lr)
+    new = unflat(np_(net["params"]))
+    for k in p0:
+        assert np.abs(new[k] - p0[k]).max() <= 1e-5 * lr + 1e-7 * np.abs(p0[k]).max(), k
+    # BF16 copies follow the new parameters
+    newflat = np_(net["params"])
+    np.testing.assert_array_equal(from_bits(net["wbf16"]), P.bf16(newflat))
+    wt = unflat(from_bits(net["wt_bf16"]))
+    for name, ci, co, _, _, _, _ in P.LAYERS:
+        t = wt[name + ".w"].reshape(-1)[:co * 9 * ci].reshape(ci, 3, 3, co)
+        np.testing.assert_array_equal(np.transpose(t, (3, 1, 2, 0)), P.bf16(new[name + ".w"]))
+
+
+def test_network_rejects_odd_sizes(lib):
+    from paper_2104_06800_amd.binding import VoldorError
+    params, flow, _ = params_and_window(N=2, H=8, W=10)
+    net = lib.net_alloc(flat(params))
+    with pytest.raises(VoldorError):
+        lib.proposal_forward(net, torch.from_numpy(flow[:, :7]).contiguous().cuda(), 1.0, 0.01, 1.0)
