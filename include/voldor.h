@@ -161,19 +161,28 @@ int voldor_finalize(voldor_ctx ctx, const voldor_window* win, const voldor_buffe
 
 /* Flags of voldor_run / voldor_batch_run. */
 #define VOLDOR_RUN_INIT 1          /* start from voldor_init_idepth's random inverse depth  */
+#define VOLDOR_RUN_NO_GRAPH 2      /* voldor_batch_run: launch directly, no graph capture    */
 
 /* A whole GEM window (sec. III-A, the iteration of Fig. 2's GEM block): optional random
- * initial depth (flags & VOLDOR_RUN_INIT), iterations 0..n_iters-1 of voldor_gem_step and
- * voldor_finalize at iteration n_iters-1.  Same results, bit for bit, as that sequence of
- * calls; the flow layout the kernels read is built once per window rather than once per
- * call.  n_iters >= 1. */
+ * initial depth (flags & VOLDOR_RUN_INIT), iterations first_iter .. first_iter + n_iters - 1
+ * of voldor_gem_step and voldor_finalize at the last of them.  Same results, bit for bit,
+ * as that sequence of calls; the flow layout the kernels read is built once per window
+ * rather than once per call.  A start at first_iter > 0 continues from the caller's depth
+ * with the later, narrower candidate perturbations (a warm start, e.g. from the learned
+ * proposal).  n_iters >= 1, first_iter >= 0. */
 int voldor_run(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
-               int n_iters, int flags, void* stream);
+               int first_iter, int n_iters, int flags, void* stream);
 
-/* n_windows independent windows (wins[i] with bufs[i]; shapes may differ), each as
- * voldor_run with the same n_iters and flags, enqueued on one stream.  Results equal those
- * of n_windows voldor_run calls.  Scratch is sized for the largest window.  1 <= n_windows
- * <= 4096; every window is validated before anything is launched. */
+/* n_windows independent windows (wins[i] with bufs[i]; shapes, N, K, priors may differ),
+ * each as voldor_run from iteration 0 with the same n_iters and flags (VOLDOR_RUN_INIT),
+ * bit for bit.  Each
+ * step of the launch sequence is one launch over all windows per shape class (log-logistic
+ * shape 2 or not, priors or not): a block finds its window in an item table.  The whole
+ * sequence is captured once into a HIP graph on the first call for a given set of windows,
+ * buffers and settings and replayed by later identical calls (VOLDOR_RUN_NO_GRAPH launches
+ * directly).  The context keeps every window's scratch (about 60 MB for 1216x352, N = 6) for
+ * the graph's lifetime.  1 <= n_windows <= 4096; every window is validated before anything
+ * is launched.  The first call for a set waits for the stream once (table upload). */
 int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, const voldor_buffers* bufs,
                      int n_iters, int flags, void* stream);
 

@@ -13,7 +13,7 @@ from .build import LIB
 
 OK, EINVAL, ENOMEM, EDEVICE, ESINGULAR = 0, 1, 2, 3, 4
 COARSE, LOCAL = 0, 1
-RUN_INIT = 1
+RUN_INIT, RUN_NO_GRAPH = 1, 2
 TIMER_LOCAL, TIMER_COARSE, TIMER_POSE = 0, 1, 2
 NET_PARAMS = 470560
 SCORE_LEN = 29
@@ -85,7 +85,7 @@ def load_library(path=LIB):
     lib.voldor_pose_step.argtypes = [V, W, B, V]
     lib.voldor_gem_step.argtypes = [V, W, B, I, V]
     lib.voldor_finalize.argtypes = [V, W, B, I, V]
-    lib.voldor_run.argtypes = [V, W, B, I, I, V]
+    lib.voldor_run.argtypes = [V, W, B, I, I, I, V]
     lib.voldor_batch_run.argtypes = [V, I, W, B, I, I, V]
     lib.voldor_timing.argtypes = [V, I]
     lib.voldor_timing_read.argtypes = [V, I, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -234,19 +234,21 @@ class Voldor:
         self._check(_LIB.voldor_finalize(self._h, make_window(p), self._bufs(p, b), it, _stream(stream)),
                     "voldor_finalize")
 
-    def run(self, p, b, iters=None, init=True, stream=None):
-        """Plain GEM window in one call: random init, iterations 0..I-1, finalize."""
+    def run(self, p, b, iters=None, init=True, first_iter=0, stream=None):
+        """GEM window in one call: optional random init, iterations first_iter ..
+        first_iter + iters - 1, finalize."""
         iters = p.get("iters", 5) if iters is None else iters
-        self._check(_LIB.voldor_run(self._h, make_window(p), self._bufs(p, b), iters, RUN_INIT if init else 0,
-                                    _stream(stream)), "voldor_run")
+        self._check(_LIB.voldor_run(self._h, make_window(p), self._bufs(p, b), first_iter, iters,
+                                    RUN_INIT if init else 0, _stream(stream)), "voldor_run")
 
-    def batch_run(self, windows, iters, init=True, stream=None):
-        """windows: list of (params, buffers); every window runs iters iterations."""
+    def batch_run(self, windows, iters, init=True, graph=True, stream=None):
+        """windows: list of (params, buffers); every window runs iters iterations, batched
+        launches captured in a HIP graph (replayed by identical later calls)."""
         n = len(windows)
         wins = (Window * n)(*[make_window(p) for p, _ in windows])
         bufs = (Buffers * n)(*[self._bufs(p, b) for p, b in windows])
-        self._check(_LIB.voldor_batch_run(self._h, n, wins, bufs, iters, RUN_INIT if init else 0, _stream(stream)),
-                    "voldor_batch_run")
+        flags = (RUN_INIT if init else 0) | (0 if graph else RUN_NO_GRAPH)
+        self._check(_LIB.voldor_batch_run(self._h, n, wins, bufs, iters, flags, _stream(stream)), "voldor_batch_run")
 
     def timing(self, enable):
         self._check(_LIB.voldor_timing(self._h, 1 if enable else 0), "voldor_timing")

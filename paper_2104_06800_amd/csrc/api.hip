@@ -67,39 +67,13 @@ void timers_discard(voldor_ctx ctx) {
     }
 }
 
-// Scratch layout: [FP32 poses | FP64 poses | work region]; grown on demand.
+// Per-window scratch: [FP32 poses | FP64 poses | flow layout | pose history | observations |
+// log-likelihood partials | reduction partials | phase-A arrays].
 struct Scratch {
     vd::PoseF* poses;
     vd::PoseD* posed;
     char* a;
 };
-
-int ensure_scratch(voldor_ctx ctx, size_t extra, hipStream_t st, Scratch& s) {
-    const size_t head = align_up((VD_NMAX + VD_PMAX) * sizeof(vd::PoseF)) + align_up(VD_NMAX * sizeof(vd::PoseD));
-    const size_t need = head + align_up(extra);
-    if (need > ctx->scratch_bytes) {
-        VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
-        if (ctx->scratch) {
-            VD_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
-            VD_CHECK(hipFree(ctx->scratch), "hipFree");
-            ctx->scratch = nullptr;
-            ctx->scratch_bytes = 0;
-        }
-        const size_t bytes = need + need / 4;
-        if (hipMalloc(&ctx->scratch, bytes) != hipSuccess) {
-            ctx->scratch = nullptr;
-            return fail(ctx, VOLDOR_ENOMEM, "scratch allocation of %zu bytes failed", bytes);
-        }
-        ctx->scratch_bytes = bytes;
-    }
-    char* p = (char*)ctx->scratch;
-    s.poses = (vd::PoseF*)p;
-    p += align_up((VD_NMAX + VD_PMAX) * sizeof(vd::PoseF));
-    s.posed = (vd::PoseD*)p;
-    p += align_up(VD_NMAX * sizeof(vd::PoseD));
-    s.a = p;
-    return VOLDOR_OK;
-}
 
 int lattice(int H, int W, int s, int* hc, int* wc) {
     const int o = s / 2;
@@ -214,11 +188,11 @@ struct GemLaunch {
     int gn_blocks;
     int pose_blocks;
     int max_level_blocks;
+    struct { size_t head, f2, hist, obs, ll, red, pa; } sz;
 };
 
-int gem_prepare(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, hipStream_t st, GemLaunch& L,
-                int n_cand = 1) {
-    L.ctx = ctx; L.v = v; L.b = b; L.st = st;
+// Launch dimensions of one window and the byte size of its scratch.
+size_t gem_layout(const voldor_window* v, int n_cand, GemLaunch& L) {
     vd::Win w0 = make_win(v, 0, 1);
     int mx = 0;
     for (int lvl = 0; lvl < 2; ++lvl)
@@ -227,42 +201,55 @@ int gem_prepare(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b,
     const int64_t npix = (int64_t)v->H * v->W;
     // ~4 pixels per thread: enough blocks to fill the chip, few partial records
     L.pose_blocks = (int)std::min<int64_t>(std::max<int64_t>(1, (npix + 2 * VD_BLOCK - 1) / (2 * VD_BLOCK)), 2048);
-    const int fin_blocks = (int)((npix + VD_BLOCK - 1) / VD_BLOCK);
-    const size_t ll_bytes = align_up(sizeof(double) * mx);
-    const size_t pp_bytes = align_up(sizeof(double) * 29 * (size_t)L.pose_blocks * n_cand);
-    const size_t fin_bytes = align_up(sizeof(double) * 5 * (size_t)fin_blocks);
-    const size_t red_bytes = std::max(pp_bytes, fin_bytes);
-    const size_t lat = (size_t)w0.hc * w0.wc;
-    const size_t pa_bytes = align_up(sizeof(float) * lat);
-    const size_t f2_bytes = align_up(sizeof(float4) * (size_t)npix * v->N);
     // pose step: one block per 1024 pixels keeps the per-block prologue cheap
     L.gn_blocks = (int)std::min<int64_t>(std::max<int64_t>(1, (npix + 4 * VD_BLOCK - 1) / (4 * VD_BLOCK)), 256);
+    const int fin_blocks = (int)((npix + VD_BLOCK - 1) / VD_BLOCK);
+    L.sz.head = align_up((VD_NMAX + VD_PMAX) * sizeof(vd::PoseF)) + align_up(VD_NMAX * sizeof(vd::PoseD));
+    L.sz.ll = align_up(sizeof(double) * mx);
+    const size_t pp_bytes = align_up(sizeof(double) * 29 * (size_t)L.pose_blocks * n_cand);
+    const size_t fin_bytes = align_up(sizeof(double) * 5 * (size_t)fin_blocks);
     const size_t gnp_bytes = align_up(sizeof(double) * 29 * 2 * (size_t)L.gn_blocks);
-    const size_t hist_bytes = align_up(sizeof(vd::PoseD) * (size_t)v->N * std::max(1, v->pose_gn_steps));
-    const size_t obs_bytes = align_up(sizeof(float2) * (size_t)npix);
-    const size_t red2_bytes = std::max(red_bytes, gnp_bytes);
-    int rc = ensure_scratch(ctx, f2_bytes + hist_bytes + obs_bytes + ll_bytes + red2_bytes + (3 + VD_SPEC) * pa_bytes,
-                            st, L.s);
+    L.sz.red = std::max(std::max(pp_bytes, fin_bytes), gnp_bytes);
+    L.sz.pa = align_up(sizeof(float) * (size_t)w0.hc * w0.wc);
+    L.sz.f2 = align_up(sizeof(float4) * (size_t)npix * v->N);
+    L.sz.hist = align_up(sizeof(vd::PoseD) * (size_t)v->N * std::max(1, v->pose_gn_steps));
+    L.sz.obs = align_up(sizeof(float2) * (size_t)npix);
+    return L.sz.head + L.sz.f2 + L.sz.hist + L.sz.obs + L.sz.ll + L.sz.red + (3 + VD_SPEC) * L.sz.pa;
+}
+
+// Points L's scratch arrays into the region at base (sized by gem_layout).
+void gem_carve(char* base, GemLaunch& L) {
+    L.s.poses = (vd::PoseF*)base;
+    L.s.posed = (vd::PoseD*)(base + align_up((VD_NMAX + VD_PMAX) * sizeof(vd::PoseF)));
+    char* p = base + L.sz.head;
+    L.s.a = p;
+    L.flow2 = (float4*)p;
+    p += L.sz.f2;
+    L.hist = (vd::PoseD*)p;
+    p += L.sz.hist;
+    L.obs = (float2*)p;
+    p += L.sz.obs;
+    L.ll_partial = (double*)p;
+    p += L.sz.ll;
+    L.pose_partials = (double*)p;
+    p += L.sz.red;
+    L.pa_E = (float*)p;
+    L.pa_V = (float*)(p + L.sz.pa);
+    L.pa_S = (int*)(p + 2 * L.sz.pa);
+    L.pa_spec = (float*)(p + 3 * L.sz.pa);
+}
+
+int gem_prepare(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, hipStream_t st, GemLaunch& L,
+                int n_cand = 1) {
+    L.ctx = ctx; L.v = v; L.b = b; L.st = st;
+    const size_t bytes = gem_layout(v, n_cand, L);
+    int rc = vdc::ensure_buffer(ctx, &ctx->scratch, &ctx->scratch_bytes, bytes, st);
     if (rc) return rc;
-    L.flow2 = (float4*)L.s.a;
-    L.hist = (vd::PoseD*)(L.s.a + f2_bytes);
-    L.obs = (float2*)(L.s.a + f2_bytes + hist_bytes);
-    char* q = L.s.a + f2_bytes + hist_bytes + obs_bytes;
-    L.ll_partial = (double*)q;
-    L.pose_partials = (double*)(q + ll_bytes);
-    L.pa_E = (float*)(q + ll_bytes + red2_bytes);
-    L.pa_V = (float*)(q + ll_bytes + red2_bytes + pa_bytes);
-    L.pa_S = (int*)(q + ll_bytes + red2_bytes + 2 * pa_bytes);
-    L.pa_spec = (float*)(q + ll_bytes + red2_bytes + 3 * pa_bytes);
+    gem_carve((char*)ctx->scratch, L);
     return VOLDOR_OK;
 }
 
-int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll) {
-    voldor_ctx ctx = L.ctx;
-    const vd::Win w = make_win(L.v, it, level, L.b);
-    const vd::LevelGeom g = make_geom(L.v, w, level, it);
-    const size_t lds = vd::level_lds_bytes(g);
-    if (lds > kLevelLdsMax) return fail(ctx, VOLDOR_EINVAL, "chain segment too long for LDS (%zu bytes)", lds);
+vd::LevelBufs level_bufs(const GemLaunch& L, int level, bool want_ll) {
     vd::LevelBufs B;
     B.P = L.s.poses;
     B.flow = (const float2*)L.b->flow;
@@ -280,6 +267,48 @@ int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll)
     B.pa_V = L.pa_V;
     B.pa_S = L.pa_S;
     B.pa_spec = L.pa_spec;
+    return B;
+}
+
+vd::PoseBufs pose_bufs(const GemLaunch& L) {
+    vd::PoseBufs B;
+    B.P = L.s.poses;
+    B.PD = L.s.posed;
+    B.flow = (const float2*)L.b->flow;
+    B.flow2 = L.flow2;
+    B.idepth = L.b->idepth;
+    B.rigid = L.b->rigid;
+    B.pose = L.b->pose;
+    B.partials = L.pose_partials;
+    B.out = nullptr;
+    B.hist = L.hist;
+    B.obs = L.obs;
+    return B;
+}
+
+vd::FinalBufs final_bufs(const GemLaunch& L) {
+    vd::FinalBufs B;
+    B.P = L.s.poses;
+    B.flow = (const float2*)L.b->flow;
+    B.flow2 = L.flow2;
+    B.idepth = L.b->idepth;
+    B.rigid = L.b->rigid;
+    B.prior = L.b->prior_idepth;
+    B.prior_weight = L.b->prior_weight;
+    B.conf = L.b->conf;
+    B.stats = L.b->stats;
+    B.partials = L.pose_partials;
+    B.ll_partial = L.ll_partial;
+    return B;
+}
+
+int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll) {
+    voldor_ctx ctx = L.ctx;
+    const vd::Win w = make_win(L.v, it, level, L.b);
+    const vd::LevelGeom g = make_geom(L.v, w, level, it);
+    const size_t lds = vd::level_lds_bytes(g);
+    if (lds > kLevelLdsMax) return fail(ctx, VOLDOR_EINVAL, "chain segment too long for LDS (%zu bytes)", lds);
+    const vd::LevelBufs B = level_bufs(L, level, want_ll);
     hipEvent_t t0 = nullptr;
     const int timer = level == VOLDOR_LEVEL_COARSE ? VOLDOR_TIMER_COARSE : VOLDOR_TIMER_LOCAL;
     const bool timed = level == VOLDOR_LEVEL_COARSE || (do_e && do_m);
@@ -301,18 +330,7 @@ int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll)
 int run_pose_step(GemLaunch& L) {
     voldor_ctx ctx = L.ctx;
     vd::Win w = make_win(L.v, 0, 1);
-    vd::PoseBufs B;
-    B.P = L.s.poses;
-    B.PD = L.s.posed;
-    B.flow = (const float2*)L.b->flow;
-    B.flow2 = L.flow2;
-    B.idepth = L.b->idepth;
-    B.rigid = L.b->rigid;
-    B.pose = L.b->pose;
-    B.partials = L.pose_partials;
-    B.out = nullptr;
-    B.hist = L.hist;
-    B.obs = L.obs;
+    const vd::PoseBufs B = pose_bufs(L);
     const int G = L.v->pose_gn_steps;
     if (G == 0) return VOLDOR_OK;
     hipEvent_t t0 = nullptr;
@@ -343,18 +361,7 @@ int run_finalize(GemLaunch& L, int iter) {
     if ((rc = run_level(L, iter, VOLDOR_LEVEL_LOCAL, 1, 0, true))) return rc;
     const vd::Win w = make_win(L.v, iter, 1, L.b);
     const vd::LevelGeom g = make_geom(L.v, w, 1, iter);
-    vd::FinalBufs B;
-    B.P = L.s.poses;
-    B.flow = (const float2*)L.b->flow;
-    B.flow2 = L.flow2;
-    B.idepth = L.b->idepth;
-    B.rigid = L.b->rigid;
-    B.prior = L.b->prior_idepth;
-    B.prior_weight = L.b->prior_weight;
-    B.conf = L.b->conf;
-    B.stats = L.b->stats;
-    B.partials = L.pose_partials;
-    B.ll_partial = L.ll_partial;
+    const vd::FinalBufs B = final_bufs(L);
     VD_CHECK(vd::launch_finalize(w, B, g.nblocks, L.st), "finalize launch");
     return VOLDOR_OK;
 }
@@ -369,15 +376,256 @@ int run_iteration(GemLaunch& L, int it, bool layout) {
     return run_pose_step(L);
 }
 
-// A whole window on a prepared launch.
-int run_window(GemLaunch& L, int n_iters, int flags) {
+// A whole window on a prepared launch: iterations first .. first + n_iters - 1.
+int run_window(GemLaunch& L, int first, int n_iters, int flags) {
     voldor_ctx ctx = L.ctx;
     int rc;
     if (flags & VOLDOR_RUN_INIT) VD_CHECK(vd::launch_init(make_win(L.v, 0, 1), L.b->idepth, L.st), "init launch");
-    for (int it = 0; it < n_iters; ++it)
-        if ((rc = run_iteration(L, it, it == 0))) return rc;
+    for (int it = first; it < first + n_iters; ++it)
+        if ((rc = run_iteration(L, it, it == first))) return rc;
     if ((rc = prep_poses(L, false))) return rc;
-    return run_finalize(L, n_iters - 1);
+    return run_finalize(L, first + n_iters - 1);
+}
+
+// ---- batched run: every window's scratch lives at once; each step of the launch sequence
+// is one launch per (shape class) over all windows, driven by item tables in device memory
+
+enum BKind { BK_PREP, BK_SETUP, BK_LEVEL, BK_POSE, BK_POSE_FINISH, BK_FINAL, BK_FINAL_FINISH };
+
+struct BLaunch {
+    int kind;
+    size_t items, b2i;         // byte offsets into the table region
+    int n_items, nblocks;
+    size_t lds;
+    int mode, s;
+    bool b2, pr;
+};
+
+struct BPlan {
+    std::vector<char> host;
+    std::vector<BLaunch> launches;
+    template <class T>
+    size_t put(const std::vector<T>& v) {
+        const size_t off = align_up(host.size());
+        host.resize(off + v.size() * sizeof(T));
+        if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
+    void add(int kind, size_t items, size_t b2i, int n_items, int nblocks, size_t lds = 0, int mode = 0, int s = 0,
+             bool b2 = true, bool pr = false) {
+        launches.push_back(BLaunch{kind, items, b2i, n_items, nblocks, lds, mode, s, b2, pr});
+    }
+};
+
+struct BWin {
+    GemLaunch L;
+    bool b2, pr;
+};
+
+// block -> item table of a launch whose items have the given block counts
+std::vector<int> blocks_to_items(const std::vector<int>& counts, std::vector<int>& begins) {
+    std::vector<int> b2i;
+    begins.clear();
+    for (size_t i = 0; i < counts.size(); ++i) {
+        begins.push_back((int)b2i.size());
+        b2i.insert(b2i.end(), (size_t)counts[i], (int)i);
+    }
+    return b2i;
+}
+
+// one level launch per shape class over the windows; geometry per window from make(L)
+template <class MakeItem>
+void plan_level(BPlan& P, const std::vector<BWin>& W, int mode, MakeItem make) {
+    for (int cls = 0; cls < 4; ++cls) {
+        const bool b2 = cls & 1, pr = cls & 2;
+        std::vector<vd::LevelItem> items;
+        std::vector<int> counts;
+        size_t lds = 0;
+        for (const BWin& bw : W) {
+            if (bw.b2 != b2 || bw.pr != pr) continue;
+            vd::LevelItem it = make(bw.L);
+            int nb = it.g.nblocks;
+            const size_t lat = (size_t)it.g.h * it.g.w;
+            if (mode == 1) nb = (int)((lat * 4 + VD_BLOCK - 1) / VD_BLOCK);
+            if (mode == 2) nb = (int)((lat * it.g.spec + VD_BLOCK - 1) / VD_BLOCK);
+            if (mode == 0) lds = std::max(lds, vd::level_lds_bytes(it.g));
+            items.push_back(it);
+            counts.push_back(nb);
+        }
+        if (items.empty()) continue;
+        std::vector<int> begins;
+        const std::vector<int> b2i = blocks_to_items(counts, begins);
+        for (size_t i = 0; i < items.size(); ++i) items[i].begin = begins[i];
+        const size_t io = P.put(items), bo = P.put(b2i);
+        P.add(BK_LEVEL, io, bo, (int)items.size(), (int)b2i.size(), lds, mode, 0, b2, pr);
+    }
+}
+
+int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPlan& P) {
+    // setup: initial depth (when asked) and the flow layout, once per window
+    {
+        std::vector<vd::PrepItem> items;
+        std::vector<int> counts;
+        for (BWin& bw : W) {
+            const GemLaunch& L = bw.L;
+            vd::PrepItem it;
+            std::memset(&it, 0, sizeof(it));
+            it.w = make_win(L.v, 0, 1);
+            it.idepth = L.b->idepth;
+            it.flow = (const float2*)L.b->flow;
+            it.flow2 = L.flow2;
+            it.N = L.v->N;
+            it.init = (flags & VOLDOR_RUN_INIT) ? 1 : 0;
+            const int64_t npix = (int64_t)L.v->H * L.v->W;
+            const int64_t pairs = (int64_t)(L.v->H - 1) * L.v->W * (L.v->N - 1);
+            it.nblocks = (int)((std::max(npix, pairs) + VD_BLOCK - 1) / VD_BLOCK);
+            items.push_back(it);
+            counts.push_back(std::max(1, it.nblocks));
+        }
+        std::vector<int> begins;
+        const std::vector<int> b2i = blocks_to_items(counts, begins);
+        for (size_t i = 0; i < items.size(); ++i) items[i].begin = begins[i];
+        const size_t io = P.put(items), bo = P.put(b2i);
+        P.add(BK_SETUP, io, bo, (int)items.size(), (int)b2i.size());
+    }
+    std::vector<vd::PrepItem> prep;
+    for (BWin& bw : W) {
+        const GemLaunch& L = bw.L;
+        vd::PrepItem it;
+        std::memset(&it, 0, sizeof(it));
+        it.pose = L.b->pose;
+        it.prior_pose = L.b->prior_pose;
+        it.N = L.v->N;
+        it.P = L.v->P;
+        it.out = L.s.poses;
+        it.outd = L.s.posed;
+        prep.push_back(it);
+    }
+    const size_t prep_off = P.put(prep);
+    int maxS = 0;
+    for (BWin& bw : W) maxS = std::max(maxS, bw.L.v->N * bw.L.v->pose_gn_steps);
+    for (int it = 0; it < n_iters; ++it) {
+        P.add(BK_PREP, prep_off, 0, (int)W.size(), (int)W.size());
+        auto item = [&](const GemLaunch& L, int level, int do_e, int do_m, bool want_ll) {
+            vd::LevelItem x;
+            std::memset(&x, 0, sizeof(x));
+            x.w = make_win(L.v, it, level, L.b);
+            x.g = make_geom(L.v, x.w, level, it);
+            x.b = level_bufs(L, level, want_ll);
+            x.do_e = do_e;
+            x.do_m = do_m;
+            return x;
+        };
+        plan_level(P, W, 0, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 1, 0, false); });
+        plan_level(P, W, 1, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 0, 1, false); });
+        plan_level(P, W, 2, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 0, 1, false); });
+        plan_level(P, W, 0, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 0, 2, false); });
+        plan_level(P, W, 0, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_LOCAL, 1, 1, false); });
+        // pose step: Gauss-Newton step s of the windows that have one
+        std::vector<vd::PoseItem> all;
+        for (BWin& bw : W) {
+            const GemLaunch& L = bw.L;
+            vd::PoseItem x;
+            std::memset(&x, 0, sizeof(x));
+            x.w = make_win(L.v, 0, 1);
+            x.b = pose_bufs(L);
+            x.G = L.v->pose_gn_steps;
+            x.S = L.v->N * L.v->pose_gn_steps;
+            x.nblocks = L.gn_blocks;
+            all.push_back(x);
+        }
+        for (int s = 0; s < maxS; ++s) {
+            for (int b2 = 0; b2 < 2; ++b2) {
+                std::vector<vd::PoseItem> items;
+                std::vector<int> counts;
+                for (size_t i = 0; i < W.size(); ++i)
+                    if ((int)W[i].b2 == b2 && s < all[i].S) {
+                        items.push_back(all[i]);
+                        counts.push_back(all[i].nblocks);
+                    }
+                if (items.empty()) continue;
+                std::vector<int> begins;
+                const std::vector<int> b2i = blocks_to_items(counts, begins);
+                for (size_t i = 0; i < items.size(); ++i) items[i].begin = begins[i];
+                const size_t io = P.put(items), bo = P.put(b2i);
+                P.add(BK_POSE, io, bo, (int)items.size(), (int)b2i.size(), 0, 0, s, b2 != 0);
+            }
+        }
+        if (maxS > 0) P.add(BK_POSE_FINISH, P.put(all), 0, (int)all.size(), (int)all.size());
+    }
+    // final E-step, confidence and statistics
+    P.add(BK_PREP, prep_off, 0, (int)W.size(), (int)W.size());
+    const int last = n_iters - 1;
+    plan_level(P, W, 0, [&](const GemLaunch& L) {
+        vd::LevelItem x;
+        std::memset(&x, 0, sizeof(x));
+        x.w = make_win(L.v, last, VOLDOR_LEVEL_LOCAL, L.b);
+        x.g = make_geom(L.v, x.w, VOLDOR_LEVEL_LOCAL, last);
+        x.b = level_bufs(L, VOLDOR_LEVEL_LOCAL, true);
+        x.do_e = 1;
+        x.do_m = 0;
+        return x;
+    });
+    std::vector<vd::FinalItem> fin_all;
+    for (BWin& bw : W) {
+        const GemLaunch& L = bw.L;
+        vd::FinalItem x;
+        std::memset(&x, 0, sizeof(x));
+        x.w = make_win(L.v, last, VOLDOR_LEVEL_LOCAL, L.b);
+        x.b = final_bufs(L);
+        x.n_ll = make_geom(L.v, x.w, VOLDOR_LEVEL_LOCAL, last).nblocks;
+        x.nblocks = (int)(((int64_t)L.v->H * L.v->W + VD_BLOCK - 1) / VD_BLOCK);
+        fin_all.push_back(x);
+    }
+    for (int cls = 0; cls < 4; ++cls) {
+        const bool b2 = cls & 1, pr = cls & 2;
+        std::vector<vd::FinalItem> items;
+        std::vector<int> counts;
+        for (size_t i = 0; i < W.size(); ++i)
+            if (W[i].b2 == b2 && W[i].pr == pr) {
+                items.push_back(fin_all[i]);
+                counts.push_back(fin_all[i].nblocks);
+            }
+        if (items.empty()) continue;
+        std::vector<int> begins;
+        const std::vector<int> b2i = blocks_to_items(counts, begins);
+        for (size_t i = 0; i < items.size(); ++i) items[i].begin = begins[i];
+        const size_t io = P.put(items), bo = P.put(b2i);
+        P.add(BK_FINAL, io, bo, (int)items.size(), (int)b2i.size(), 0, 0, 0, b2, pr);
+    }
+    P.add(BK_FINAL_FINISH, P.put(fin_all), 0, (int)fin_all.size(), (int)fin_all.size());
+    for (const BLaunch& l : P.launches)
+        if (l.lds > kLevelLdsMax) return fail(ctx, VOLDOR_EINVAL, "chain segment too long for LDS (%zu bytes)", l.lds);
+    return VOLDOR_OK;
+}
+
+int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st) {
+    for (const BLaunch& l : P.launches) {
+        const void* items = dev + l.items;
+        const int* b2i = (const int*)(dev + l.b2i);
+        hipError_t e = hipSuccess;
+        switch (l.kind) {
+        case BK_PREP: e = vd::launch_prep_batch((const vd::PrepItem*)items, l.n_items, st); break;
+        case BK_SETUP: e = vd::launch_setup_batch((const vd::PrepItem*)items, b2i, l.nblocks, st); break;
+        case BK_LEVEL:
+            e = vd::launch_level_batch((const vd::LevelItem*)items, b2i, l.nblocks, l.lds, l.mode, l.b2, l.pr, st);
+            break;
+        case BK_POSE: e = vd::launch_pose_gn_batch((const vd::PoseItem*)items, b2i, l.nblocks, l.s, l.b2, st); break;
+        case BK_POSE_FINISH: e = vd::launch_pose_gn_finish_batch((const vd::PoseItem*)items, l.n_items, st); break;
+        case BK_FINAL: e = vd::launch_finalize_batch((const vd::FinalItem*)items, b2i, l.nblocks, l.b2, l.pr, st); break;
+        case BK_FINAL_FINISH: e = vd::launch_finalize_finish_batch((const vd::FinalItem*)items, l.n_items, st); break;
+        }
+        VD_CHECK(e, "batched launch");
+    }
+    return VOLDOR_OK;
+}
+
+void drop_graph(voldor_ctx ctx) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->batch_key.clear();
 }
 
 }  // namespace
@@ -457,6 +705,10 @@ void voldor_ctx_destroy(voldor_ctx ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->net_ws) (void)hipFree(ctx->net_ws);
+    drop_graph(ctx);
+    if (ctx->batch_ws) (void)hipFree(ctx->batch_ws);
+    if (ctx->batch_tab) (void)hipFree(ctx->batch_tab);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     timers_discard(ctx);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -583,9 +835,19 @@ int voldor_finalize(voldor_ctx ctx, const voldor_window* v, const voldor_buffers
     return run_finalize(L, iter);
 }
 
-int voldor_run(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int n_iters, int flags,
-               void* stream) {
-    return voldor_batch_run(ctx, 1, v, b, n_iters, flags, stream);
+int voldor_run(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int first_iter, int n_iters,
+               int flags, void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    if (!b->conf || !b->stats) return fail(ctx, VOLDOR_EINVAL, "null conf/stats pointer");
+    if (n_iters < 1 || first_iter < 0 || (int64_t)first_iter + n_iters > 0xffffff)
+        return fail(ctx, VOLDOR_EINVAL, "need n_iters >= 1 and first_iter >= 0");
+    if (flags & ~VOLDOR_RUN_INIT) return fail(ctx, VOLDOR_EINVAL, "unknown flags 0x%x", flags);
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    GemLaunch L;
+    if ((rc = gem_prepare(ctx, v, b, st, L))) return rc;
+    return run_window(L, first_iter, n_iters, flags);
 }
 
 int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, const voldor_buffers* bufs,
@@ -594,7 +856,7 @@ int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, c
     if (n_windows < 1 || n_windows > (int)kMaxBatch || !wins || !bufs)
         return fail(ctx, VOLDOR_EINVAL, "bad window batch");
     if (n_iters < 1 || n_iters > 0xffffff) return fail(ctx, VOLDOR_EINVAL, "n_iters must be >= 1");
-    if (flags & ~VOLDOR_RUN_INIT) return fail(ctx, VOLDOR_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(VOLDOR_RUN_INIT | VOLDOR_RUN_NO_GRAPH)) return fail(ctx, VOLDOR_EINVAL, "unknown flags 0x%x", flags);
     int rc;
     for (int i = 0; i < n_windows; ++i) {
         if ((rc = check_window(ctx, &wins[i], &bufs[i]))) return rc;
@@ -602,14 +864,59 @@ int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, c
     }
     hipStream_t st = (hipStream_t)stream;
     VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
-    // size the scratch for the largest window before the first launch
-    GemLaunch L;
-    for (int i = 0; i < n_windows; ++i)
-        if ((rc = gem_prepare(ctx, &wins[i], &bufs[i], st, L))) return rc;
-    for (int i = 0; i < n_windows; ++i) {
-        if ((rc = gem_prepare(ctx, &wins[i], &bufs[i], st, L))) return rc;
-        if ((rc = run_window(L, n_iters, flags))) return rc;
+    const bool use_graph = !(flags & VOLDOR_RUN_NO_GRAPH);
+    // the same windows, buffers and settings as the captured graph: replay it
+    std::vector<char> key(sizeof(int) * 2 + n_windows * (sizeof(voldor_window) + sizeof(voldor_buffers)));
+    {
+        char* k = key.data();
+        const int hdr[2] = {n_iters, flags & VOLDOR_RUN_INIT};
+        std::memcpy(k, hdr, sizeof(hdr));
+        std::memcpy(k + sizeof(hdr), wins, n_windows * sizeof(voldor_window));
+        std::memcpy(k + sizeof(hdr) + n_windows * sizeof(voldor_window), bufs, n_windows * sizeof(voldor_buffers));
     }
+    if (use_graph && ctx->graph_exec && key == ctx->batch_key) {
+        VD_CHECK(hipGraphLaunch(ctx->graph_exec, st), "hipGraphLaunch");
+        return VOLDOR_OK;
+    }
+    // layout: every window's scratch, then the item tables
+    std::vector<BWin> W((size_t)n_windows);
+    size_t total = 0;
+    std::vector<size_t> offs((size_t)n_windows);
+    for (int i = 0; i < n_windows; ++i) {
+        GemLaunch& L = W[i].L;
+        L.ctx = ctx; L.v = &wins[i]; L.b = &bufs[i]; L.st = st;
+        offs[i] = total;
+        total += align_up(gem_layout(&wins[i], 1, L));
+        W[i].b2 = wins[i].fisk_beta == 2.0f;
+        W[i].pr = wins[i].P > 0;
+    }
+    // a new set of windows: the old graph goes before its buffers may be replaced
+    drop_graph(ctx);
+    if ((rc = vdc::ensure_buffer(ctx, &ctx->batch_ws, &ctx->batch_ws_bytes, total, st))) return rc;
+    for (int i = 0; i < n_windows; ++i) gem_carve((char*)ctx->batch_ws + offs[i], W[i].L);
+    BPlan plan;
+    if ((rc = build_plan(ctx, W, n_iters, flags, plan))) return rc;
+    if ((rc = vdc::ensure_buffer(ctx, &ctx->batch_tab, &ctx->batch_tab_bytes, plan.host.size(), st))) return rc;
+    char* tables = (char*)ctx->batch_tab;
+    ctx->batch_host = plan.host;
+    VD_CHECK(hipMemcpyAsync(tables, ctx->batch_host.data(), ctx->batch_host.size(), hipMemcpyHostToDevice, st),
+             "table upload");
+    VD_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (!use_graph) return enqueue_plan(ctx, plan, tables, st);
+    if (!ctx->cap_stream) VD_CHECK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "stream create");
+    VD_CHECK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed), "begin capture");
+    rc = enqueue_plan(ctx, plan, tables, ctx->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    VD_CHECK(ec, "end capture");
+    ctx->graph = g;
+    VD_CHECK(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0), "graph instantiate");
+    ctx->batch_key = key;
+    VD_CHECK(hipGraphLaunch(ctx->graph_exec, st), "hipGraphLaunch");
     return VOLDOR_OK;
 }
 
@@ -663,9 +970,9 @@ int voldor_align_p2p(voldor_ctx ctx, const voldor_align_params* ap, int n_pairs,
     const int nblk = (int)std::min<size_t>(std::max<size_t>(1, (plane + VD_BLOCK * 4 - 1) / (VD_BLOCK * 4)), 512);
     const size_t nrm_bytes = align_up(sizeof(float4) * plane * n_pairs);
     const size_t part_bytes = align_up(sizeof(double) * 29 * nblk * (size_t)n_pairs);
-    Scratch s;
-    int rc = ensure_scratch(ctx, nrm_bytes + part_bytes, st, s);
+    int rc = vdc::ensure_buffer(ctx, &ctx->scratch, &ctx->scratch_bytes, nrm_bytes + part_bytes, st);
     if (rc) return rc;
+    char* base = (char*)ctx->scratch;
     vd::AlignArgs a;
     a.H = ap->H; a.W = ap->W;
     a.fx = ap->fx; a.fy = ap->fy; a.cx = ap->cx; a.cy = ap->cy;
@@ -675,8 +982,8 @@ int voldor_align_p2p(voldor_ctx ctx, const voldor_align_params* ap, int n_pairs,
     a.n_pairs = n_pairs;
     vd::AlignBufs B;
     B.idepth1 = idepth1; B.idepth2 = idepth2; B.conf2 = conf2;
-    B.normals = (float4*)s.a;
-    B.partials = (double*)(s.a + nrm_bytes);
+    B.normals = (float4*)base;
+    B.partials = (double*)(base + nrm_bytes);
     B.pose = pose_inout; B.cov = cov_out; B.stats = stats_out; B.status = status_out;
     VD_CHECK(vd::launch_align_prepare(a, B, st), "align prepare launch");
     for (int k = 0; k < ap->gn_steps; ++k) VD_CHECK(vd::launch_align_step(a, B, 0, nblk, st), "align step launch");

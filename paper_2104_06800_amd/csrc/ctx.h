@@ -18,6 +18,15 @@ struct voldor_ctx_s {
     size_t scratch_bytes = 0;
     void* net_ws = nullptr;           // proposal-network workspace (activations, gradients)
     size_t net_ws_bytes = 0;
+    void* batch_ws = nullptr;         // batched run: every window's scratch
+    size_t batch_ws_bytes = 0;
+    void* batch_tab = nullptr;        // batched run: item tables of the launch sequence
+    size_t batch_tab_bytes = 0;
+    std::vector<char> batch_host;     // host copy of the item tables
+    std::vector<char> batch_key;      // windows / buffers / settings of the captured graph
+    hipStream_t cap_stream = nullptr; // capture stream (default priority, non-blocking)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
     int n_cu = 256;
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;                                   // idle events

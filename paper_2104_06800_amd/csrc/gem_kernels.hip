@@ -9,8 +9,8 @@ namespace vd {
 // ----------------------------------------------------------------------------------
 // pose conversion (FP64 6-vectors -> FP32 R|t for frames and priors)
 // ----------------------------------------------------------------------------------
-__global__ void k_pose_prep(const double* __restrict__ pose, int N, const double* __restrict__ prior_pose, int P,
-                            PoseF* __restrict__ out, PoseD* __restrict__ outd) {
+__device__ __forceinline__ void pose_prep_body(const double* __restrict__ pose, int N, const double* __restrict__ prior_pose,
+                                               int P, PoseF* __restrict__ out, PoseD* __restrict__ outd) {
     const int i = threadIdx.x;
     if (i < N) {
         pose_to_f(pose + 6 * i, out + i);
@@ -20,29 +20,44 @@ __global__ void k_pose_prep(const double* __restrict__ pose, int N, const double
     }
 }
 
+__global__ void k_pose_prep(const double* __restrict__ pose, int N, const double* __restrict__ prior_pose, int P,
+                            PoseF* __restrict__ out, PoseD* __restrict__ outd) {
+    pose_prep_body(pose, N, prior_pose, P, out, outd);
+}
+
 // ----------------------------------------------------------------------------------
 // random initial inverse depth
 // ----------------------------------------------------------------------------------
-__global__ void k_init_idepth(Win w, float* __restrict__ idepth) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void init_body(const Win& w, float* __restrict__ idepth, int blk) {
+    const int j = blk * VD_BLOCK + threadIdx.x;
     if (j >= w.H * w.W) return;
     const uint4 r = philox10(make_uint4((uint32_t)j, 0u, philox_word2(0, 1, PURPOSE_INIT), w.window_id),
                              w.key0, w.key1);
     idepth[j] = fmaf(unit24(r.x), w.rmax - w.rmin, w.rmin);
 }
 
+__global__ void __launch_bounds__(VD_BLOCK) k_init_idepth(Win w, float* __restrict__ idepth) {
+    init_body(w, idepth, blockIdx.x);
+}
+
 // ----------------------------------------------------------------------------------
 // row-pair flow layout for the bilinear samples of frames t >= 2:
 // F2[t][y][x] = (X_t(x, y), X_t(x, y + 1)), y <= H - 2
 // ----------------------------------------------------------------------------------
-__global__ void k_flow_pairs(const float2* __restrict__ flow, float4* __restrict__ f2, int N, int H, int W) {
+__device__ __forceinline__ void flow_pairs_body(const float2* __restrict__ flow, float4* __restrict__ f2, int N, int H,
+                                                int W, int blk) {
     const size_t per = (size_t)(H - 1) * W;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t i = (size_t)blk * VD_BLOCK + threadIdx.x;
     if (i >= per * (N - 1)) return;
     const size_t t = 1 + i / per, r = i - (t - 1) * per;
     const size_t o = t * (size_t)H * W + r;
     const float2 a = flow[o], b = flow[o + W];
     f2[o] = make_float4(a.x, a.y, b.x, b.y);
+}
+
+__global__ void __launch_bounds__(VD_BLOCK) k_flow_pairs(const float2* __restrict__ flow, float4* __restrict__ f2, int N,
+                                                         int H, int W) {
+    flow_pairs_body(flow, f2, N, H, W, blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------------
@@ -67,9 +82,8 @@ struct BlockPix {
     bool valid;
 };
 
-__device__ __forceinline__ BlockPix block_pix(const LevelGeom& g, int k) {
+__device__ __forceinline__ BlockPix block_pix(const LevelGeom& g, int b, int k) {
     BlockPix p;
-    const int b = xcd_block(blockIdx.x, gridDim.x);
     const int sidx = b % g.nseg, lb = b / g.nseg;
     int c, i;
     if (g.horizontal) { c = k / g.seg; i = k - c * g.seg; }
@@ -86,8 +100,7 @@ __device__ __forceinline__ BlockPix block_pix(const LevelGeom& g, int k) {
 }
 
 // number of valid nodes of chain c of this block
-__device__ __forceinline__ int chain_len(const LevelGeom& g, int c) {
-    const int b = xcd_block(blockIdx.x, gridDim.x);
+__device__ __forceinline__ int chain_len(const LevelGeom& g, int b, int c) {
     const int sidx = b % g.nseg, lb = b / g.nseg;
     const int line = lb * g.C + c;
     const int nlines = g.horizontal ? g.h : g.w;
@@ -97,9 +110,8 @@ __device__ __forceinline__ int chain_len(const LevelGeom& g, int c) {
 }
 
 template <bool B2, bool PR>
-__global__ void __launch_bounds__(VD_BLOCK)
-k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
-    extern __shared__ float lds[];
+__device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, const LevelBufs& B, int do_e, int do_m,
+                                           int blk, float* lds) {
     const int stride = g.seg + 1;
     const int nodes = g.C * stride;
     float* q_s = lds;                       // [N][C][stride] emission ratios -> alpha -> q
@@ -121,7 +133,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     // -------------------------------- E-step ------------------------------------
     if (do_e) {
         for (int k = tid; k < npix; k += VD_BLOCK) {
-            const BlockPix p = block_pix(g, k);
+            const BlockPix p = block_pix(g, blk, k);
             if (!p.valid) continue;
             Pix c;
             pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, c);
@@ -166,7 +178,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
         __syncthreads();
         if (w.chain_axis == 0 && tid < g.C * w.N) {
             const int c = tid % g.C, t = tid / g.C;
-            const int L = chain_len(g, c);
+            const int L = chain_len(g, blk, c);
             if (L > 0) {
                 const float* r = r_s + t * nodes + c * stride;
                 float* a = q_s + t * nodes + c * stride;
@@ -199,7 +211,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
         __syncthreads();
         // posteriors out (coalesced along the level grid rows)
         for (int k = tid; k < npix; k += VD_BLOCK) {
-            const BlockPix p = block_pix(g, k);
+            const BlockPix p = block_pix(g, blk, k);
             if (!p.valid) continue;
             const int o = p.c * stride + p.i;
             for (int t = 0; t < w.N; ++t) B.q_out[t * lplane + p.li] = q_s[t * nodes + o];
@@ -212,7 +224,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
             if (tid == 0) {
                 double s = 0.0;
                 for (int i = 0; i < VD_BLOCK / 64; ++i) s += ll_red[i];
-                B.ll_partial[blockIdx.x] = s;
+                B.ll_partial[blk] = s;
             }
         }
     }
@@ -221,7 +233,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     // -------------------------------- M-step ------------------------------------
     if (!do_e) {
         for (int k = tid; k < npix; k += VD_BLOCK) {
-            const BlockPix p = block_pix(g, k);
+            const BlockPix p = block_pix(g, blk, k);
             if (!p.valid) continue;
             const int o = p.c * stride + p.i;
             for (int t = 0; t < w.N; ++t) q_s[t * nodes + o] = B.q_in[t * lplane + p.li];
@@ -235,7 +247,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     // phase A: parallel over pixels and slots {0, 2, 3..K-1} (or precomputed by k_phase_a)
     if (do_m == 2) {
         for (int k = tid; k < npix; k += VD_BLOCK) {
-            const BlockPix p = block_pix(g, k);
+            const BlockPix p = block_pix(g, blk, k);
             if (!p.valid) continue;
             const int o = p.c * stride + p.i;
             bestE[o] = B.pa_E[p.li];
@@ -246,7 +258,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
         }
     }
     for (int k = tid; k < npix && do_m == 1; k += VD_BLOCK) {
-        const BlockPix p = block_pix(g, k);
+        const BlockPix p = block_pix(g, blk, k);
         if (!p.valid) continue;
         const int o = p.c * stride + p.i;
         Pix c;
@@ -288,9 +300,9 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     const bool fwd = (w.dir < 2);
     const int di = fwd ? 1 : -1;
     for (int k = tid; k < npix && do_m == 1; k += VD_BLOCK) {
-        const BlockPix p = block_pix(g, k);
+        const BlockPix p = block_pix(g, blk, k);
         if (!p.valid) continue;
-        const int L = chain_len(g, p.c);
+        const int L = chain_len(g, blk, p.c);
         const int o = p.c * stride + p.i;
         Pix c;
         pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, c);
@@ -309,7 +321,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     // phase B: serial scan per chain
     if (tid < g.C) {
         const int c = tid;
-        const int L = chain_len(g, c);
+        const int L = chain_len(g, blk, c);
         if (L > 0) {
             const int i0 = fwd ? 0 : L - 1;
             const int base = c * stride;
@@ -325,7 +337,7 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
                 } else {
                     // storage-order node i of chain c -> block linear index
                     const int kk = g.horizontal ? (c * g.seg + i) : (i * g.C + c);
-                    const BlockPix p = block_pix(g, kk);
+                    const BlockPix p = block_pix(g, blk, kk);
                     Pix cx;
                     pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, cx);
 #pragma unroll
@@ -342,10 +354,17 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     }
     __syncthreads();
     for (int k = tid; k < npix; k += VD_BLOCK) {
-        const BlockPix p = block_pix(g, k);
+        const BlockPix p = block_pix(g, blk, k);
         if (!p.valid) continue;
         B.rho_out[local ? (p.v * w.W + p.u) : p.li] = newV[p.c * stride + p.i];
     }
+}
+
+template <bool B2, bool PR>
+__global__ void __launch_bounds__(VD_BLOCK)
+k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
+    extern __shared__ float lds[];
+    level_body<B2, PR>(w, g, B, do_e, do_m, xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 // ----------------------------------------------------------------------------------
@@ -356,9 +375,8 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
 // slot): the result equals the argmin over all slots with ties to the lowest slot.
 // ----------------------------------------------------------------------------------
 template <bool B2, bool PR>
-__global__ void __launch_bounds__(VD_BLOCK)
-k_phase_a(Win w, LevelGeom g, LevelBufs B) {
-    const int gid = xcd_block(blockIdx.x, gridDim.x) * VD_BLOCK + threadIdx.x;
+__device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, const LevelBufs& B, int blk) {
+    const int gid = blk * VD_BLOCK + threadIdx.x;
     const int li = gid >> 2, lane = gid & 3;
     const size_t lplane = (size_t)g.h * g.w;
     const bool valid = li < (int)lplane;
@@ -415,15 +433,19 @@ k_phase_a(Win w, LevelGeom g, LevelBufs B) {
     }
 }
 
+template <bool B2, bool PR>
+__global__ void __launch_bounds__(VD_BLOCK) k_phase_a(Win w, LevelGeom g, LevelBufs B) {
+    phase_a_body<B2, PR>(w, g, B, xcd_block(blockIdx.x, gridDim.x));
+}
+
 // ----------------------------------------------------------------------------------
 // phase A2 as a separate grid (level with few long chains): one lane per (level pixel,
 // depth d), E_i at the phase-A winner of the node d + 1 steps back along the chain,
 // bounded (strict) by the pixel's phase-A energy.
 // ----------------------------------------------------------------------------------
 template <bool B2, bool PR>
-__global__ void __launch_bounds__(VD_BLOCK)
-k_phase_a2(Win w, LevelGeom g, LevelBufs B) {
-    const int gid = xcd_block(blockIdx.x, gridDim.x) * VD_BLOCK + threadIdx.x;
+__device__ __forceinline__ void phase_a2_body(const Win& w, const LevelGeom& g, const LevelBufs& B, int blk) {
+    const int gid = blk * VD_BLOCK + threadIdx.x;
     const int li = gid / g.spec, d = gid - li * g.spec;
     const size_t lplane = (size_t)g.h * g.w;
     if (li >= (int)lplane) return;
@@ -444,6 +466,11 @@ k_phase_a2(Win w, LevelGeom g, LevelBufs B) {
     prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, fpix, c, B.idepth[fpix]);
     B.pa_spec[d * lplane + li] =
         energy2_bounded<B2, PR, true>(w, B.P, B.flow2, B.prior, c, B.pa_V[lp], B.pa_E[li]);
+}
+
+template <bool B2, bool PR>
+__global__ void __launch_bounds__(VD_BLOCK) k_phase_a2(Win w, LevelGeom g, LevelBufs B) {
+    phase_a2_body<B2, PR>(w, g, B, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ----------------------------------------------------------------------------------
@@ -598,12 +625,10 @@ __device__ inline void pose_gn_solve(const double* red, PoseD& P) {
 }
 
 template <bool B2>
-__global__ void __launch_bounds__(VD_BLOCK)
-k_pose_gn(Win w, PoseBufs B, int s, int G) {
+__device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, int s, int G, int blk, unsigned nb) {
     __shared__ double red[(VD_BLOCK / 64) * 29];
     __shared__ PoseF curF, prevF;
     const int tid = threadIdx.x;
-    const unsigned nb = gridDim.x;
     const int t = s / G + 1, k = s - (t - 1) * G;
     if (s > 0) {
         reduce_partials<29>(B.partials + (size_t)((s - 1) & 1) * 29 * nb, nb, red);
@@ -613,7 +638,7 @@ k_pose_gn(Win w, PoseBufs B, int s, int G) {
             pose_gn_solve(red, P);
             PoseF F;
             posef_from_d(P, &F);
-            if (blockIdx.x == 0) B.hist[sp] = P;
+            if (blk == 0) B.hist[sp] = P;
             if (k == 0) { prevF = F; curF = B.P[t - 1]; }
             else curF = F;
         }
@@ -634,7 +659,7 @@ k_pose_gn(Win w, PoseBufs B, int s, int G) {
     for (int i = 0; i < 29; ++i) a32[i] = 0.f;
     const int stride = (int)nb * VD_BLOCK;
     constexpr int UB = 4;                  // pixels per thread and batch: loads issued together
-    for (int j0 = xcd_block(blockIdx.x, nb) * VD_BLOCK + tid; j0 < plane; j0 += UB * stride) {
+    for (int j0 = blk * VD_BLOCK + tid; j0 < plane; j0 += UB * stride) {
         float rho[UB], q[UB], ox[UB], oy[UB];
         int jj[UB];
 #pragma unroll
@@ -710,13 +735,17 @@ k_pose_gn(Win w, PoseBufs B, int s, int G) {
 #pragma unroll
     for (int i = 0; i < 29; ++i) acc[i] = (double)a32[i];
     block_reduce<29>(acc, red);
-    if (tid < 29) B.partials[((size_t)(s & 1) * 29 + tid) * nb + blockIdx.x] = red[tid] * (tid == 0 ? (double)VD_LN2 : 1.0);
+    if (tid < 29) B.partials[((size_t)(s & 1) * 29 + tid) * nb + blk] = red[tid] * (tid == 0 ? (double)VD_LN2 : 1.0);
+}
+
+template <bool B2>
+__global__ void __launch_bounds__(VD_BLOCK) k_pose_gn(Win w, PoseBufs B, int s, int G) {
+    pose_gn_body<B2>(w, B, s, G, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // Last step's solve, then every frame's final pose into the FP32 / FP64 copies and the
 // caller's 6-vectors.
-__global__ void __launch_bounds__(VD_BLOCK)
-k_pose_gn_finish(PoseBufs B, int N, int G, unsigned nb) {
+__device__ __forceinline__ void pose_gn_finish_body(const PoseBufs& B, int N, int G, unsigned nb) {
     __shared__ double red[(VD_BLOCK / 64) * 29];
     const int S = N * G;
     reduce_partials<29>(B.partials + (size_t)((S - 1) & 1) * 29 * nb, nb, red);
@@ -739,17 +768,20 @@ k_pose_gn_finish(PoseBufs B, int N, int G, unsigned nb) {
     }
 }
 
+__global__ void __launch_bounds__(VD_BLOCK) k_pose_gn_finish(PoseBufs B, int N, int G, unsigned nb) {
+    pose_gn_finish_body(B, N, G, nb);
+}
+
 // ----------------------------------------------------------------------------------
 // final confidence and statistics
 // ----------------------------------------------------------------------------------
 template <bool B2, bool PR>
-__global__ void __launch_bounds__(VD_BLOCK)
-k_finalize(Win w, FinalBufs B) {
+__device__ __forceinline__ void finalize_body(const Win& w, const FinalBufs& B, int blk, int nb) {
     __shared__ double red[(VD_BLOCK / 64) * 5];
     const int tid = threadIdx.x;
     const size_t plane = (size_t)w.H * w.W;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // energy, valid, invalid, prior terms, sum C
-    const int j = blockIdx.x * VD_BLOCK + tid;
+    const int j = blk * VD_BLOCK + tid;
     if (j < (int)plane) {
         const int v = j / w.W, u = j - v * w.W;
         Pix c;
@@ -773,11 +805,15 @@ k_finalize(Win w, FinalBufs B) {
         acc[4] = C;
     }
     block_reduce<5>(acc, red);
-    if (tid < 5) B.partials[(size_t)tid * gridDim.x + blockIdx.x] = red[tid];
+    if (tid < 5) B.partials[(size_t)tid * nb + blk] = red[tid];
 }
 
-__global__ void __launch_bounds__(VD_BLOCK)
-k_finalize_finish(FinalBufs B, unsigned nb, int n_ll) {
+template <bool B2, bool PR>
+__global__ void __launch_bounds__(VD_BLOCK) k_finalize(Win w, FinalBufs B) {
+    finalize_body<B2, PR>(w, B, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void finalize_finish_body(const FinalBufs& B, unsigned nb, int n_ll) {
     __shared__ double red[(VD_BLOCK / 64) * 5];
     reduce_partials<5>(B.partials, nb, red);
     const double s0 = red[0], s1 = red[1], s2 = red[2], s3 = red[3], s4 = red[4];
@@ -794,6 +830,70 @@ k_finalize_finish(FinalBufs B, unsigned nb, int n_ll) {
     }
 }
 
+__global__ void __launch_bounds__(VD_BLOCK) k_finalize_finish(FinalBufs B, unsigned nb, int n_ll) {
+    finalize_finish_body(B, nb, n_ll);
+}
+
+// ----------------------------------------------------------------------------------
+// batched kernels: one launch serves many windows
+// ----------------------------------------------------------------------------------
+// pose tables of every window: one block per window
+__global__ void k_prep_batch(const PrepItem* __restrict__ items) {
+    const PrepItem& it = items[blockIdx.x];
+    pose_prep_body(it.pose, it.N, it.prior_pose, it.P, it.out, it.outd);
+}
+
+// initial depth (when asked) and the row-pair flow layout of every window
+__global__ void __launch_bounds__(VD_BLOCK) k_setup_batch(const PrepItem* __restrict__ items,
+                                                          const int* __restrict__ blk2item) {
+    const int gb = xcd_block(blockIdx.x, gridDim.x);
+    const PrepItem& it = items[blk2item[gb]];
+    const int blk = gb - it.begin;
+    if (it.init) init_body(it.w, it.idepth, blk);
+    flow_pairs_body(it.flow, it.flow2, it.N, it.w.H, it.w.W, blk);
+}
+
+// mode 0: fused level pass (do_e / do_m of the item); 1: phase A; 2: phase A2
+template <bool B2, bool PR, int MODE>
+__global__ void __launch_bounds__(VD_BLOCK) k_level_batch(const LevelItem* __restrict__ items,
+                                                          const int* __restrict__ blk2item) {
+    extern __shared__ float lds[];
+    const int gb = xcd_block(blockIdx.x, gridDim.x);
+    const LevelItem& it = items[blk2item[gb]];
+    const int blk = gb - it.begin;
+    if (MODE == 0) level_body<B2, PR>(it.w, it.g, it.b, it.do_e, it.do_m, blk, lds);
+    else if (MODE == 1) phase_a_body<B2, PR>(it.w, it.g, it.b, blk);
+    else phase_a2_body<B2, PR>(it.w, it.g, it.b, blk);
+}
+
+// Gauss-Newton step s of every window that has one (windows with fewer steps idle)
+template <bool B2>
+__global__ void __launch_bounds__(VD_BLOCK) k_pose_gn_batch(const PoseItem* __restrict__ items,
+                                                            const int* __restrict__ blk2item, int s) {
+    const int gb = xcd_block(blockIdx.x, gridDim.x);
+    const PoseItem& it = items[blk2item[gb]];
+    if (s >= it.S) return;
+    pose_gn_body<B2>(it.w, it.b, s, it.G, gb - it.begin, (unsigned)it.nblocks);
+}
+
+__global__ void __launch_bounds__(VD_BLOCK) k_pose_gn_finish_batch(const PoseItem* __restrict__ items) {
+    const PoseItem& it = items[blockIdx.x];
+    if (it.S > 0) pose_gn_finish_body(it.b, it.w.N, it.G, (unsigned)it.nblocks);
+}
+
+template <bool B2, bool PR>
+__global__ void __launch_bounds__(VD_BLOCK) k_finalize_batch(const FinalItem* __restrict__ items,
+                                                             const int* __restrict__ blk2item) {
+    const int gb = xcd_block(blockIdx.x, gridDim.x);
+    const FinalItem& it = items[blk2item[gb]];
+    finalize_body<B2, PR>(it.w, it.b, gb - it.begin, it.nblocks);
+}
+
+__global__ void __launch_bounds__(VD_BLOCK) k_finalize_finish_batch(const FinalItem* __restrict__ items) {
+    const FinalItem& it = items[blockIdx.x];
+    finalize_finish_body(it.b, (unsigned)it.nblocks, it.n_ll);
+}
+
 }  // namespace vd
 
 // ----------------------------------------------------------------------------------
@@ -807,8 +907,10 @@ size_t level_lds_bytes(const LevelGeom& g) {
 }
 
 hipError_t set_level_lds_limit(size_t bytes) {
-    const void* fns[4] = {(const void*)k_level<false, false>, (const void*)k_level<false, true>,
-                          (const void*)k_level<true, false>, (const void*)k_level<true, true>};
+    const void* fns[8] = {(const void*)k_level<false, false>, (const void*)k_level<false, true>,
+                          (const void*)k_level<true, false>, (const void*)k_level<true, true>,
+                          (const void*)k_level_batch<false, false, 0>, (const void*)k_level_batch<false, true, 0>,
+                          (const void*)k_level_batch<true, false, 0>, (const void*)k_level_batch<true, true, 0>};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
@@ -905,6 +1007,65 @@ hipError_t launch_finalize(const Win& w, const FinalBufs& b, int n_ll, hipStream
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_finalize_finish, dim3(1), dim3(VD_BLOCK), 0, st, b, grid.x, n_ll);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_batch(const PrepItem* items, int n_items, hipStream_t st) {
+    hipLaunchKernelGGL(k_prep_batch, dim3((unsigned)n_items), dim3(64), 0, st, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_batch(const PrepItem* items, const int* blk2item, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_setup_batch, dim3((unsigned)nblocks), dim3(VD_BLOCK), 0, st, items, blk2item);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static void level_batch_mode(const LevelItem* items, const int* b2i, int nb, size_t lds, bool b2, bool pr,
+                             hipStream_t st) {
+    if (b2) {
+        if (pr) hipLaunchKernelGGL((k_level_batch<true, true, MODE>), dim3(nb), dim3(VD_BLOCK), lds, st, items, b2i);
+        else hipLaunchKernelGGL((k_level_batch<true, false, MODE>), dim3(nb), dim3(VD_BLOCK), lds, st, items, b2i);
+    } else {
+        if (pr) hipLaunchKernelGGL((k_level_batch<false, true, MODE>), dim3(nb), dim3(VD_BLOCK), lds, st, items, b2i);
+        else hipLaunchKernelGGL((k_level_batch<false, false, MODE>), dim3(nb), dim3(VD_BLOCK), lds, st, items, b2i);
+    }
+}
+
+hipError_t launch_level_batch(const LevelItem* items, const int* blk2item, int nblocks, size_t lds, int mode,
+                              bool b2, bool pr, hipStream_t st) {
+    if (mode == 0) level_batch_mode<0>(items, blk2item, nblocks, lds, b2, pr, st);
+    else if (mode == 1) level_batch_mode<1>(items, blk2item, nblocks, 0, b2, pr, st);
+    else level_batch_mode<2>(items, blk2item, nblocks, 0, b2, pr, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_gn_batch(const PoseItem* items, const int* blk2item, int nblocks, int s, bool b2,
+                                hipStream_t st) {
+    if (b2) hipLaunchKernelGGL((k_pose_gn_batch<true>), dim3(nblocks), dim3(VD_BLOCK), 0, st, items, blk2item, s);
+    else hipLaunchKernelGGL((k_pose_gn_batch<false>), dim3(nblocks), dim3(VD_BLOCK), 0, st, items, blk2item, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_gn_finish_batch(const PoseItem* items, int n_items, hipStream_t st) {
+    hipLaunchKernelGGL(k_pose_gn_finish_batch, dim3((unsigned)n_items), dim3(VD_BLOCK), 0, st, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const FinalItem* items, const int* blk2item, int nblocks, bool b2, bool pr,
+                                 hipStream_t st) {
+    if (b2) {
+        if (pr) hipLaunchKernelGGL((k_finalize_batch<true, true>), dim3(nblocks), dim3(VD_BLOCK), 0, st, items, blk2item);
+        else hipLaunchKernelGGL((k_finalize_batch<true, false>), dim3(nblocks), dim3(VD_BLOCK), 0, st, items, blk2item);
+    } else {
+        if (pr) hipLaunchKernelGGL((k_finalize_batch<false, true>), dim3(nblocks), dim3(VD_BLOCK), 0, st, items, blk2item);
+        else hipLaunchKernelGGL((k_finalize_batch<false, false>), dim3(nblocks), dim3(VD_BLOCK), 0, st, items, blk2item);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_finish_batch(const FinalItem* items, int n_items, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize_finish_batch, dim3((unsigned)n_items), dim3(VD_BLOCK), 0, st, items);
     return hipGetLastError();
 }
 

@@ -89,6 +89,46 @@ struct AlignBufs {
     double* partials;
 };
 
+// ---- batched launches over many windows: one item per window and launch; a block finds
+// its item through blk2item[global block] and its block index within the window as
+// (global block - begin).  Global blocks are XCD-remapped first.
+struct LevelItem {
+    Win w;
+    LevelGeom g;
+    LevelBufs b;
+    int do_e, do_m;
+    int begin;
+};
+
+struct PoseItem {
+    Win w;
+    PoseBufs b;
+    int G, S;          // Gauss-Newton steps per frame, steps of the window (N * G)
+    int begin, nblocks;
+};
+
+struct FinalItem {
+    Win w;
+    FinalBufs b;
+    int n_ll;
+    int begin, nblocks;
+};
+
+struct PrepItem {
+    const double* pose;
+    const double* prior_pose;
+    int N, P;
+    PoseF* out;
+    PoseD* outd;
+    // initial depth and flow layout (done once per window)
+    Win w;
+    float* idepth;
+    const float2* flow;
+    float4* flow2;
+    int init;
+    int begin, nblocks;
+};
+
 size_t level_lds_bytes(const LevelGeom& g);
 hipError_t launch_pose_prep(const double* pose, int N, const double* prior_pose, int P, PoseF* out, PoseD* outd,
                             hipStream_t st);
@@ -103,6 +143,19 @@ hipError_t launch_pose(const Win& w, const PoseBufs& b, int t, const double* can
                        int nblocks, hipStream_t st);
 hipError_t launch_finalize(const Win& w, const FinalBufs& b, int n_ll, hipStream_t st);
 hipError_t set_level_lds_limit(size_t bytes);
+
+// batched launchers: items / blk2item in device memory, nblocks = total blocks; PR selects the
+// prior path (all items of one launch share it and the log-logistic shape class B2)
+hipError_t launch_prep_batch(const PrepItem* items, int n_items, hipStream_t st);
+hipError_t launch_setup_batch(const PrepItem* items, const int* blk2item, int nblocks, hipStream_t st);
+hipError_t launch_level_batch(const LevelItem* items, const int* blk2item, int nblocks, size_t lds, int mode,
+                              bool b2, bool pr, hipStream_t st);
+hipError_t launch_pose_gn_batch(const PoseItem* items, const int* blk2item, int nblocks, int s, bool b2,
+                                hipStream_t st);
+hipError_t launch_pose_gn_finish_batch(const PoseItem* items, int n_items, hipStream_t st);
+hipError_t launch_finalize_batch(const FinalItem* items, const int* blk2item, int nblocks, bool b2, bool pr,
+                                 hipStream_t st);
+hipError_t launch_finalize_finish_batch(const FinalItem* items, int n_items, hipStream_t st);
 
 hipError_t launch_align_prepare(const AlignArgs& a, const AlignBufs& b, hipStream_t st);
 hipError_t launch_align_step(const AlignArgs& a, const AlignBufs& b, int final_pass, int nblocks, hipStream_t st);

@@ -74,6 +74,19 @@ def test_run_without_init_continues_from_given_depth(lib):
     assert_same(host(a), host(b))
 
 
+def test_warm_start_equals_step_sequence(lib):
+    w = synth.make_window(1, 5)
+    p = w["params"]
+    a, b = alloc(lib, w), alloc(lib, w)
+    for t in (a, b):
+        t["idepth"].copy_(torch.as_tensor(w["idepth_gt"] * 1.1, dtype=torch.float32).cuda())
+    lib.run(p, a, iters=2, init=False, first_iter=3)
+    for it in (3, 4):
+        lib.gem_step(p, b, it)
+    lib.finalize(p, b, 4)
+    assert_same(host(a), host(b))
+
+
 def test_batch_run_equals_individual_runs(lib):
     ws = windows()
     iters = 3
@@ -87,6 +100,27 @@ def test_batch_run_equals_individual_runs(lib):
         hx = host(x)
         assert_same(hx, host(y))
         assert np.isfinite(hx["stats"]).all()
+
+
+def test_batch_graph_replay_and_direct_launches_agree(lib):
+    """The captured graph, its replay on a later identical call and the uncaptured batched
+    launches all give the individual runs' results."""
+    ws = windows()
+    ws.append(synth.make_window(1, 9, H=30, W=44, N=2))
+    ws[-1]["params"].update(pose_gn_steps=0, n_candidates=9)
+    iters = 2
+    single = [(w["params"], alloc(lib, w)) for w in ws]
+    for p, b in single:
+        lib.run(p, b, iters=iters)
+    ref = [host(b) for _, b in single]
+    batch = [(w["params"], alloc(lib, w)) for w in ws]
+    pose0 = [b["pose"].clone() for _, b in batch]
+    for graph, rep in ((True, 0), (True, 1), (False, 0)):
+        for (p, b), p0 in zip(batch, pose0):
+            b["pose"].copy_(p0)
+        lib.batch_run(batch, iters, graph=graph)
+        for (_, b), r in zip(batch, ref):
+            assert_same(host(b), r)
 
 
 def test_batch_run_rejects_bad_arguments(lib):
