@@ -16,9 +16,17 @@ Also reported, on the same JSON line:
                 per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary committed under
                 profiles/ (null when the library sources changed since it was taken);
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same window (GEM iteration 0
-                on the full image), timed on this host.
+                on the full image), timed on this host;
+  batch         64 uneven windows (320..1216 x 240..352, N 3..8, half with a depth prior),
+                10 iterations each: 64 sequential whole-window calls against one replay of
+                the batched launch sequence captured in a HIP graph (windows/s, per-window
+                latency percentiles);
+  learned_init  plain GEM against GEM started from the learned proposal on held-out
+                640x480 windows: median error, and ms to reach plain GEM's median error;
+  proposal      the proposal network's forward pass at 640x480 (BF16 implicit-GEMM
+                convolutions on the matrix cores) against the dense BF16 peak.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--only-window]
 """
 import argparse
 import glob
@@ -40,6 +48,9 @@ FLOPS_ESTEP_PER_PIXEL_FRAME = 65.0
 # Non-packed FP32 vector peak: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz.  Packed FP32
 # instructions are disabled in this build, which halves the 157.3 TFLOP/s published peak.
 PEAK_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+PEAK_BF16_TFLOPS = 2500.0           # dense BF16 matrix-core peak
+# stored (computed) channel counts of the proposal network's layers: (c_in, c_out, scale)
+PROPOSAL_LAYERS = [(16, 64, 1), (64, 128, 0.25), (128, 128, 0.25), (128, 128, 0.25), (128, 64, 1), (64, 32, 1)]
 # Algorithmic bytes of one local-level launch per pixel: per frame the flow (8 B) and the
 # rigidness written (4 B); inverse depth read and written (8 B); the coarse value (4 B per
 # lattice cell of s*s = 16 pixels).
@@ -78,6 +89,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-window", action="store_true", help="skip the batch / learned-init / proposal parts")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -172,6 +184,11 @@ def main():
                                            f"(FP64 numpy, single thread), {cs:.1f} s"}
         log(f"oracle: {cs:.1f} s for one iteration -> {cpu['value']:.0f} pixel-frame updates/s")
 
+    extra = {}
+    if not args.only_window:
+        extra["batch"] = batch_workload(lib, np, torch, args)
+        extra["learned_init"], extra["proposal"] = learned_init(lib, np, torch)
+
     out = {
         "metric": "GEM pixel-frame updates/s at 1216x352 N=6",
         "value": round(value, 1),
@@ -190,9 +207,117 @@ def main():
                    "coarse_stride": p["coarse_stride"], "pose_gn_steps": p["pose_gn_steps"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        **extra,
     }
     print(json.dumps(out), flush=True)
     lib.close()
+
+
+def _pool_generate(fn, items, workers=16):
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(fn, items))
+
+
+def batch_workload(lib, np, torch, args):
+    from paper_2104_06800_amd import synth
+    t0 = time.time()
+    specs = synth.batch_shapes()
+    wins = _pool_generate(synth.batch_window, specs)
+    log(f"batch: {len(wins)} windows generated in {time.time() - t0:.1f}s")
+    items = []
+    for w in wins:
+        p = w["params"]
+        b = lib.alloc(p, w["flow"], w["pose_init"], w.get("prior_idepth"), w.get("prior_pose"))
+        items.append((p, b, b["pose"].clone()))
+    iters = items[0][0]["iters"]
+    assert all(p["iters"] == iters for p, _, _ in items)
+
+    def reset():
+        for _, b, p0 in items:
+            b["pose"].copy_(p0)
+
+    # sequential whole-window calls, each timed with events on the current stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in items]
+    for rep in range(2):
+        reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for (p, b, _), (e0, e1) in zip(items, ev):
+            e0.record()
+            lib.run(p, b, iters=iters)
+            e1.record()
+        torch.cuda.synchronize()
+        seq_ms = (time.perf_counter() - t1) * 1e3
+    per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    # batched: the first call captures the graph, later identical calls replay it
+    batch = [(p, b) for p, b, _ in items]
+    reset()
+    lib.batch_run(batch, iters)
+    torch.cuda.synchronize()
+    reps = 5
+    ts = []
+    for _ in range(reps):
+        reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lib.batch_run(batch, iters)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t1) * 1e3)
+    bat_ms = float(np.median(ts))
+    px = sum(p["H"] * p["W"] * p["N"] for p, _, _ in items) * iters
+    log(f"batch: sequential {seq_ms:.2f} ms ({len(items) / seq_ms * 1e3:.0f} windows/s), batched graph "
+        f"{bat_ms:.2f} ms ({len(items) / bat_ms * 1e3:.0f} windows/s)")
+    return {"windows": len(items), "iters": iters, "pixel_frame_updates": px,
+            "sequential_ms": round(seq_ms, 3), "batched_graph_ms": round(bat_ms, 3),
+            "windows_per_s_sequential": round(len(items) / seq_ms * 1e3, 1),
+            "windows_per_s_batched": round(len(items) / bat_ms * 1e3, 1),
+            "speedup": round(seq_ms / bat_ms, 3),
+            "per_window_ms_sequential": {"p50": round(float(np.percentile(per, 50)), 3),
+                                         "p90": round(float(np.percentile(per, 90)), 3),
+                                         "p99": round(float(np.percentile(per, 99)), 3)},
+            "per_window_ms_batched": round(bat_ms, 3),
+            "shapes": "W 320..1216, H 240..352 (steps of 16), N 3..8, odd windows with a depth prior"}
+
+
+def learned_init(lib, np, torch):
+    from paper_2104_06800_amd import proposal as pr
+    path = os.path.join(ROOT, "paper_2104_06800_amd", "weights", "proposal_n6.npz")
+    params, meta = pr.load(path)
+    net = lib.net_alloc(params)
+    t0 = time.time()
+    test = pr.generate(list(range(pr.TEST_SEED0, pr.TEST_SEED0 + 8)), 8)
+    log(f"learned init: {len(test)} held-out windows generated in {time.time() - t0:.1f}s")
+    res = pr.compare(lib, net, test)
+    summ = pr.summarize(res)
+    log("learned init: " + json.dumps(summ))
+    # proposal forward: MFMA throughput of the whole network at 640x480
+    p = test[0]["params"]
+    H, W = p["H"], p["W"]
+    flow = lib.alloc(p, test[0]["flow"], test[0]["pose_init"])["flow"]
+    tn = pr.tnorm_of(test[0]["pose_init"])
+    for _ in range(3):
+        lib.proposal_forward(net, flow, tn, p["idepth_min"], p["idepth_max"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        lib.proposal_forward(net, flow, tn, p["idepth_min"], p["idepth_max"])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = sum(2.0 * H * W * sc * co * 9 * ci for ci, co, sc in PROPOSAL_LAYERS)
+    achieved = flops / (ms / 1e3) / 1e12
+    log(f"proposal forward at {W}x{H}: {ms:.3f} ms, {flops / 1e9:.1f} GFLOP, {achieved:.1f} TFLOP/s")
+    prop = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "ms": round(ms, 4), "gflop": round(flops / 1e9, 2),
+            "workload": f"proposal forward {W}x{H}, N={p['N']}, BF16 weights/activations, FP32 accumulation"}
+    summ["held_out_windows"] = "seeds 10^6..10^6+7 of the 640x480 street recipe, N=6"
+    summ["training"] = (f"{int(meta.get('train', 0))} windows, {int(meta.get('steps', 0))} Adam steps on plain-GEM "
+                        "outputs")
+    return summ, prop
 
 
 if __name__ == "__main__":

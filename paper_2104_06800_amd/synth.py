@@ -434,6 +434,29 @@ def make_window(cfg: int, k: int = 0, noise: bool = True, H=None, W=None, N=None
     return out
 
 
+BATCH_SEED = 5_000_000
+
+
+def batch_shapes(n=64, seed=BATCH_SEED):
+    """Shapes of the uneven-window batch: width U{320..1216} and height U{240..352} in steps
+    of 16, N U{3..8}; odd windows carry a depth prior (indoor recipe), even ones are street
+    windows."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        W = int(rng.integers(20, 77)) * 16
+        H = int(rng.integers(15, 23)) * 16
+        N = int(rng.integers(3, 9))
+        out.append((i, H, W, N, bool(i % 2)))
+    return out
+
+
+def batch_window(spec, seed=BATCH_SEED):
+    """One window of the uneven batch from its (index, H, W, N, prior) spec."""
+    i, H, W, N, prior = spec
+    return make_window(3 if prior else 2, seed + i, H=H, W=W, N=N)
+
+
 def make_pairs(n_pairs: int, H=480, W=640, seed=3_000_000, max_deg=2.0, max_t=0.1,
                noise_rel=0.0, conf="ones", planar=False):
     """Keyframe pairs for point-to-plane alignment: two inverse-depth maps of one room
