@@ -79,4 +79,5 @@ hipError_t launch_loss(const float* o, int HW, int N, float tnorm, const float* 
                        hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
 
+
 }  // namespace vp

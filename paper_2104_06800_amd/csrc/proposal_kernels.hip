@@ -1,13 +1,12 @@
 // Learned depth / rigidness proposal on gfx950: BF16 3x3 convolutions as implicit GEMMs on
 // the matrix cores (v_mfma_f32_32x32x16_bf16), FP32 accumulation, NHWC activations.
 //
-//   k_conv<NT, MODE>  MODE 0: y = act(conv3x3(x) + b [+ skip])    (stride 1 or 2, optional 2x
+//   k_conv2           MODE 0: y = act(conv3x3(x) + b [+ skip])    (stride 1 or 2, optional 2x
 //                              nearest upsampling of the input)
 //                     MODE 1: data gradient dx = conv3x3^T(dy) with the transposed weights
 //                              [Cin][3][3][Cout], optional "+ add" and "* (mask > 0)" epilogue
 //                     GEMM view: M = output pixels, N = output channels, K = 9 * input
-//                     channels.  A wave owns 32 pixels x 32 NT channels (NT accumulators of
-//                     32x32); a block of 4 waves owns 128 consecutive pixels.  Cin is a
+//                     channels, operand tiles staged through LDS (see the kernel).  Cin is a
 //                     multiple of 16, Cout of 16 (a partial channel tile reads zero weights).
 //   k_wgrad           dW[co][tap][ci] = sum_m dy[m][co] x_tap(m)[ci] per pixel chunk (FP32
 //                     partials), k_sum_chunks reduces them in a fixed order
@@ -36,11 +35,6 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
     return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
-__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
-    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
-}
-
-__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u}); }
 
 // ---------------------------------------------------------------------------------------
 // input features: channel 2(t-1) + c = X_t[c] / FLOW_SCALE (non-finite -> 0), 16 channels
@@ -67,83 +61,146 @@ __global__ void k_features(const float2* __restrict__ flow, int N, int HW, uint1
 }
 
 // ---------------------------------------------------------------------------------------
-// implicit-GEMM convolution
+// LDS-staged implicit-GEMM convolution (the fast path; same arithmetic roles as k_conv).
+// Block tile BM pixels x BN output channels with 4 waves arranged WAVES_M x (4 / WAVES_M);
+// a wave owns (32 WM) x (32 WN) (WM * WN accumulators).  K is walked in chunks of KC
+// channels of one tap; the A chunk (BM x KC) and the B chunk (BN x KC) are staged in LDS
+// with 16-byte loads, double buffered: the next chunk's global loads are in flight while
+// the matrix cores work on the current one.
 // ---------------------------------------------------------------------------------------
-template <int NT, int MODE>
-__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+template <int WAVES_M, int WM, int WN, int KC, int MODE>
+__global__ void __launch_bounds__(256) k_conv2(ConvArgs a) {
+    constexpr int WAVES_N = 4 / WAVES_M;
+    constexpr int BM = WAVES_M * 32 * WM, BN = WAVES_N * 32 * WN;
+    constexpr int LD = KC + 8;                         // padded LDS row (bf16 elements)
+    constexpr int QA = KC / 8;                         // 16-byte units per row
+    constexpr int UA = (BM * QA + 255) / 256, UB = (BN * QA + 255) / 256;
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LD];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave % WAVES_M) * 32 * WM, wn0 = (wave / WAVES_M) * 32 * WN;
     const int Mpix = a.Ho * a.Wo;
-    const int m = (blockIdx.x * 4 + wave) * 32 + (lane & 31);   // A row of this lane
-    const int kb = lane >> 5;                                     // k sub-block (8 channels)
-    const int n0 = blockIdx.y * 32 * NT;
-    const bool mvalid = m < Mpix;
-    const int oy = mvalid ? m / a.Wo : 0, ox = mvalid ? m - oy * a.Wo : 0;
-    f32x16 acc[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[nt][e] = 0.f;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int kchunks = a.Cin / KC, nchunks = 9 * kchunks;
 
-    // output channels beyond Cout (a 16-channel data gradient fills half a tile) read zeros
-    const uint16_t* wrow[NT];
-    bool nvalid[NT];
+    // the rows (pixels / output channels) this thread stages
+    int a_oy[UA], a_ox[UA];
+    bool a_pv[UA];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int n = n0 + 32 * nt + (lane & 31);
-        nvalid[nt] = n < a.Cout;
-        wrow[nt] = a.w + (size_t)(nvalid[nt] ? n : 0) * 9 * a.Cin + 8 * kb;
+    for (int i = 0; i < UA; ++i) {
+        const int u = tid + 256 * i, r = u / QA;
+        const int m = m0 + r;
+        a_pv[i] = (u < BM * QA) && (m < Mpix);
+        a_oy[i] = a_pv[i] ? m / a.Wo : 0;
+        a_ox[i] = a_pv[i] ? m - a_oy[i] * a.Wo : 0;
     }
-
-    for (int tap = 0; tap < 9; ++tap) {
+    u32x4 ra[UA], rb[UB];
+    auto load_chunk = [&](int c) {
+        const int tap = c / kchunks, c0 = (c - tap * kchunks) * KC;
         const int ky = tap / 3, kx = tap - 3 * ky;
-        int sy, sx;
-        bool ok = mvalid;
-        if (MODE == 0) {
-            sy = oy * a.stride + ky - 1;
-            sx = ox * a.stride + kx - 1;
-            ok = ok && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws;
-            if (a.up) { sy >>= 1; sx >>= 1; }
-        } else {
-            sy = oy + 1 - ky;
-            sx = ox + 1 - kx;
-            if (a.stride == 2) {
-                ok = ok && !(sy & 1) && !(sx & 1);
-                sy >>= 1;
-                sx >>= 1;
-            }
-            ok = ok && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws;
-        }
-        const uint16_t* xp = a.x + ((size_t)(ok ? sy : 0) * a.Wx + (ok ? sx : 0)) * a.Cin + 8 * kb;
-        const size_t woff = (size_t)tap * a.Cin;
-        for (int c0 = 0; c0 < a.Cin; c0 += 16) {
-            const bf16x8 A = ok ? load8(xp + c0) : zero8();
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const bf16x8 B = nvalid[nt] ? load8(wrow[nt] + woff + c0) : zero8();
-                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[nt], 0, 0, 0);
+        for (int i = 0; i < UA; ++i) {
+            const int u = tid + 256 * i, q = u % QA;
+            int sy, sx;
+            bool ok = a_pv[i];
+            if (MODE == 0) {
+                sy = a_oy[i] * a.stride + ky - 1;
+                sx = a_ox[i] * a.stride + kx - 1;
+                ok = ok && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws;
+                if (a.up) { sy >>= 1; sx >>= 1; }
+            } else {
+                sy = a_oy[i] + 1 - ky;
+                sx = a_ox[i] + 1 - kx;
+                if (a.stride == 2) {
+                    ok = ok && !(sy & 1) && !(sx & 1);
+                    sy >>= 1;
+                    sx >>= 1;
+                }
+                ok = ok && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws;
             }
+            ra[i] = ok ? *reinterpret_cast<const u32x4*>(a.x + ((size_t)sy * a.Wx + sx) * a.Cin + c0 + 8 * q)
+                       : u32x4{0u, 0u, 0u, 0u};
         }
+#pragma unroll
+        for (int i = 0; i < UB; ++i) {
+            const int u = tid + 256 * i, r = u / QA, q = u % QA;
+            const int n = n0 + r;
+            const bool ok = (u < BN * QA) && (n < a.Cout);
+            rb[i] = ok ? *reinterpret_cast<const u32x4*>(a.w + ((size_t)n * 9 + tap) * a.Cin + c0 + 8 * q)
+                       : u32x4{0u, 0u, 0u, 0u};
+        }
+    };
+    auto store_chunk = [&](int st) {
+#pragma unroll
+        for (int i = 0; i < UA; ++i) {
+            const int u = tid + 256 * i;
+            if (u < BM * QA) *reinterpret_cast<u32x4*>(&As[st][(u / QA) * LD + 8 * (u % QA)]) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < UB; ++i) {
+            const int u = tid + 256 * i;
+            if (u < BN * QA) *reinterpret_cast<u32x4*>(&Bs[st][(u / QA) * LD + 8 * (u % QA)]) = rb[i];
+        }
+    };
+
+    f32x16 acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int st = c & 1;
+        if (c + 1 < nchunks) load_chunk(c + 1);
+#pragma unroll
+        for (int kk = 0; kk < KC / 16; ++kk) {
+            const int col = 16 * kk + 8 * (lane >> 5);
+            bf16x8 A[WM], B[WN];
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+                A[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(
+                                                      &As[st][(wm0 + 32 * i + (lane & 31)) * LD + col]));
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+                B[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(
+                                                      &Bs[st][(wn0 + 32 * j + (lane & 31)) * LD + col]));
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[i], B[j], acc[i][j], 0, 0, 0);
+        }
+        if (c + 1 < nchunks) store_chunk(st ^ 1);
+        __syncthreads();
     }
 
     // epilogue: lane holds D[i][j = lane%32] for rows i = 8(e/4) + 4(lane/32) + e%4
-    const int mw = (blockIdx.x * 4 + wave) * 32;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int n = n0 + 32 * nt + (lane & 31);
+    for (int j = 0; j < WN; ++j) {
+        const int n = n0 + wn0 + 32 * j + (lane & 31);
         if (n >= a.Cout) continue;
         const float bias = a.bias ? a.bias[n] : 0.f;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int mm = mw + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-            if (mm >= Mpix) continue;
-            const size_t o = (size_t)mm * a.Cout + n;
-            float v = acc[nt][e] + bias;
-            if (a.skip) v += bf2f(a.skip[o]);
-            if (a.addf) v += a.addf[o];
-            if (a.relu) v = fmaxf(v, 0.f);
-            if (a.mask && !(bf2f(a.mask[o]) > 0.f)) v = 0.f;
-            if (a.y) a.y[o] = f2bf(v);
-            if (a.yf) a.yf[o] = v;
+        for (int i = 0; i < WM; ++i) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int mm = m0 + wm0 + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                if (mm >= Mpix) continue;
+                const size_t o = (size_t)mm * a.Cout + n;
+                float v = acc[i][j][e] + bias;
+                if (a.skip) v += bf2f(a.skip[o]);
+                if (a.addf) v += a.addf[o];
+                if (a.relu) v = fmaxf(v, 0.f);
+                if (a.mask && !(bf2f(a.mask[o]) > 0.f)) v = 0.f;
+                if (a.y) a.y[o] = f2bf(v);
+                if (a.yf) a.yf[o] = v;
+            }
         }
     }
 }
@@ -367,22 +424,36 @@ __global__ void k_adam(AdamArgs a) {
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
+
 hipError_t launch_features(const float* flow, int N, int HW, uint16_t* x, hipStream_t st) {
     hipLaunchKernelGGL(k_features, dim3((HW + 255) / 256), dim3(256), 0, st, (const float2*)flow, N, HW, x);
     return hipGetLastError();
 }
 
-hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t st) {
+template <int WAVES_M, int WM, int WN, int KC>
+static void conv2_launch(const ConvArgs& a, int mode, hipStream_t st) {
+    constexpr int BM = WAVES_M * 32 * WM, BN = (4 / WAVES_M) * 32 * WN;
     const int Mpix = a.Ho * a.Wo;
-    const int NT = (a.Cout % 64 == 0) ? 2 : 1;
-    const dim3 grid((unsigned)((Mpix + 127) / 128), (unsigned)((a.Cout + 32 * NT - 1) / (32 * NT)));
-    if (mode == 0) {
-        if (NT == 2) hipLaunchKernelGGL((k_conv<2, 0>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_conv<1, 0>), grid, dim3(256), 0, st, a);
+    const dim3 grid((unsigned)((Mpix + BM - 1) / BM), (unsigned)((a.Cout + BN - 1) / BN));
+    if (mode == 0) hipLaunchKernelGGL((k_conv2<WAVES_M, WM, WN, KC, 0>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_conv2<WAVES_M, WM, WN, KC, 1>), grid, dim3(256), 0, st, a);
+}
+
+// LDS-staged kernel: block 128 x 128 (Cout multiple of 128), 256 x 64 (Cout multiple of 64)
+// or 256 x 32; chunks of 32 channels (16 when Cin is not a multiple of 32)
+static void launch_conv2(const ConvArgs& a, int mode, hipStream_t st) {
+    const bool k32 = (a.Cin % 32) == 0;
+    if (a.Cout % 128 == 0) {
+        if (k32) conv2_launch<2, 2, 2, 32>(a, mode, st); else conv2_launch<2, 2, 2, 16>(a, mode, st);
+    } else if (a.Cout % 64 == 0) {
+        if (k32) conv2_launch<4, 2, 2, 32>(a, mode, st); else conv2_launch<4, 2, 2, 16>(a, mode, st);
     } else {
-        if (NT == 2) hipLaunchKernelGGL((k_conv<2, 1>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_conv<1, 1>), grid, dim3(256), 0, st, a);
+        if (k32) conv2_launch<4, 2, 1, 32>(a, mode, st); else conv2_launch<4, 2, 1, 16>(a, mode, st);
     }
+}
+
+hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t st) {
+    launch_conv2(a, mode, st);
     return hipGetLastError();
 }
 
