@@ -475,6 +475,66 @@ __device__ __forceinline__ float energy2(const Win& w, const PoseF* __restrict__
     return E;
 }
 
+// E_j(rho) with the frame terms on separate lanes of a 32-lane group: lane hl < N computes
+// frame hl's cost factor (its own reprojections into frames hl-1 and hl, as the sequential
+// loop does), so the frames' flow gathers are in flight together; the terms are then summed
+// in frame order with the sequential loop's FMAs, so the result equals energy2's bit for bit.
+// Every lane of the group must call it (hbase = the group's first lane in the wave).
+template <bool B2>
+__device__ __forceinline__ float frame_cost(const Win& w, const PoseF* __restrict__ P, const float4* __restrict__ flow2,
+                                            const Pix& c, float rho, int t) {
+    const PoseF& T = P[t];
+    const float Dx = fmaf(rho, T.t[0], fmaf(T.d[0], c.x0, fmaf(T.d[1], c.x1, T.d[2])));
+    const float Dy = fmaf(rho, T.t[1], fmaf(T.d[3], c.x0, fmaf(T.d[4], c.x1, T.d[5])));
+    const float Dz = fmaf(rho, T.t[2], fmaf(T.d[6], c.x0, fmaf(T.d[7], c.x1, T.d[8])));
+    const float Qz = 1.f + Dz;
+    const bool zok = Qz > 0.f;
+    const float iz = rcp(Qz);
+    const float dx = w.fx * fmaf(-c.x0, Dz, Dx) * iz;
+    const float dy = w.fy * fmaf(-c.x1, Dz, Dy) * iz;
+    float dpx = 0.f, dpy = 0.f, fx, fy;
+    bool zprev = true, fok;
+    if (t == 0) {
+        fx = c.f1x; fy = c.f1y; fok = c.ok1;
+    } else {
+        const PoseF& Tp = P[t - 1];
+        const float Ex = fmaf(rho, Tp.t[0], fmaf(Tp.d[0], c.x0, fmaf(Tp.d[1], c.x1, Tp.d[2])));
+        const float Ey = fmaf(rho, Tp.t[1], fmaf(Tp.d[3], c.x0, fmaf(Tp.d[4], c.x1, Tp.d[5])));
+        const float Ez = fmaf(rho, Tp.t[2], fmaf(Tp.d[6], c.x0, fmaf(Tp.d[7], c.x1, Tp.d[8])));
+        const float Pz = 1.f + Ez;
+        zprev = Pz > 0.f;
+        const float ipz = rcp(Pz);
+        dpx = w.fx * fmaf(-c.x0, Ez, Ex) * ipz;
+        dpy = w.fy * fmaf(-c.x1, Ez, Ey) * ipz;
+        fok = sample_flow2(flow2 + t * (size_t)w.H * w.W, w.H, w.W, c.u + dpx, c.v + dpy, fx, fy);
+    }
+    const bool ok = zprev && zok && fok;
+    const float ex = (dx - dpx) - fx, ey = (dy - dpy) - fy;
+    return ok ? flow_cost2<B2>(w, fmaf(ex, ex, ey * ey)) : 1.0f;
+}
+
+template <bool B2, bool PR>
+__device__ __forceinline__ float energy2_lanes(const Win& w, const PoseF* __restrict__ P,
+                                               const float4* __restrict__ flow2, const float* __restrict__ prior,
+                                               const Pix& c, float rho, int hl, int hbase) {
+    const float mine = hl < w.N ? frame_cost<B2>(w, P, flow2, c, rho, hl) : 0.f;
+    float E = 0.f;
+#pragma unroll
+    for (int t = 0; t < VD_NMAX; ++t)
+        if (t < w.N) E = fmaf(c.q[t], __shfl(mine, hbase + t), E);
+    if (!PR) return E;
+#pragma unroll
+    for (int k = 0; k < VD_PMAX; ++k) {
+        if (k < w.P && c.qh[k] > 0.f) {
+            float z;
+            const float cost = prior_z(w, P, prior, c, k, rho, z)
+                             ? softplus2(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)) : 1.0f;
+            E = fmaf(c.qh[k], cost, E);
+        }
+    }
+    return E;
+}
+
 // E_j(rho) with pruning: all terms are non-negative and the FP32 running sum only grows, so
 // once it passes `bound` the candidate cannot win and the remaining frames (and their flow
 // gathers) are skipped.  STRICT: stop when E > bound (callers that keep ties), otherwise

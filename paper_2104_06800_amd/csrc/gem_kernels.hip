@@ -318,16 +318,19 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
     }
     __syncthreads();
 
-    // phase B: serial scan per chain
-    if (tid < g.C) {
-        const int c = tid;
-        const int L = chain_len(g, blk, c);
-        if (L > 0) {
+    // phase B: serial scan per chain, a group of 32 lanes per chain.  A speculation miss
+    // evaluates E_i(carried) with the frame terms on separate lanes of the group
+    // (energy2_lanes), which equals the sequential evaluation bit for bit.
+    {
+        const int grp = tid >> 5, hl = tid & 31, hbase = tid & 32;
+        for (int c = grp; c < g.C; c += VD_BLOCK / 32) {
+            const int L = chain_len(g, blk, c);
+            if (L <= 0) continue;
             const int i0 = fwd ? 0 : L - 1;
             const int base = c * stride;
             float carried = bestV[base + i0];
             int src = i0;
-            newV[base + i0] = carried;
+            if (hl == 0) newV[base + i0] = carried;
             for (int n = 1, i = i0 + di; n < L; ++n, i += di) {
                 const int o = base + i;
                 float e1;
@@ -343,12 +346,12 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
 #pragma unroll
                     for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) cx.q[t] = q_s[t * nodes + o];
                     prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cx, rcur[o]);
-                    e1 = energy2_bounded<B2, PR, true>(w, B.P, B.flow2, B.prior, cx, carried, bestE[o]);
+                    e1 = energy2_lanes<B2, PR>(w, B.P, B.flow2, B.prior, cx, carried, hl, hbase);
                 }
                 const float eA = bestE[o];
                 const bool keep = (e1 < eA) || (e1 == eA && bestS[o] > 1);
                 if (!keep) { carried = bestV[o]; src = i; }
-                newV[o] = carried;
+                if (hl == 0) newV[o] = carried;
             }
         }
     }
