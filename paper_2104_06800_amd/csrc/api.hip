@@ -165,8 +165,9 @@ vd::LevelGeom make_geom(const voldor_window* v, const vd::Win& w, int level, int
     const int lines = g.horizontal ? g.h : g.w;
     g.nseg = (axis + g.seg - 1) / g.seg;
     g.nblocks = g.nseg * ((lines + g.C - 1) / g.C);
-    // the coarse level's long chains run many nodes per propagated value: deeper speculation
-    g.spec = level == VOLDOR_LEVEL_COARSE ? VD_SPEC : 1;
+    // speculation depth of the chain scan: the coarse level's long chains carry a value over
+    // many nodes, so it speculates deeper (phase A2 cost grows with the depth, misses shrink)
+    g.spec = level == VOLDOR_LEVEL_COARSE ? VD_SPEC : 2;
     return g;
 }
 

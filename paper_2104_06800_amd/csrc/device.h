@@ -11,7 +11,7 @@
 #define VD_NMAX 8
 #define VD_PMAX 4
 #define VD_BLOCK 256
-#define VD_SPEC 4       // maximum speculation depth of the chain scan
+#define VD_SPEC 8       // maximum speculation depth of the chain scan
 #define VD_LN2 0.69314718055994530942f
 #define VD_LOG2E 1.44269504088896340736f
 

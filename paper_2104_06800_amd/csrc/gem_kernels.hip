@@ -118,8 +118,8 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
     float* r_s = q_s + VD_NMAX * nodes;     // [N][C][stride] emission ratios (E-step)
     float* bestE = r_s + VD_NMAX * nodes;   // [C][stride]
     float* bestV = bestE + nodes;
-    float* specE = bestV + nodes;           // [VD_SPEC][C][stride]
-    float* rcur = specE + VD_SPEC * nodes;
+    float* specE = bestV + nodes;           // [spec][C][stride]
+    float* rcur = specE + g.spec * nodes;
     float* newV = rcur + nodes;
     int* bestS = (int*)(newV + nodes);
     __shared__ double ll_red[VD_BLOCK / 64];
@@ -906,7 +906,7 @@ namespace vd {
 
 size_t level_lds_bytes(const LevelGeom& g) {
     const size_t nodes = (size_t)g.C * (g.seg + 1);
-    return (2 * VD_NMAX * nodes + (4 + VD_SPEC) * nodes) * sizeof(float) + nodes * sizeof(int);
+    return (2 * VD_NMAX * nodes + (4 + (size_t)g.spec) * nodes) * sizeof(float) + nodes * sizeof(int);
 }
 
 hipError_t set_level_lds_limit(size_t bytes) {
