@@ -633,6 +633,30 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
     __shared__ PoseF curF, prevF;
     const int tid = threadIdx.x;
     const int t = s / G + 1, k = s - (t - 1) * G;
+    const int plane = w.H * w.W;
+    const float2* __restrict__ flow_t = B.flow + (size_t)(t - 1) * plane;
+    const float4* __restrict__ flow2_t = B.flow2 + (size_t)(t - 1) * plane;
+    const float* __restrict__ idepth = B.idepth;
+    const float* __restrict__ rig = B.rigid + (size_t)(t - 1) * plane;
+    float2* __restrict__ obs = B.obs;
+    const int stride = (int)nb * VD_BLOCK;
+    constexpr int UB = 4;                  // pixels per thread and batch: loads issued together
+    float rho[UB], q[UB], ox[UB], oy[UB];
+    int jj[UB];
+    auto load = [&](int j0) {
+#pragma unroll
+        for (int b = 0; b < UB; ++b) {
+            const int j = j0 + b * stride;
+            jj[b] = j < plane ? j : -1;
+            const int jc = j < plane ? j : 0;
+            rho[b] = idepth[jc];
+            q[b] = rig[jc];
+            if (k > 0) { const float2 o = obs[jc]; ox[b] = o.x; oy[b] = o.y; }
+            else if (t == 1) { const float2 f = flow_t[jc]; ox[b] = f.x; oy[b] = f.y; }
+        }
+    };
+    int j0 = blk * VD_BLOCK + tid;
+    if (j0 < plane) load(j0);              // the first batch is in flight during the prologue
     if (s > 0) {
         reduce_partials<29>(B.partials + (size_t)((s - 1) & 1) * 29 * nb, nb, red);
         if (tid == 0) {
@@ -650,31 +674,11 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
     }
     __syncthreads();
     const PoseF Tc = curF;
-    const int plane = w.H * w.W;
-    const float2* __restrict__ flow_t = B.flow + (size_t)(t - 1) * plane;
-    const float4* __restrict__ flow2_t = B.flow2 + (size_t)(t - 1) * plane;
-    const float* __restrict__ idepth = B.idepth;
-    const float* __restrict__ rig = B.rigid + (size_t)(t - 1) * plane;
-    float2* __restrict__ obs = B.obs;
     // per-thread sums in FP32 (a thread covers a few pixels), FP64 across threads and blocks
     float a32[29];
 #pragma unroll
     for (int i = 0; i < 29; ++i) a32[i] = 0.f;
-    const int stride = (int)nb * VD_BLOCK;
-    constexpr int UB = 4;                  // pixels per thread and batch: loads issued together
-    for (int j0 = blk * VD_BLOCK + tid; j0 < plane; j0 += UB * stride) {
-        float rho[UB], q[UB], ox[UB], oy[UB];
-        int jj[UB];
-#pragma unroll
-        for (int b = 0; b < UB; ++b) {
-            const int j = j0 + b * stride;
-            jj[b] = j < plane ? j : -1;
-            const int jc = j < plane ? j : 0;
-            rho[b] = idepth[jc];
-            q[b] = rig[jc];
-            if (k > 0) { const float2 o = obs[jc]; ox[b] = o.x; oy[b] = o.y; }
-            else if (t == 1) { const float2 f = flow_t[jc]; ox[b] = f.x; oy[b] = f.y; }
-        }
+    while (j0 < plane) {
         if (k == 0 && t > 1) {
             const PoseF& Tp = prevF;
 #pragma unroll
@@ -733,6 +737,8 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
                 a32[28] += 1.f;
             }
         }
+        j0 += UB * stride;
+        if (j0 < plane) load(j0);
     }
     double acc[29];
 #pragma unroll
