@@ -186,17 +186,19 @@ int voldor_run(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* b
 int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, const voldor_buffers* bufs,
                      int n_iters, int flags, void* stream);
 
-/* Launch timers (measurement).  While enabled, the library brackets launches of each timer
- * class with HIP events on the launch stream: VOLDOR_TIMER_LOCAL = the fused local-level
- * E+M kernel, VOLDOR_TIMER_COARSE = a coarse-level pass (its E-step and M-step launches),
- * VOLDOR_TIMER_POSE = a pose step (all its Gauss-Newton launches).  voldor_timing(ctx, 1)
- * starts afresh and discards earlier records; voldor_timing(ctx, 0) stops recording.
- * voldor_timing_read waits for the recorded events of one class, returns the summed
- * duration (ms) and the number of bracketed launches, and clears that class. */
+/* Launch timers (measurement).  The library brackets launches of each enabled timer class
+ * with HIP events on the launch stream: VOLDOR_TIMER_LOCAL = the fused local-level E+M
+ * kernel, VOLDOR_TIMER_COARSE = a coarse-level pass (its E-step and M-step launches),
+ * VOLDOR_TIMER_POSE = a pose step (all its Gauss-Newton launches).  Each event record costs
+ * the stream a few microseconds, so enable only the classes you read.
+ * voldor_timing(ctx, mask) enables the classes whose bit (1 << timer) is set, starts afresh
+ * and discards earlier records; mask 0 stops recording; a mask outside 0..7 is
+ * VOLDOR_EINVAL.  voldor_timing_read waits for the recorded events of one class, returns
+ * the summed duration (ms) and the number of bracketed launches, and clears that class. */
 #define VOLDOR_TIMER_LOCAL  0
 #define VOLDOR_TIMER_COARSE 1
 #define VOLDOR_TIMER_POSE   2
-int voldor_timing(voldor_ctx ctx, int enable);
+int voldor_timing(voldor_ctx ctx, int mask);
 int voldor_timing_read(voldor_ctx ctx, int timer, double* total_ms, int64_t* launches);
 
 /* ---------------------------------------------------------------------------------

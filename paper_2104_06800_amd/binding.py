@@ -250,8 +250,10 @@ class Voldor:
         flags = (RUN_INIT if init else 0) | (0 if graph else RUN_NO_GRAPH)
         self._check(_LIB.voldor_batch_run(self._h, n, wins, bufs, iters, flags, _stream(stream)), "voldor_batch_run")
 
-    def timing(self, enable):
-        self._check(_LIB.voldor_timing(self._h, 1 if enable else 0), "voldor_timing")
+    def timing(self, enable, timers=(TIMER_LOCAL, TIMER_COARSE, TIMER_POSE)):
+        """Starts (afresh) or stops the launch timers of the given classes."""
+        mask = sum(1 << t for t in set(timers)) if enable else 0
+        self._check(_LIB.voldor_timing(self._h, mask), "voldor_timing")
 
     def timing_read(self, timer):
         """(total ms, launches) of one timer class since the last read; waits for them."""

@@ -35,9 +35,9 @@ hipError_t take_event(voldor_ctx ctx, hipEvent_t* e) {
 }
 
 // Start of a bracket: *a stays null when timing is off.
-hipError_t timer_start(voldor_ctx ctx, hipStream_t st, hipEvent_t* a) {
+hipError_t timer_start(voldor_ctx ctx, int which, hipStream_t st, hipEvent_t* a) {
     *a = nullptr;
-    if (!ctx->timing) return hipSuccess;
+    if (!(ctx->timing & (1u << which))) return hipSuccess;
     hipError_t e = take_event(ctx, a);
     if (e == hipSuccess) e = hipEventRecord(*a, st);
     return e;
@@ -168,6 +168,13 @@ vd::LevelGeom make_geom(const voldor_window* v, const vd::Win& w, int level, int
     // speculation depth of the chain scan: the coarse level's long chains carry a value over
     // many nodes, so it speculates deeper (phase A2 cost grows with the depth, misses shrink)
     g.spec = level == VOLDOR_LEVEL_COARSE ? VD_SPEC : 2;
+    // a fused local pass keeps its E-step frame costs when there are no priors and the
+    // block still fits 5 per CU (32 KB of the 160 KB LDS)
+    g.ncost = 0;
+    if (level == VOLDOR_LEVEL_LOCAL && v->P == 0) {
+        g.ncost = v->N;
+        if (vd::level_lds_bytes(g) > 32 * 1024) g.ncost = 0;
+    }
     return g;
 }
 
@@ -203,7 +210,8 @@ size_t gem_layout(const voldor_window* v, int n_cand, GemLaunch& L) {
     // ~4 pixels per thread: enough blocks to fill the chip, few partial records
     L.pose_blocks = (int)std::min<int64_t>(std::max<int64_t>(1, (npix + 2 * VD_BLOCK - 1) / (2 * VD_BLOCK)), 2048);
     // pose step: one block per 1024 pixels keeps the per-block prologue cheap
-    L.gn_blocks = (int)std::min<int64_t>(std::max<int64_t>(1, (npix + 4 * VD_BLOCK - 1) / (4 * VD_BLOCK)), 256);
+    L.gn_blocks = (int)std::min<int64_t>(
+        std::max<int64_t>(1, (npix + VD_GN_PIX * VD_GN_BLOCK - 1) / (VD_GN_PIX * VD_GN_BLOCK)), 256);
     const int fin_blocks = (int)((npix + VD_BLOCK - 1) / VD_BLOCK);
     L.sz.head = align_up((VD_NMAX + VD_PMAX) * sizeof(vd::PoseF)) + align_up(VD_NMAX * sizeof(vd::PoseD));
     L.sz.ll = align_up(sizeof(double) * mx);
@@ -313,7 +321,7 @@ int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll)
     hipEvent_t t0 = nullptr;
     const int timer = level == VOLDOR_LEVEL_COARSE ? VOLDOR_TIMER_COARSE : VOLDOR_TIMER_LOCAL;
     const bool timed = level == VOLDOR_LEVEL_COARSE || (do_e && do_m);
-    if (timed) VD_CHECK(timer_start(ctx, L.st, &t0), "timer event");
+    if (timed) VD_CHECK(timer_start(ctx, timer, L.st, &t0), "timer event");
     if (level == VOLDOR_LEVEL_COARSE && do_m) {
         // few long chains: E-step per chain, phase A over the whole lattice, then the
         // per-chain speculation + scan from the stored phase-A results
@@ -335,7 +343,7 @@ int run_pose_step(GemLaunch& L) {
     const int G = L.v->pose_gn_steps;
     if (G == 0) return VOLDOR_OK;
     hipEvent_t t0 = nullptr;
-    VD_CHECK(timer_start(ctx, L.st, &t0), "timer event");
+    VD_CHECK(timer_start(ctx, VOLDOR_TIMER_POSE, L.st, &t0), "timer event");
     for (int s = 0; s < L.v->N * G; ++s)
         VD_CHECK(vd::launch_pose_gn(w, B, s, G, L.gn_blocks, L.st), "pose step launch");
     VD_CHECK(vd::launch_pose_gn_finish(B, L.v->N, G, L.gn_blocks, L.st), "pose finish launch");
@@ -921,10 +929,11 @@ int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, c
     return VOLDOR_OK;
 }
 
-int voldor_timing(voldor_ctx ctx, int enable) {
+int voldor_timing(voldor_ctx ctx, int mask) {
     if (!ctx) return VOLDOR_EINVAL;
+    if (mask < 0 || mask >= (1 << kTimers)) return fail(ctx, VOLDOR_EINVAL, "timer mask %d outside 0..%d", mask, (1 << kTimers) - 1);
     timers_discard(ctx);
-    ctx->timing = enable != 0;
+    ctx->timing = (unsigned)mask;
     return VOLDOR_OK;
 }
 

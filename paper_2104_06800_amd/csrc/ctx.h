@@ -28,7 +28,7 @@ struct voldor_ctx_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int n_cu = 256;
-    bool timing = false;
+    unsigned timing = 0;              // enabled timer classes, bit (1 << timer)
     std::vector<hipEvent_t> ev_pool;                                   // idle events
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec[kTimers];    // recorded brackets
 };

@@ -11,6 +11,13 @@
 #define VD_NMAX 8
 #define VD_PMAX 4
 #define VD_BLOCK 256
+// pose Gauss-Newton launches: threads per block and pixels per thread and load batch
+#ifndef VD_GN_BLOCK
+#define VD_GN_BLOCK 256
+#endif
+#ifndef VD_GN_PIX
+#define VD_GN_PIX 4
+#endif
 #define VD_SPEC 8       // maximum speculation depth of the chain scan
 #define VD_LN2 0.69314718055994530942f
 #define VD_LOG2E 1.44269504088896340736f
@@ -475,6 +482,28 @@ __device__ __forceinline__ float energy2(const Win& w, const PoseF* __restrict__
     return E;
 }
 
+// E_j(rho) from frame cost factors already evaluated at rho (cost[t * step], as energy2
+// forms them): the same FMAs in the same order as energy2, so the same value bit for bit.
+template <bool PR>
+__device__ __forceinline__ float energy2_costs(const Win& w, const PoseF* __restrict__ P, const float* __restrict__ prior,
+                                               const Pix& c, float rho, const float* cost, int step) {
+    float E = 0.f;
+#pragma unroll
+    for (int t = 0; t < VD_NMAX; ++t)
+        if (t < w.N) E = fmaf(c.q[t], cost[t * step], E);
+    if (!PR) return E;
+#pragma unroll
+    for (int k = 0; k < VD_PMAX; ++k) {
+        if (k < w.P && c.qh[k] > 0.f) {
+            float z;
+            const float cost_k = prior_z(w, P, prior, c, k, rho, z)
+                               ? softplus2(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)) : 1.0f;
+            E = fmaf(c.qh[k], cost_k, E);
+        }
+    }
+    return E;
+}
+
 // E_j(rho) with the frame terms on separate lanes of a 32-lane group: lane hl < N computes
 // frame hl's cost factor (its own reprojections into frames hl-1 and hl, as the sequential
 // loop does), so the frames' flow gathers are in flight together; the terms are then summed
@@ -586,6 +615,73 @@ __device__ __forceinline__ float energy2_bounded(const Win& w, const PoseF* __re
     return E;
 }
 
+// M candidates against one bound with their frames in lockstep.  Each candidate keeps the
+// running sum and stop test of energy2_bounded<STRICT>, so every returned value is exactly
+// what energy2_bounded returns for that candidate and bound; the flow gathers of the live
+// candidates of a frame are in flight together.  Bit m of live selects candidate m; an
+// unselected candidate's value is meaningless.
+template <bool B2, bool PR, bool STRICT, int M>
+__device__ __forceinline__ void energy2_bounded_m(const Win& w, const PoseF* __restrict__ P,
+                                                  const float4* __restrict__ flow2, const float* __restrict__ prior,
+                                                  const Pix& c, const float* rho, unsigned live, float bound,
+                                                  float* E) {
+    float dpx[M], dpy[M];
+    bool zprev[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) { E[m] = 0.f; dpx[m] = 0.f; dpy[m] = 0.f; zprev[m] = true; }
+    const size_t plane = (size_t)w.H * w.W;
+#pragma unroll
+    for (int t = 0; t < VD_NMAX; ++t) {
+        if (t >= w.N || live == 0u) break;
+        const PoseF& T = P[t];
+        float dx[M], dy[M], fx[M], fy[M];
+        bool zok[M], fok[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float r = rho[m];
+            const float Dx = fmaf(r, T.t[0], fmaf(T.d[0], c.x0, fmaf(T.d[1], c.x1, T.d[2])));
+            const float Dy = fmaf(r, T.t[1], fmaf(T.d[3], c.x0, fmaf(T.d[4], c.x1, T.d[5])));
+            const float Dz = fmaf(r, T.t[2], fmaf(T.d[6], c.x0, fmaf(T.d[7], c.x1, T.d[8])));
+            const float Qz = 1.f + Dz;
+            zok[m] = Qz > 0.f;
+            const float iz = rcp(Qz);
+            dx[m] = w.fx * fmaf(-c.x0, Dz, Dx) * iz;
+            dy[m] = w.fy * fmaf(-c.x1, Dz, Dy) * iz;
+            fx[m] = 0.f; fy[m] = 0.f; fok[m] = false;
+            if (t == 0) {
+                fx[m] = c.f1x; fy[m] = c.f1y; fok[m] = c.ok1;
+            } else if ((live >> m) & 1u) {
+                fok[m] = sample_flow2(flow2 + t * plane, w.H, w.W, c.u + dpx[m], c.v + dpy[m], fx[m], fy[m]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if ((live >> m) & 1u) {
+                const bool ok = zprev[m] && zok[m] && fok[m];
+                const float ex = (dx[m] - dpx[m]) - fx[m], ey = (dy[m] - dpy[m]) - fy[m];
+                E[m] = fmaf(c.q[t], ok ? flow_cost2<B2>(w, fmaf(ex, ex, ey * ey)) : 1.0f, E[m]);
+                if (STRICT ? (E[m] > bound) : (E[m] >= bound)) live &= ~(1u << m);
+            }
+            dpx[m] = dx[m]; dpy[m] = dy[m]; zprev[m] = zok[m];
+        }
+    }
+    if (!PR) return;
+    // candidates below the bound after every frame take the prior terms
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        if (!((live >> m) & 1u)) continue;
+#pragma unroll
+        for (int k = 0; k < VD_PMAX; ++k) {
+            if (k < w.P && c.qh[k] > 0.f) {
+                float z;
+                const float cost = prior_z(w, P, prior, c, k, rho[m], z)
+                                 ? softplus2(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)) : 1.0f;
+                E[m] = fmaf(c.qh[k], cost, E[m]);
+            }
+        }
+    }
+}
+
 // Prior posteriors q^_k at the current value (Eq. 3 mixture): pi N / (pi N + (1 - pi) U).
 // Returns a bit mask of the priors whose transfer is valid (no hole) at rho_cur.
 template <bool PR>
@@ -628,7 +724,7 @@ __device__ __forceinline__ void emissions(const Win& w, const PoseF* __restrict_
                 ratio = exp2f_fast(-log2_ratio<false>(w, r2));
             }
         }
-        out(t, ratio, ok);
+        out(t, ratio, ok, r2);
     });
 }
 
@@ -660,17 +756,17 @@ __device__ __forceinline__ void block_reduce(double* acc, double* red /* [NT/64]
 // thread i takes the blocks i, i + 256, ... (coalesced, independent loads), then a
 // fixed-order block reduction.  The NR sums are in red[0..NR-1] after the call (all
 // threads synchronised).
-template <int NR>
+template <int NR, int NT = VD_BLOCK>
 __device__ __forceinline__ void reduce_partials(const double* part, unsigned nb, double* red) {
     double acc[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-    for (unsigned b = threadIdx.x; b < nb; b += VD_BLOCK) {
+    for (unsigned b = threadIdx.x; b < nb; b += NT) {
 #pragma unroll
         for (int k = 0; k < NR; ++k) acc[k] += __builtin_nontemporal_load(part + (size_t)k * nb + b);
     }
     __syncthreads();
-    block_reduce<NR>(acc, red);
+    block_reduce<NR, NT>(acc, red);
     __syncthreads();
 }
 

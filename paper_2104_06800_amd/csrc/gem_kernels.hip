@@ -122,7 +122,11 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
     float* rcur = specE + g.spec * nodes;
     float* newV = rcur + nodes;
     int* bestS = (int*)(newV + nodes);
+    float* cost_s = (float*)(bestS + nodes);  // [ncost][C][stride] E-step frame costs at rho
     __shared__ double ll_red[VD_BLOCK / 64];
+    // a fused pass keeps the E-step's frame costs at the current value: the M-step's slot-0
+    // energy is then their q-weighted sum, with no flow gathers
+    const bool keep_cost = do_e && do_m == 1 && g.ncost > 0;
 
     const int tid = threadIdx.x;
     const int npix = g.C * g.seg;
@@ -140,11 +144,17 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             const float rho = rho_full[p.v * w.W + p.u];
             const int o = p.c * stride + p.i;
             if (w.chain_axis == 0) {
-                emissions<B2>(w, B.P, B.flow2, c, rho, [&](int t, float ratio, bool) { r_s[t * nodes + o] = ratio; });
+                emissions<B2>(w, B.P, B.flow2, c, rho, [&](int t, float ratio, bool ok, float r2) {
+                    r_s[t * nodes + o] = ratio;
+                    if (keep_cost) cost_s[t * nodes + o] = ok ? flow_cost2<B2>(w, r2) : 1.0f;
+                });
             } else {
                 // temporal chain over the frame window, in registers
                 float rr[VD_NMAX], al[VD_NMAX];
-                emissions<B2>(w, B.P, B.flow2, c, rho, [&](int t, float ratio, bool) { rr[t] = ratio; });
+                emissions<B2>(w, B.P, B.flow2, c, rho, [&](int t, float ratio, bool ok, float r2) {
+                    rr[t] = ratio;
+                    if (keep_cost) cost_s[t * nodes + o] = ok ? flow_cost2<B2>(w, r2) : 1.0f;
+                });
                 float logc = 0.f;
                 float a1 = 0.f;
 #pragma unroll
@@ -268,7 +278,9 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
         const int fpix = p.v * w.W + p.u;
         const float r0 = rho_full[fpix];
         prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, fpix, c, r0);
-        float bE = energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, r0), bV = r0;
+        float bE = keep_cost ? energy2_costs<PR>(w, B.P, B.prior, c, r0, cost_s + o, nodes)
+                             : energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, r0);
+        float bV = r0;
         int bS = 0;
         if (local) {
             const int U = min(p.u / w.s, w.wc - 1), V = min(p.v / w.s, w.hc - 1);
@@ -276,20 +288,30 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             const float e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, rc, bE);
             if (e < bE) { bE = e; bV = rc; bS = 2; }
         }
+        // the candidates of a draw are evaluated in groups of PG against the best before the
+        // group, then merged in slot order: the same winner and energy as one at a time.  With
+        // priors the per-pixel context is larger and single candidates keep more waves resident.
+        constexpr int PG = PR ? 1 : 4;
         for (int gi = 0; gi < G; ++gi) {
             const uint4 r = philox10(make_uint4((uint32_t)p.li, (uint32_t)gi, word2, w.window_id), w.key0, w.key1);
             const uint32_t words[4] = {r.x, r.y, r.z, r.w};
+            float cand[4], e[4];
+            unsigned live = 0u;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int slot = 3 + 4 * gi + m;
-                if (slot < w.K) {
-                    const float uu = unit24(words[m]);
-                    const float cand = (slot & 1)
-                        ? fminf(fmaxf(r0 * fmaf(w.sigma_it, fmaf(2.f, uu, -1.f), 1.f), w.rmin), w.rmax)
-                        : fmaf(uu, w.rmax - w.rmin, w.rmin);
-                    const float e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, cand, bE);
-                    if (e < bE) { bE = e; bV = cand; bS = slot; }
-                }
+                const float uu = unit24(words[m]);
+                cand[m] = (slot & 1) ? fminf(fmaxf(r0 * fmaf(w.sigma_it, fmaf(2.f, uu, -1.f), 1.f), w.rmin), w.rmax)
+                                     : fmaf(uu, w.rmax - w.rmin, w.rmin);
+                if (slot < w.K) live |= 1u << m;
+            }
+#pragma unroll
+            for (int h = 0; h < 4; h += PG) {
+                energy2_bounded_m<B2, PR, false, PG>(w, B.P, B.flow2, B.prior, c, cand + h,
+                                                     (live >> h) & ((1u << PG) - 1u), bE, e + h);
+#pragma unroll
+                for (int m = h; m < h + PG; ++m)
+                    if (((live >> m) & 1u) && e[m] < bE) { bE = e[m]; bV = cand[m]; bS = 3 + 4 * gi + m; }
             }
         }
         bestE[o] = bE; bestV[o] = bV; bestS[o] = bS; rcur[o] = r0;
@@ -309,11 +331,31 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
 #pragma unroll
         for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) c.q[t] = q_s[t * nodes + o];
         prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, c, rcur[o]);
-        for (int d = 0; d < g.spec; ++d) {
-            const int ip = p.i - (d + 1) * di;
-            if (ip < 0 || ip >= L) break;
-            specE[d * nodes + o] =
-                energy2_bounded<B2, PR, true>(w, B.P, B.flow2, B.prior, c, bestV[p.c * stride + ip], bestE[o]);
+        if constexpr (!PR) {
+            // two depths at a time, in lockstep against the pixel's phase-A energy
+            for (int d = 0; d < g.spec; d += 2) {
+                float cand[2], e[2];
+                unsigned live = 0u;
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const int ip = p.i - (d + m + 1) * di;
+                    const bool in = d + m < g.spec && ip >= 0 && ip < L;
+                    cand[m] = in ? bestV[p.c * stride + ip] : 0.f;
+                    if (in) live |= 1u << m;
+                }
+                if (live == 0u) break;
+                energy2_bounded_m<B2, PR, true, 2>(w, B.P, B.flow2, B.prior, c, cand, live, bestE[o], e);
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+                    if ((live >> m) & 1u) specE[(d + m) * nodes + o] = e[m];
+            }
+        } else {
+            for (int d = 0; d < g.spec; ++d) {
+                const int ip = p.i - (d + 1) * di;
+                if (ip < 0 || ip >= L) break;
+                specE[d * nodes + o] =
+                    energy2_bounded<B2, PR, true>(w, B.P, B.flow2, B.prior, c, bestV[p.c * stride + ip], bestE[o]);
+            }
         }
     }
     __syncthreads();
@@ -629,7 +671,7 @@ __device__ inline void pose_gn_solve(const double* red, PoseD& P) {
 
 template <bool B2>
 __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, int s, int G, int blk, unsigned nb) {
-    __shared__ double red[(VD_BLOCK / 64) * 29];
+    __shared__ double red[(VD_GN_BLOCK / 64) * 29];
     __shared__ PoseF curF, prevF;
     const int tid = threadIdx.x;
     const int t = s / G + 1, k = s - (t - 1) * G;
@@ -639,8 +681,8 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
     const float* __restrict__ idepth = B.idepth;
     const float* __restrict__ rig = B.rigid + (size_t)(t - 1) * plane;
     float2* __restrict__ obs = B.obs;
-    const int stride = (int)nb * VD_BLOCK;
-    constexpr int UB = 4;                  // pixels per thread and batch: loads issued together
+    const int stride = (int)nb * VD_GN_BLOCK;
+    constexpr int UB = VD_GN_PIX;          // pixels per thread and batch: loads issued together
     float rho[UB], q[UB], ox[UB], oy[UB];
     int jj[UB];
     auto load = [&](int j0) {
@@ -655,10 +697,10 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
             else if (t == 1) { const float2 f = flow_t[jc]; ox[b] = f.x; oy[b] = f.y; }
         }
     };
-    int j0 = blk * VD_BLOCK + tid;
+    int j0 = blk * VD_GN_BLOCK + tid;
     if (j0 < plane) load(j0);              // the first batch is in flight during the prologue
     if (s > 0) {
-        reduce_partials<29>(B.partials + (size_t)((s - 1) & 1) * 29 * nb, nb, red);
+        reduce_partials<29, VD_GN_BLOCK>(B.partials + (size_t)((s - 1) & 1) * 29 * nb, nb, red);
         if (tid == 0) {
             const int sp = s - 1, tp = sp / G + 1, kp = sp - (tp - 1) * G;
             PoseD P = (kp == 0) ? B.PD[tp - 1] : B.hist[sp - 1];
@@ -743,12 +785,12 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
     double acc[29];
 #pragma unroll
     for (int i = 0; i < 29; ++i) acc[i] = (double)a32[i];
-    block_reduce<29>(acc, red);
+    block_reduce<29, VD_GN_BLOCK>(acc, red);
     if (tid < 29) B.partials[((size_t)(s & 1) * 29 + tid) * nb + blk] = red[tid] * (tid == 0 ? (double)VD_LN2 : 1.0);
 }
 
 template <bool B2>
-__global__ void __launch_bounds__(VD_BLOCK) k_pose_gn(Win w, PoseBufs B, int s, int G) {
+__global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn(Win w, PoseBufs B, int s, int G) {
     pose_gn_body<B2>(w, B, s, G, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
@@ -806,7 +848,7 @@ __device__ __forceinline__ void finalize_body(const Win& w, const FinalBufs& B, 
         const float C = qs / (float)(w.N + w.P);
         B.conf[j] = C;
         int nv = 0;
-        emissions<B2>(w, B.P, B.flow2, c, rho, [&](int, float, bool ok) { nv += ok; });
+        emissions<B2>(w, B.P, B.flow2, c, rho, [&](int, float, bool ok, float) { nv += ok; });
         acc[0] = (double)energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, rho) * (double)VD_LN2;
         acc[1] = nv;
         acc[2] = w.N - nv;
@@ -877,7 +919,7 @@ __global__ void __launch_bounds__(VD_BLOCK) k_level_batch(const LevelItem* __res
 
 // Gauss-Newton step s of every window that has one (windows with fewer steps idle)
 template <bool B2>
-__global__ void __launch_bounds__(VD_BLOCK) k_pose_gn_batch(const PoseItem* __restrict__ items,
+__global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn_batch(const PoseItem* __restrict__ items,
                                                             const int* __restrict__ blk2item, int s) {
     const int gb = xcd_block(blockIdx.x, gridDim.x);
     const PoseItem& it = items[blk2item[gb]];
@@ -912,7 +954,8 @@ namespace vd {
 
 size_t level_lds_bytes(const LevelGeom& g) {
     const size_t nodes = (size_t)g.C * (g.seg + 1);
-    return (2 * VD_NMAX * nodes + (4 + (size_t)g.spec) * nodes) * sizeof(float) + nodes * sizeof(int);
+    return (2 * VD_NMAX * nodes + (4 + (size_t)g.spec) * nodes + (size_t)g.ncost * nodes) * sizeof(float) +
+           nodes * sizeof(int);
 }
 
 hipError_t set_level_lds_limit(size_t bytes) {
@@ -983,8 +1026,8 @@ hipError_t launch_phase_a2(const Win& w, const LevelGeom& g, const LevelBufs& b,
 }
 
 hipError_t launch_pose_gn(const Win& w, const PoseBufs& b, int s, int G, int nblocks, hipStream_t st) {
-    if (w.beta2) hipLaunchKernelGGL((k_pose_gn<true>), dim3(nblocks), dim3(VD_BLOCK), 0, st, w, b, s, G);
-    else hipLaunchKernelGGL((k_pose_gn<false>), dim3(nblocks), dim3(VD_BLOCK), 0, st, w, b, s, G);
+    if (w.beta2) hipLaunchKernelGGL((k_pose_gn<true>), dim3(nblocks), dim3(VD_GN_BLOCK), 0, st, w, b, s, G);
+    else hipLaunchKernelGGL((k_pose_gn<false>), dim3(nblocks), dim3(VD_GN_BLOCK), 0, st, w, b, s, G);
     return hipGetLastError();
 }
 
@@ -1051,8 +1094,8 @@ hipError_t launch_level_batch(const LevelItem* items, const int* blk2item, int n
 
 hipError_t launch_pose_gn_batch(const PoseItem* items, const int* blk2item, int nblocks, int s, bool b2,
                                 hipStream_t st) {
-    if (b2) hipLaunchKernelGGL((k_pose_gn_batch<true>), dim3(nblocks), dim3(VD_BLOCK), 0, st, items, blk2item, s);
-    else hipLaunchKernelGGL((k_pose_gn_batch<false>), dim3(nblocks), dim3(VD_BLOCK), 0, st, items, blk2item, s);
+    if (b2) hipLaunchKernelGGL((k_pose_gn_batch<true>), dim3(nblocks), dim3(VD_GN_BLOCK), 0, st, items, blk2item, s);
+    else hipLaunchKernelGGL((k_pose_gn_batch<false>), dim3(nblocks), dim3(VD_GN_BLOCK), 0, st, items, blk2item, s);
     return hipGetLastError();
 }
 

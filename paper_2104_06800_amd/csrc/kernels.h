@@ -18,7 +18,8 @@ struct LevelGeom {
     int C;             // chain segments per block
     int nseg;          // segments per line
     int nblocks;
-    int spec;          // speculation depth of the chain scan (1..4)
+    int spec;          // speculation depth of the chain scan
+    int ncost;         // frames of E-step costs kept for a fused pass's M-step (0: none)
 };
 
 struct LevelBufs {

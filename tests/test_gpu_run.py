@@ -153,3 +153,15 @@ def test_timers_count_bracketed_launches(lib):
     assert lib.timing_read(TIMER_LOCAL) == (0.0, 0)
     lib.run(p, b, iters=1)
     assert lib.timing_read(TIMER_LOCAL) == (0.0, 0)
+    # one class enabled: only its launches are bracketed
+    lib.timing(True, timers=(TIMER_POSE,))
+    lib.run(p, b, iters=2)
+    assert lib.timing_read(TIMER_POSE)[1] == 2
+    assert lib.timing_read(TIMER_LOCAL) == (0.0, 0) and lib.timing_read(TIMER_COARSE) == (0.0, 0)
+    lib.timing(False)
+
+
+def test_timing_rejects_bad_mask(lib):
+    from paper_2104_06800_amd import binding
+    assert binding._LIB.voldor_timing(lib._h, 8) == binding.EINVAL
+    assert binding._LIB.voldor_timing(lib._h, -1) == binding.EINVAL
