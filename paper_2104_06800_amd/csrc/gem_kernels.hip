@@ -290,8 +290,9 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
         }
         // the candidates of a draw are evaluated in groups of PG against the best before the
         // group, then merged in slot order: the same winner and energy as one at a time.  With
-        // priors the per-pixel context is larger and single candidates keep more waves resident.
-        constexpr int PG = PR ? 1 : 4;
+        // priors the per-pixel context is larger and single candidates keep more waves resident;
+        // groups of 4 hold too many registers for the gathers they overlap.
+        constexpr int PG = PR ? 1 : 2;
         for (int gi = 0; gi < G; ++gi) {
             const uint4 r = philox10(make_uint4((uint32_t)p.li, (uint32_t)gi, word2, w.window_id), w.key0, w.key1);
             const uint32_t words[4] = {r.x, r.y, r.z, r.w};
@@ -307,7 +308,7 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             }
 #pragma unroll
             for (int h = 0; h < 4; h += PG) {
-                energy2_bounded_m<B2, PR, false, PG>(w, B.P, B.flow2, B.prior, c, cand + h,
+                energy2_bounded_m<B2, PR, PG>(w, B.P, B.flow2, B.prior, c, cand + h,
                                                      (live >> h) & ((1u << PG) - 1u), bE, e + h);
 #pragma unroll
                 for (int m = h; m < h + PG; ++m)
@@ -331,31 +332,11 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
 #pragma unroll
         for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) c.q[t] = q_s[t * nodes + o];
         prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, c, rcur[o]);
-        if constexpr (!PR) {
-            // two depths at a time, in lockstep against the pixel's phase-A energy
-            for (int d = 0; d < g.spec; d += 2) {
-                float cand[2], e[2];
-                unsigned live = 0u;
-#pragma unroll
-                for (int m = 0; m < 2; ++m) {
-                    const int ip = p.i - (d + m + 1) * di;
-                    const bool in = d + m < g.spec && ip >= 0 && ip < L;
-                    cand[m] = in ? bestV[p.c * stride + ip] : 0.f;
-                    if (in) live |= 1u << m;
-                }
-                if (live == 0u) break;
-                energy2_bounded_m<B2, PR, true, 2>(w, B.P, B.flow2, B.prior, c, cand, live, bestE[o], e);
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-                    if ((live >> m) & 1u) specE[(d + m) * nodes + o] = e[m];
-            }
-        } else {
-            for (int d = 0; d < g.spec; ++d) {
-                const int ip = p.i - (d + 1) * di;
-                if (ip < 0 || ip >= L) break;
-                specE[d * nodes + o] =
-                    energy2_bounded<B2, PR, true>(w, B.P, B.flow2, B.prior, c, bestV[p.c * stride + ip], bestE[o]);
-            }
+        for (int d = 0; d < g.spec; ++d) {
+            const int ip = p.i - (d + 1) * di;
+            if (ip < 0 || ip >= L) break;
+            specE[d * nodes + o] =
+                energy2_bounded<B2, PR, true>(w, B.P, B.flow2, B.prior, c, bestV[p.c * stride + ip], bestE[o]);
         }
     }
     __syncthreads();
