@@ -343,9 +343,13 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
 
     // phase B: serial scan per chain, a group of 32 lanes per chain.  A speculation miss
     // evaluates E_i(carried) with the frame terms on separate lanes of the group
-    // (energy2_lanes), which equals the sequential evaluation bit for bit.
+    // (energy2_lanes), which equals the sequential evaluation bit for bit.  Without priors a
+    // miss evaluates the carried value at this node and the next LA - 1 nodes of the chain
+    // at once, one lane per (node, frame), each energy summed in frame order as energy2_lanes
+    // does; the next nodes use them while the same value is carried.
     {
         const int grp = tid >> 5, hl = tid & 31, hbase = tid & 32;
+        const int LA = 32 / w.N;                            // nodes per lookahead
         for (int c = grp; c < g.C; c += VD_BLOCK / 32) {
             const int L = chain_len(g, blk, c);
             if (L <= 0) continue;
@@ -353,6 +357,8 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             const int base = c * stride;
             float carried = bestV[base + i0];
             int src = i0;
+            int la_src = -1, la_i = 0;                      // lookahead: source node, first node
+            float la_e = 0.f;                               // lane m < LA: energy at node la_i + m*di
             if (hl == 0) newV[base + i0] = carried;
             for (int n = 1, i = i0 + di; n < L; ++n, i += di) {
                 const int o = base + i;
@@ -360,6 +366,32 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                 const int dist = (i - src) * di;           // steps back to the carried value's node
                 if (dist <= g.spec) {
                     e1 = specE[(dist - 1) * nodes + o];
+                } else if constexpr (!PR) {
+                    if (la_src != src || (i - la_i) * di >= LA) {
+                        la_src = src;
+                        la_i = i;
+                        const int m = hl / w.N, t = hl - m * w.N;
+                        const int im = i + m * di;
+                        float mine = 0.f;
+                        if (m < LA && im >= 0 && im < L) {
+                            const int kk = g.horizontal ? (c * g.seg + im) : (im * g.C + c);
+                            const BlockPix p = block_pix(g, blk, kk);
+                            Pix cx;
+                            pix_geometry<false>(w, B.P, B.flow, p.u, p.v, cx);
+                            mine = frame_cost<B2>(w, B.P, B.flow2, cx, carried, t);
+                        }
+                        const int mm = min(hl, LA - 1), imm = i + mm * di;
+                        const bool mine_node = hl < LA && imm >= 0 && imm < L;
+                        la_e = 0.f;
+#pragma unroll
+                        for (int tt = 0; tt < VD_NMAX; ++tt) {
+                            if (tt < w.N) {
+                                const float ct = __shfl(mine, hbase + mm * w.N + tt);
+                                if (mine_node) la_e = fmaf(q_s[tt * nodes + base + imm], ct, la_e);
+                            }
+                        }
+                    }
+                    e1 = __shfl(la_e, hbase + (i - la_i) * di);
                 } else {
                     // storage-order node i of chain c -> block linear index
                     const int kk = g.horizontal ? (c * g.seg + i) : (i * g.C + c);
