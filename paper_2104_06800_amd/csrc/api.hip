@@ -457,7 +457,7 @@ void plan_level(BPlan& P, const std::vector<BWin>& W, int mode, MakeItem make) {
             const size_t lat = (size_t)it.g.h * it.g.w;
             if (mode == 1) nb = (int)((lat * 4 + VD_BLOCK - 1) / VD_BLOCK);
             if (mode == 2) nb = (int)((lat * it.g.spec + VD_BLOCK - 1) / VD_BLOCK);
-            if (mode == 0) lds = std::max(lds, vd::level_lds_bytes(it.g));
+            if (mode == 0 || mode == 3) lds = std::max(lds, vd::level_lds_bytes(it.g));
             items.push_back(it);
             counts.push_back(nb);
         }
@@ -528,7 +528,7 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
         plan_level(P, W, 0, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 1, 0, false); });
         plan_level(P, W, 1, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 0, 1, false); });
         plan_level(P, W, 2, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 0, 1, false); });
-        plan_level(P, W, 0, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 0, 2, false); });
+        plan_level(P, W, 3, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 0, 2, false); });
         plan_level(P, W, 0, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_LOCAL, 1, 1, false); });
         // pose step: Gauss-Newton step s of the windows that have one
         std::vector<vd::PoseItem> all;

@@ -109,7 +109,7 @@ __device__ __forceinline__ int chain_len(const LevelGeom& g, int b, int c) {
     return min(g.seg, axis - sidx * g.seg);
 }
 
-template <bool B2, bool PR>
+template <bool B2, bool PR, bool FS = false>
 __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, const LevelBufs& B, int do_e, int do_m,
                                            int blk, float* lds) {
     const int stride = g.seg + 1;
@@ -357,15 +357,26 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             const int base = c * stride;
             float carried = bestV[base + i0];
             int src = i0;
+            int so = -nodes;                                // FS: (dist - 1) * nodes, kept incrementally
             int la_src = -1, la_i = 0;                      // lookahead: source node, first node
             float la_e = 0.f;                               // lane m < LA: energy at node la_i + m*di
             if (hl == 0) newV[base + i0] = carried;
             for (int n = 1, i = i0 + di; n < L; ++n, i += di) {
                 const int o = base + i;
+                // FS (scan-only launches, long chains): the node's phase-A result is read up front
+                // and the decision below is branch-free, which shortens the serial path per node
+                float eA = 0.f, vA = 0.f;
+                int sA = 0;
+                if constexpr (FS) {
+                    eA = bestE[o];
+                    vA = bestV[o];
+                    sA = bestS[o];
+                    so += nodes;
+                }
                 float e1;
-                const int dist = (i - src) * di;           // steps back to the carried value's node
+                const int dist = FS ? (fwd ? i - src : src - i) : (i - src) * di;  // steps back to the carried value's node
                 if (dist <= g.spec) {
-                    e1 = specE[(dist - 1) * nodes + o];
+                    e1 = FS ? specE[so + o] : specE[(dist - 1) * nodes + o];
                 } else if constexpr (!PR) {
                     if (la_src != src || (i - la_i) * di >= LA) {
                         la_src = src;
@@ -403,9 +414,16 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                     prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cx, rcur[o]);
                     e1 = energy2_lanes<B2, PR>(w, B.P, B.flow2, B.prior, cx, carried, hl, hbase);
                 }
-                const float eA = bestE[o];
-                const bool keep = (e1 < eA) || (e1 == eA && bestS[o] > 1);
-                if (!keep) { carried = bestV[o]; src = i; }
+                if constexpr (FS) {
+                    const bool keep = (e1 < eA) | ((e1 == eA) & (sA > 1));
+                    carried = keep ? carried : vA;
+                    src = keep ? src : i;
+                    so = keep ? so : -nodes;
+                } else {
+                    eA = bestE[o];
+                    const bool keep = (e1 < eA) || (e1 == eA && bestS[o] > 1);
+                    if (!keep) { carried = bestV[o]; src = i; }
+                }
                 if (hl == 0) newV[o] = carried;
             }
         }
@@ -418,11 +436,12 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
     }
 }
 
-template <bool B2, bool PR>
+// FS: the scan-only launch of a level with long chains (streamlined serial path)
+template <bool B2, bool PR, bool FS>
 __global__ void __launch_bounds__(VD_BLOCK)
 k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     extern __shared__ float lds[];
-    level_body<B2, PR>(w, g, B, do_e, do_m, xcd_block(blockIdx.x, gridDim.x), lds);
+    level_body<B2, PR, FS>(w, g, B, do_e, do_m, xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 // ----------------------------------------------------------------------------------
@@ -917,7 +936,7 @@ __global__ void __launch_bounds__(VD_BLOCK) k_setup_batch(const PrepItem* __rest
     flow_pairs_body(it.flow, it.flow2, it.N, it.w.H, it.w.W, blk);
 }
 
-// mode 0: fused level pass (do_e / do_m of the item); 1: phase A; 2: phase A2
+// mode 0: fused level pass (do_e / do_m of the item); 1: phase A; 2: phase A2; 3: scan only
 template <bool B2, bool PR, int MODE>
 __global__ void __launch_bounds__(VD_BLOCK) k_level_batch(const LevelItem* __restrict__ items,
                                                           const int* __restrict__ blk2item) {
@@ -926,6 +945,7 @@ __global__ void __launch_bounds__(VD_BLOCK) k_level_batch(const LevelItem* __res
     const LevelItem& it = items[blk2item[gb]];
     const int blk = gb - it.begin;
     if (MODE == 0) level_body<B2, PR>(it.w, it.g, it.b, it.do_e, it.do_m, blk, lds);
+    else if (MODE == 3) level_body<B2, PR, true>(it.w, it.g, it.b, it.do_e, it.do_m, blk, lds);
     else if (MODE == 1) phase_a_body<B2, PR>(it.w, it.g, it.b, blk);
     else phase_a2_body<B2, PR>(it.w, it.g, it.b, blk);
 }
@@ -972,10 +992,14 @@ size_t level_lds_bytes(const LevelGeom& g) {
 }
 
 hipError_t set_level_lds_limit(size_t bytes) {
-    const void* fns[8] = {(const void*)k_level<false, false>, (const void*)k_level<false, true>,
-                          (const void*)k_level<true, false>, (const void*)k_level<true, true>,
-                          (const void*)k_level_batch<false, false, 0>, (const void*)k_level_batch<false, true, 0>,
-                          (const void*)k_level_batch<true, false, 0>, (const void*)k_level_batch<true, true, 0>};
+    const void* fns[16] = {(const void*)k_level<false, false, false>, (const void*)k_level<false, true, false>,
+                           (const void*)k_level<true, false, false>, (const void*)k_level<true, true, false>,
+                           (const void*)k_level<false, false, true>, (const void*)k_level<false, true, true>,
+                           (const void*)k_level<true, false, true>, (const void*)k_level<true, true, true>,
+                           (const void*)k_level_batch<false, false, 0>, (const void*)k_level_batch<false, true, 0>,
+                           (const void*)k_level_batch<true, false, 0>, (const void*)k_level_batch<true, true, 0>,
+                           (const void*)k_level_batch<false, false, 3>, (const void*)k_level_batch<false, true, 3>,
+                           (const void*)k_level_batch<true, false, 3>, (const void*)k_level_batch<true, true, 3>};
     for (const void* f : fns) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
@@ -1005,11 +1029,17 @@ hipError_t launch_init(const Win& w, float* idepth, hipStream_t st) {
 hipError_t launch_level(const Win& w, const LevelGeom& g, const LevelBufs& b, int do_e, int do_m, hipStream_t st) {
     const size_t lds = level_lds_bytes(g);
     if (w.beta2) {
-        if (w.P > 0) hipLaunchKernelGGL((k_level<true, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
-        else hipLaunchKernelGGL((k_level<true, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+        if (do_m == 2) {
+            if (w.P > 0) hipLaunchKernelGGL((k_level<true, true, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+            else hipLaunchKernelGGL((k_level<true, false, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+        } else if (w.P > 0) hipLaunchKernelGGL((k_level<true, true, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+        else hipLaunchKernelGGL((k_level<true, false, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
     } else {
-        if (w.P > 0) hipLaunchKernelGGL((k_level<false, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
-        else hipLaunchKernelGGL((k_level<false, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+        if (do_m == 2) {
+            if (w.P > 0) hipLaunchKernelGGL((k_level<false, true, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+            else hipLaunchKernelGGL((k_level<false, false, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+        } else if (w.P > 0) hipLaunchKernelGGL((k_level<false, true, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
+        else hipLaunchKernelGGL((k_level<false, false, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
     }
     return hipGetLastError();
 }
@@ -1100,6 +1130,7 @@ static void level_batch_mode(const LevelItem* items, const int* b2i, int nb, siz
 hipError_t launch_level_batch(const LevelItem* items, const int* blk2item, int nblocks, size_t lds, int mode,
                               bool b2, bool pr, hipStream_t st) {
     if (mode == 0) level_batch_mode<0>(items, blk2item, nblocks, lds, b2, pr, st);
+    else if (mode == 3) level_batch_mode<3>(items, blk2item, nblocks, lds, b2, pr, st);
     else if (mode == 1) level_batch_mode<1>(items, blk2item, nblocks, 0, b2, pr, st);
     else level_batch_mode<2>(items, blk2item, nblocks, 0, b2, pr, st);
     return hipGetLastError();
