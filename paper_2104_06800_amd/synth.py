@@ -379,8 +379,13 @@ def make_window(cfg: int, k: int = 0, noise: bool = True, H=None, W=None, N=None
            one depth prior (5% multiplicative noise on depth, 10% holes), K=32, 10 iterations.
     cfg 4: the cfg-2 street recipe at 640x480 (intrinsics scaled), N=6.
     H, W, N override the size (cfg 2/3 recipes scale the intrinsics).
+    Initial poses: the true ones with a rotation error of up to 0.5 deg per axis and a
+    translation error of up to 5% (perturb); the street recipe shrinks both by
+    f_640 / f for focal lengths above f_640 = 720 * 640 / 1216 px, so the initial error
+    is the same in pixels as at 640x480.
     """
     rng = np.random.default_rng(1_000_000 * cfg + k)
+    pose_scale = 1.0
     if cfg == 1:
         H, W, N = H or 48, W or 64, N or 3
         intr = (50.0 * W / 64, 50.0 * W / 64, W / 2, H / 2)
@@ -400,6 +405,7 @@ def make_window(cfg: int, k: int = 0, noise: bool = True, H=None, W=None, N=None
             f0 = 720.0 * W / 1216
         intr = (f0, f0, W / 2, H / 2)
         scene = scene_street(rng, N, intr=intr, HW=(H, W))
+        pose_scale = min(1.0, (720.0 * 640 / 1216) / f0)
         Ts = traj_drive(rng, N)
         alpha, beta = 0.8, 2.0
         flow, rho_gt, dyn = render_window(scene, Ts, H, W, intr, rng, alpha, beta, noise)
@@ -418,7 +424,7 @@ def make_window(cfg: int, k: int = 0, noise: bool = True, H=None, W=None, N=None
     else:
         raise ValueError(f"unknown workload {cfg}")
     pose_gt = np.stack([_as6(T) for T in Ts[1:]])
-    pose_init = np.stack([_as6(perturb(rng, T)) for T in Ts[1:]])
+    pose_init = np.stack([_as6(perturb(rng, T, max_deg=0.5 * pose_scale, rel_t=0.05 * pose_scale)) for T in Ts[1:]])
     params["seed"] = int(rng.integers(0, 2 ** 63))
     params.update(kw)
     out = dict(params=params, flow=flow.astype(np.float32), pose_gt=pose_gt,
