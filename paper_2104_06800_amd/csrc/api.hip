@@ -399,7 +399,7 @@ int run_window(GemLaunch& L, int first, int n_iters, int flags) {
 // ---- batched run: every window's scratch lives at once; each step of the launch sequence
 // is one launch per (shape class) over all windows, driven by item tables in device memory
 
-enum BKind { BK_PREP, BK_SETUP, BK_LEVEL, BK_POSE, BK_POSE_FINISH, BK_FINAL, BK_FINAL_FINISH };
+enum BKind { BK_PREP, BK_SETUP, BK_LEVEL, BK_POSE, BK_POSE_SOLVE, BK_FINAL, BK_FINAL_FINISH };
 
 struct BLaunch {
     int kind;
@@ -559,8 +559,12 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
                 const size_t io = P.put(items), bo = P.put(b2i);
                 P.add(BK_POSE, io, bo, (int)items.size(), (int)b2i.size(), 0, 0, s, b2 != 0);
             }
+            // step s's solve, one block per window that has the step
+            std::vector<vd::PoseItem> act;
+            for (size_t i = 0; i < W.size(); ++i)
+                if (s < all[i].S) act.push_back(all[i]);
+            P.add(BK_POSE_SOLVE, P.put(act), 0, (int)act.size(), (int)act.size(), 0, 0, s);
         }
-        if (maxS > 0) P.add(BK_POSE_FINISH, P.put(all), 0, (int)all.size(), (int)all.size());
     }
     // final E-step, confidence and statistics
     P.add(BK_PREP, prep_off, 0, (int)W.size(), (int)W.size());
@@ -620,7 +624,7 @@ int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st
             e = vd::launch_level_batch((const vd::LevelItem*)items, b2i, l.nblocks, l.lds, l.mode, l.b2, l.pr, st);
             break;
         case BK_POSE: e = vd::launch_pose_gn_batch((const vd::PoseItem*)items, b2i, l.nblocks, l.s, l.b2, st); break;
-        case BK_POSE_FINISH: e = vd::launch_pose_gn_finish_batch((const vd::PoseItem*)items, l.n_items, st); break;
+        case BK_POSE_SOLVE: e = vd::launch_pose_gn_solve_batch((const vd::PoseItem*)items, l.n_items, l.s, st); break;
         case BK_FINAL: e = vd::launch_finalize_batch((const vd::FinalItem*)items, b2i, l.nblocks, l.b2, l.pr, st); break;
         case BK_FINAL_FINISH: e = vd::launch_finalize_finish_batch((const vd::FinalItem*)items, l.n_items, st); break;
         }

@@ -701,7 +701,11 @@ __device__ inline void pose_gn_solve(const double* red, PoseD& P) {
     if (chol6_solve(H, gv, x)) left_update_d(&P, x);      // singular: pose unchanged
 }
 
-template <bool B2>
+// SPLIT (batched launches): no prologue solve; the pose of step s-1 is read from hist[s-1],
+// stored there by the one-block solve launch that follows each pass (pose_gn_solve_body).
+// Many windows' blocks share the chip there, and re-reducing every window's records in each
+// of its blocks would cost more than the extra launch.
+template <bool B2, bool SPLIT = false>
 __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, int s, int G, int blk, unsigned nb) {
     __shared__ double red[(VD_GN_BLOCK / 64) * 29];
     __shared__ PoseF curF, prevF;
@@ -731,7 +735,16 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
     };
     int j0 = blk * VD_GN_BLOCK + tid;
     if (j0 < plane) load(j0);              // the first batch is in flight during the prologue
-    if (s > 0) {
+    if constexpr (SPLIT) {
+        if (tid == 0) {
+            if (k > 0) {
+                posef_from_d(B.hist[s - 1], &curF);
+            } else {
+                curF = B.P[t - 1];
+                if (t > 1) posef_from_d(B.hist[s - 1], &prevF);
+            }
+        }
+    } else if (s > 0) {
         reduce_partials<29, VD_GN_BLOCK>(B.partials + (size_t)((s - 1) & 1) * 29 * nb, nb, red);
         if (tid == 0) {
             const int sp = s - 1, tp = sp / G + 1, kp = sp - (tp - 1) * G;
@@ -824,6 +837,32 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
 template <bool B2>
 __global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn(Win w, PoseBufs B, int s, int G) {
     pose_gn_body<B2>(w, B, s, G, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// Step s's solve (one block, the same fixed-order reduction and solve as the prologue of the
+// unsplit pass); after the window's last step, every frame's final pose into the FP32 /
+// FP64 tables and the caller's 6-vectors.
+__device__ __forceinline__ void pose_gn_solve_body(const PoseBufs& B, int N, int G, int s, unsigned nb) {
+    __shared__ double red[(VD_BLOCK / 64) * 29];
+    reduce_partials<29>(B.partials + (size_t)(s & 1) * 29 * nb, nb, red);
+    const int t = s / G + 1, k = s - (t - 1) * G;
+    if (threadIdx.x == 0) {
+        PoseD P = k == 0 ? B.PD[t - 1] : B.hist[s - 1];
+        pose_gn_solve(red, P);
+        B.hist[s] = P;
+    }
+    if (s < N * G - 1) return;
+    __syncthreads();
+    const int i = threadIdx.x;
+    if (i < N) {
+        const PoseD P = B.hist[(i + 1) * G - 1];
+        B.PD[i] = P;
+        posef_from_d(P, B.P + i);
+        log_so3(P.R, B.pose + 6 * i);
+        B.pose[6 * i + 3] = P.t[0];
+        B.pose[6 * i + 4] = P.t[1];
+        B.pose[6 * i + 5] = P.t[2];
+    }
 }
 
 // Last step's solve, then every frame's final pose into the FP32 / FP64 copies and the
@@ -957,12 +996,13 @@ __global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn_batch(const PoseItem* _
     const int gb = xcd_block(blockIdx.x, gridDim.x);
     const PoseItem& it = items[blk2item[gb]];
     if (s >= it.S) return;
-    pose_gn_body<B2>(it.w, it.b, s, it.G, gb - it.begin, (unsigned)it.nblocks);
+    pose_gn_body<B2, true>(it.w, it.b, s, it.G, gb - it.begin, (unsigned)it.nblocks);
 }
 
-__global__ void __launch_bounds__(VD_BLOCK) k_pose_gn_finish_batch(const PoseItem* __restrict__ items) {
+// step s's solve of every window that has the step, one block per window
+__global__ void __launch_bounds__(VD_BLOCK) k_pose_gn_solve_batch(const PoseItem* __restrict__ items, int s) {
     const PoseItem& it = items[blockIdx.x];
-    if (it.S > 0) pose_gn_finish_body(it.b, it.w.N, it.G, (unsigned)it.nblocks);
+    if (s < it.S) pose_gn_solve_body(it.b, it.w.N, it.G, s, (unsigned)it.nblocks);
 }
 
 template <bool B2, bool PR>
@@ -1143,8 +1183,8 @@ hipError_t launch_pose_gn_batch(const PoseItem* items, const int* blk2item, int 
     return hipGetLastError();
 }
 
-hipError_t launch_pose_gn_finish_batch(const PoseItem* items, int n_items, hipStream_t st) {
-    hipLaunchKernelGGL(k_pose_gn_finish_batch, dim3((unsigned)n_items), dim3(VD_BLOCK), 0, st, items);
+hipError_t launch_pose_gn_solve_batch(const PoseItem* items, int n_items, int s, hipStream_t st) {
+    hipLaunchKernelGGL(k_pose_gn_solve_batch, dim3((unsigned)n_items), dim3(VD_BLOCK), 0, st, items, s);
     return hipGetLastError();
 }
 

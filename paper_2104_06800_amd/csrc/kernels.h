@@ -153,7 +153,7 @@ hipError_t launch_level_batch(const LevelItem* items, const int* blk2item, int n
                               bool b2, bool pr, hipStream_t st);
 hipError_t launch_pose_gn_batch(const PoseItem* items, const int* blk2item, int nblocks, int s, bool b2,
                                 hipStream_t st);
-hipError_t launch_pose_gn_finish_batch(const PoseItem* items, int n_items, hipStream_t st);
+hipError_t launch_pose_gn_solve_batch(const PoseItem* items, int n_items, int s, hipStream_t st);
 hipError_t launch_finalize_batch(const FinalItem* items, const int* blk2item, int nblocks, bool b2, bool pr,
                                  hipStream_t st);
 hipError_t launch_finalize_finish_batch(const FinalItem* items, int n_items, hipStream_t st);
