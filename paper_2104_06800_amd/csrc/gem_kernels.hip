@@ -689,13 +689,17 @@ k_pose_finish(PoseBufs B, int t, unsigned nb, int solve) {
 // pose; the observation o_t = p_{t-1} + X_t(p_{t-1}) is formed at k = 0 and stored as a
 // displacement from the pixel (NaN when invalid) for the frame's later steps.
 // ----------------------------------------------------------------------------------
+// A Gauss-Newton record holds the normal equations only: H (upper triangle, 21 values)
+// then g (6 values); the energy and term count of the pose score are not needed here.
+constexpr int kGnRec = 27;
+
 __device__ inline void pose_gn_solve(const double* red, PoseD& P) {
     double H[36], gv[6], x[6];
-    int k = 1;
+    int k = 0;
     for (int i = 0; i < 6; ++i)
         for (int l = i; l < 6; ++l) { H[6 * i + l] = H[6 * l + i] = red[k++]; }
     double tr = 0.0;
-    for (int i = 0; i < 6; ++i) { gv[i] = -red[22 + i]; tr += H[7 * i]; }
+    for (int i = 0; i < 6; ++i) { gv[i] = -red[21 + i]; tr += H[7 * i]; }
     const double lam = 1e-9 * tr / 6.0;
     for (int i = 0; i < 6; ++i) H[7 * i] += lam;
     if (chol6_solve(H, gv, x)) left_update_d(&P, x);      // singular: pose unchanged
@@ -745,7 +749,7 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
             }
         }
     } else if (s > 0) {
-        reduce_partials<29, VD_GN_BLOCK>(B.partials + (size_t)((s - 1) & 1) * 29 * nb, nb, red);
+        reduce_partials<kGnRec, VD_GN_BLOCK>(B.partials + (size_t)((s - 1) & 1) * kGnRec * nb, nb, red);
         if (tid == 0) {
             const int sp = s - 1, tp = sp / G + 1, kp = sp - (tp - 1) * G;
             PoseD P = (kp == 0) ? B.PD[tp - 1] : B.hist[sp - 1];
@@ -762,9 +766,9 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
     __syncthreads();
     const PoseF Tc = curF;
     // per-thread sums in FP32 (a thread covers a few pixels), FP64 across threads and blocks
-    float a32[29];
+    float a32[kGnRec];
 #pragma unroll
-    for (int i = 0; i < 29; ++i) a32[i] = 0.f;
+    for (int i = 0; i < kGnRec; ++i) a32[i] = 0.f;
     while (j0 < plane) {
         if (k == 0 && t > 1) {
             const PoseF& Tp = prevF;
@@ -806,32 +810,30 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
             const bool ok = zok && isfinite(ox[b]) && isfinite(oy[b]) && in_frame(w, (float)u + dx, (float)v + dy);
             const float ex = dx - ox[b], ey = dy - oy[b];
             const float r2 = fmaf(ex, ex, ey * ey);
-            a32[0] = fmaf(q[b], ok ? flow_cost2<B2>(w, r2) : 1.0f, a32[0]);
             if (ok) {
                 const float wt = q[b] * flow_dcost<B2>(w, r2);
                 const float a = w.fx * iz, bb = -w.fx * Qx * iz * iz;
                 const float c = w.fy * iz, d = -w.fy * Qy * iz * iz;
                 const float jx[6] = {bb * Qy, a * Qz - bb * Qx, -a * Qy, a * r, 0.f, bb * r};
                 const float jy[6] = {d * Qy - c * Qz, -d * Qx, c * Qx, 0.f, c * r, d * r};
-                int m = 1;
+                int m = 0;
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
                     const float wxi = wt * jx[i], wyi = wt * jy[i];
 #pragma unroll
                     for (int l = i; l < 6; ++l) { a32[m] = fmaf(wxi, jx[l], fmaf(wyi, jy[l], a32[m])); ++m; }
-                    a32[22 + i] = fmaf(wxi, ex, fmaf(wyi, ey, a32[22 + i]));
+                    a32[21 + i] = fmaf(wxi, ex, fmaf(wyi, ey, a32[21 + i]));
                 }
-                a32[28] += 1.f;
             }
         }
         j0 += UB * stride;
         if (j0 < plane) load(j0);
     }
-    double acc[29];
+    double acc[kGnRec];
 #pragma unroll
-    for (int i = 0; i < 29; ++i) acc[i] = (double)a32[i];
-    block_reduce<29, VD_GN_BLOCK>(acc, red);
-    if (tid < 29) B.partials[((size_t)(s & 1) * 29 + tid) * nb + blk] = red[tid] * (tid == 0 ? (double)VD_LN2 : 1.0);
+    for (int i = 0; i < kGnRec; ++i) acc[i] = (double)a32[i];
+    block_reduce<kGnRec, VD_GN_BLOCK>(acc, red);
+    if (tid < kGnRec) B.partials[((size_t)(s & 1) * kGnRec + tid) * nb + blk] = red[tid];
 }
 
 template <bool B2>
@@ -844,7 +846,7 @@ __global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn(Win w, PoseBufs B, int 
 // FP64 tables and the caller's 6-vectors.
 __device__ __forceinline__ void pose_gn_solve_body(const PoseBufs& B, int N, int G, int s, unsigned nb) {
     __shared__ double red[(VD_BLOCK / 64) * 29];
-    reduce_partials<29>(B.partials + (size_t)(s & 1) * 29 * nb, nb, red);
+    reduce_partials<kGnRec>(B.partials + (size_t)(s & 1) * kGnRec * nb, nb, red);
     const int t = s / G + 1, k = s - (t - 1) * G;
     if (threadIdx.x == 0) {
         PoseD P = k == 0 ? B.PD[t - 1] : B.hist[s - 1];
@@ -870,7 +872,7 @@ __device__ __forceinline__ void pose_gn_solve_body(const PoseBufs& B, int N, int
 __device__ __forceinline__ void pose_gn_finish_body(const PoseBufs& B, int N, int G, unsigned nb) {
     __shared__ double red[(VD_BLOCK / 64) * 29];
     const int S = N * G;
-    reduce_partials<29>(B.partials + (size_t)((S - 1) & 1) * 29 * nb, nb, red);
+    reduce_partials<kGnRec>(B.partials + (size_t)((S - 1) & 1) * kGnRec * nb, nb, red);
     if (threadIdx.x == 0) {
         const int sp = S - 1, tp = sp / G + 1, kp = sp - (tp - 1) * G;
         PoseD P = (kp == 0) ? B.PD[tp - 1] : B.hist[sp - 1];
