@@ -353,7 +353,7 @@ def learned_init(lib, np, torch):
     t0 = time.time()
     test = pr.generate(list(range(pr.TEST_SEED0, pr.TEST_SEED0 + 16)), 16)
     log(f"learned init: {len(test)} held-out windows generated in {time.time() - t0:.1f}s")
-    res = pr.compare(lib, net, test)
+    res = pr.compare(lib, net, test, warm=False)
     summ = pr.summarize(res)
     log("learned init: " + json.dumps(summ))
     # proposal forward: MFMA throughput of the whole network at 640x480
