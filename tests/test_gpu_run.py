@@ -123,6 +123,24 @@ def test_batch_graph_replay_and_direct_launches_agree(lib):
             assert_same(host(b), r)
 
 
+def test_batch_run_with_uneven_pose_steps_equals_individual_runs(lib):
+    """Windows with 0, 1 and 3 Gauss-Newton steps per frame (different step counts N*G):
+    the batched pose passes and per-step solves cover only the windows that have step s."""
+    ws = [synth.make_window(1, 20), synth.make_window(1, 21, H=40, W=52, N=5),
+          synth.make_window(3, 22, H=36, W=48, N=4)]
+    for w, G in zip(ws, (1, 3, 0)):
+        w["params"]["pose_gn_steps"] = G
+    iters = 2
+    single = [(w["params"], alloc(lib, w)) for w in ws]
+    for p, b in single:
+        lib.run(p, b, iters=iters)
+    batch = [(w["params"], alloc(lib, w)) for w in ws]
+    print("pose steps per window", [p["N"] * p["pose_gn_steps"] for p, _ in batch], flush=True)
+    lib.batch_run(batch, iters)
+    for (_, x), (_, y) in zip(batch, single):
+        assert_same(host(x), host(y))
+
+
 def test_batch_run_rejects_bad_arguments(lib):
     from paper_2104_06800_amd.binding import VoldorError
     ws = windows()[:2]
