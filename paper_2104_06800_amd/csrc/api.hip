@@ -525,7 +525,7 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
             x.do_m = do_m;
             return x;
         };
-        plan_level(P, W, 0, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 1, 0, false); });
+        plan_level(P, W, 3, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 1, 0, false); });
         plan_level(P, W, 1, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 0, 1, false); });
         plan_level(P, W, 2, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 0, 1, false); });
         plan_level(P, W, 3, [&](const GemLaunch& L) { return item(L, VOLDOR_LEVEL_COARSE, 0, 2, false); });

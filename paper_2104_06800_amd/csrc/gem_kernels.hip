@@ -109,7 +109,121 @@ __device__ __forceinline__ int chain_len(const LevelGeom& g, int b, int c) {
     return min(g.seg, axis - sidx * g.seg);
 }
 
-template <bool B2, bool PR, bool FS = false>
+// ----------------------------------------------------------------------------------
+// Forward-backward on long chains as a segmented scan (sec. III-A, the two-state chain
+// of the rigidness maps).  Both recursions are linear in the unnormalised state
+// (alpha, 1 - alpha): the forward step of node i is diag(r_i, 1) T and the backward
+// step into node i - 1 is T diag(r_i, 1), with T = [[g, 1 - g], [1 - g, g]] the
+// transition matrix.  A group of G lanes splits a chain into G segments; each lane
+// composes its segment's 2x2 matrices, the group scans them (prefix for the forward
+// pass, suffix for the backward), and each lane then runs the ordinary normalised
+// recursion over its own nodes from the state that enters the segment.  The result
+// equals the serial recursion up to rounding; the serial path per chain drops from 2L
+// steps to about 4L/G + 2 log2 G.
+// ----------------------------------------------------------------------------------
+struct Mat2 {
+    float a, b, c, d;  // [[a b] [c d]]
+};
+
+// x y scaled to unit entry sum (all entries are non-negative, the sum is positive)
+__device__ __forceinline__ Mat2 mat2_mul(const Mat2& x, const Mat2& y) {
+    Mat2 z;
+    z.a = fmaf(x.a, y.a, x.b * y.c);
+    z.b = fmaf(x.a, y.b, x.b * y.d);
+    z.c = fmaf(x.c, y.a, x.d * y.c);
+    z.d = fmaf(x.c, y.b, x.d * y.d);
+    const float s = rcp((z.a + z.b) + (z.c + z.d));
+    z.a *= s; z.b *= s; z.c *= s; z.d *= s;
+    return z;
+}
+
+__device__ __forceinline__ Mat2 mat2_shfl_up(const Mat2& x, int d, int G) {
+    return {__shfl_up(x.a, d, G), __shfl_up(x.b, d, G), __shfl_up(x.c, d, G), __shfl_up(x.d, d, G)};
+}
+
+__device__ __forceinline__ Mat2 mat2_shfl_down(const Mat2& x, int d, int G) {
+    return {__shfl_down(x.a, d, G), __shfl_down(x.b, d, G), __shfl_down(x.c, d, G), __shfl_down(x.d, d, G)};
+}
+
+// chain (c, t) of the block: emission ratios r_s in, posteriors q_s out ([N][C][stride]);
+// returns this lane's share of the chain log-likelihood.  Every lane of a group takes the
+// same branches up to the shuffles (G is a power of two, groups never straddle a wave).
+__device__ __forceinline__ double chain_fb_scan(const Win& w, const LevelGeom& g, int blk, const float* r_s,
+                                                float* q_s, int nodes, int stride) {
+    const int nch = g.C * w.N;
+    int G = 64;
+    while (G > 1 && G * nch > VD_BLOCK) G >>= 1;
+    const int tid = threadIdx.x;
+    if (tid >= G * nch) return 0.0;
+    const int j = tid / G, lane = tid & (G - 1);
+    const int c = j % g.C, t = j / g.C;
+    const int L = chain_len(g, blk, c);
+    if (L <= 0) return 0.0;
+    const int sl = (L + G - 1) / G;
+    const int s0 = min(L, lane * sl), s1 = min(L, s0 + sl);
+    const float* r = r_s + t * nodes + c * stride;
+    float* a = q_s + t * nodes + c * stride;
+    const float gm = w.gamma, gc = 1.f - w.gamma, h = 2.f * w.gamma - 1.f;
+
+    // forward: the segment's map, then the prefix over the group
+    Mat2 F = {1.f, 0.f, 0.f, 1.f};
+    for (int i = s0; i < s1; ++i) {
+        const float ri = r[i];
+        const Mat2 M = {ri * gm, ri * gc, gc, gm};
+        F = mat2_mul(M, F);
+    }
+    for (int d = 1; d < G; d <<= 1) {
+        const Mat2 X = mat2_shfl_up(F, d, G);
+        if (lane >= d) F = mat2_mul(F, X);
+    }
+    const Mat2 Fin = mat2_shfl_up(F, 1, G);
+    float a1 = 0.5f;  // the state before node 0 gives the prior 1/2
+    if (lane > 0) {
+        const float v1 = Fin.a + Fin.b, v0 = Fin.c + Fin.d;
+        a1 = v1 * rcp(v1 + v0);
+    }
+    float logc = 0.f;
+    for (int i = s0; i < s1; ++i) {
+        const float p1 = (i == 0) ? 0.5f : fmaf(h, a1, gc);
+        const float x1 = p1 * r[i];
+        const float cc = (1.f - p1) + x1;
+        a1 = x1 * rcp(cc);
+        a[i] = a1;
+        logc += log2f_fast(cc);
+    }
+
+    // backward: the segment's map (its nodes' ratios, last node first), then the suffix
+    Mat2 Bk = {1.f, 0.f, 0.f, 1.f};
+    for (int i = s1 - 1; i >= s0; --i) {
+        const float ri = r[i];
+        const Mat2 M = {gm * ri, gc, gc * ri, gm};
+        Bk = mat2_mul(M, Bk);
+    }
+    for (int d = 1; d < G; d <<= 1) {
+        const Mat2 X = mat2_shfl_down(Bk, d, G);
+        if (lane + d < G) Bk = mat2_mul(Bk, X);
+    }
+    const Mat2 Bin = mat2_shfl_down(Bk, 1, G);
+    float b1 = 0.5f;  // the last node's backward message
+    if (lane < G - 1) {
+        const float v1 = Bin.a + Bin.b, v0 = Bin.c + Bin.d;
+        b1 = v1 * rcp(v1 + v0);
+    }
+    for (int i = s1 - 1; i >= s0; --i) {
+        if (i < s1 - 1) {
+            const float m0 = 1.f - b1, m1 = r[i + 1] * b1;
+            const float y1 = fmaf(gm, m1, gc * m0);
+            const float y0 = fmaf(gm, m0, gc * m1);
+            b1 = y1 * rcp(y0 + y1);
+        }
+        const float ai = a[i];
+        const float num = ai * b1;
+        a[i] = num * rcp(fmaf(1.f - ai, 1.f - b1, num));
+    }
+    return (double)(logc * VD_LN2) + (double)(s1 - s0) * (double)w.ln_L0;
+}
+
+template <bool B2, bool PR, bool LC = false>
 __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, const LevelBufs& B, int do_e, int do_m,
                                            int blk, float* lds) {
     const int stride = g.seg + 1;
@@ -186,7 +300,9 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             }
         }
         __syncthreads();
-        if (w.chain_axis == 0 && tid < g.C * w.N) {
+        if constexpr (LC) {
+            if (w.chain_axis == 0) ll += chain_fb_scan(w, g, blk, r_s, q_s, nodes, stride);
+        } else if (w.chain_axis == 0 && tid < g.C * w.N) {
             const int c = tid % g.C, t = tid / g.C;
             const int L = chain_len(g, blk, c);
             if (L > 0) {
@@ -357,26 +473,26 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             const int base = c * stride;
             float carried = bestV[base + i0];
             int src = i0;
-            int so = -nodes;                                // FS: (dist - 1) * nodes, kept incrementally
+            int so = -nodes;                                // LC: (dist - 1) * nodes, kept incrementally
             int la_src = -1, la_i = 0;                      // lookahead: source node, first node
             float la_e = 0.f;                               // lane m < LA: energy at node la_i + m*di
             if (hl == 0) newV[base + i0] = carried;
             for (int n = 1, i = i0 + di; n < L; ++n, i += di) {
                 const int o = base + i;
-                // FS (scan-only launches, long chains): the node's phase-A result is read up front
+                // LC (scan-only launches, long chains): the node's phase-A result is read up front
                 // and the decision below is branch-free, which shortens the serial path per node
                 float eA = 0.f, vA = 0.f;
                 int sA = 0;
-                if constexpr (FS) {
+                if constexpr (LC) {
                     eA = bestE[o];
                     vA = bestV[o];
                     sA = bestS[o];
                     so += nodes;
                 }
                 float e1;
-                const int dist = FS ? (fwd ? i - src : src - i) : (i - src) * di;  // steps back to the carried value's node
+                const int dist = LC ? (fwd ? i - src : src - i) : (i - src) * di;  // steps back to the carried value's node
                 if (dist <= g.spec) {
-                    e1 = FS ? specE[so + o] : specE[(dist - 1) * nodes + o];
+                    e1 = LC ? specE[so + o] : specE[(dist - 1) * nodes + o];
                 } else if constexpr (!PR) {
                     if (la_src != src || (i - la_i) * di >= LA) {
                         la_src = src;
@@ -414,7 +530,7 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                     prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cx, rcur[o]);
                     e1 = energy2_lanes<B2, PR>(w, B.P, B.flow2, B.prior, cx, carried, hl, hbase);
                 }
-                if constexpr (FS) {
+                if constexpr (LC) {
                     const bool keep = (e1 < eA) | ((e1 == eA) & (sA > 1));
                     carried = keep ? carried : vA;
                     src = keep ? src : i;
@@ -436,12 +552,13 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
     }
 }
 
-// FS: the scan-only launch of a level with long chains (streamlined serial path)
-template <bool B2, bool PR, bool FS>
+// LC: the E-only and scan-only launches of a level with few long chains (the coarse
+// lattice): forward-backward as a segmented scan, and the streamlined serial scan
+template <bool B2, bool PR, bool LC>
 __global__ void __launch_bounds__(VD_BLOCK)
 k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     extern __shared__ float lds[];
-    level_body<B2, PR, FS>(w, g, B, do_e, do_m, xcd_block(blockIdx.x, gridDim.x), lds);
+    level_body<B2, PR, LC>(w, g, B, do_e, do_m, xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
 // ----------------------------------------------------------------------------------
@@ -977,7 +1094,8 @@ __global__ void __launch_bounds__(VD_BLOCK) k_setup_batch(const PrepItem* __rest
     flow_pairs_body(it.flow, it.flow2, it.N, it.w.H, it.w.W, blk);
 }
 
-// mode 0: fused level pass (do_e / do_m of the item); 1: phase A; 2: phase A2; 3: scan only
+// mode 0: fused level pass (do_e / do_m of the item); 1: phase A; 2: phase A2; 3: E-only or
+// scan-only pass of the coarse level (long chains)
 template <bool B2, bool PR, int MODE>
 __global__ void __launch_bounds__(VD_BLOCK) k_level_batch(const LevelItem* __restrict__ items,
                                                           const int* __restrict__ blk2item) {
@@ -1070,14 +1188,15 @@ hipError_t launch_init(const Win& w, float* idepth, hipStream_t st) {
 
 hipError_t launch_level(const Win& w, const LevelGeom& g, const LevelBufs& b, int do_e, int do_m, hipStream_t st) {
     const size_t lds = level_lds_bytes(g);
+    const bool lc = do_m == 2 || (w.level == 0 && do_m == 0);
     if (w.beta2) {
-        if (do_m == 2) {
+        if (lc) {
             if (w.P > 0) hipLaunchKernelGGL((k_level<true, true, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
             else hipLaunchKernelGGL((k_level<true, false, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
         } else if (w.P > 0) hipLaunchKernelGGL((k_level<true, true, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
         else hipLaunchKernelGGL((k_level<true, false, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
     } else {
-        if (do_m == 2) {
+        if (lc) {
             if (w.P > 0) hipLaunchKernelGGL((k_level<false, true, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
             else hipLaunchKernelGGL((k_level<false, false, true>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
         } else if (w.P > 0) hipLaunchKernelGGL((k_level<false, true, false>), dim3(g.nblocks), dim3(VD_BLOCK), lds, st, w, g, b, do_e, do_m);
