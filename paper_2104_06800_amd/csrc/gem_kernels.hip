@@ -466,81 +466,181 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
     {
         const int grp = tid >> 5, hl = tid & 31, hbase = tid & 32;
         const int LA = 32 / w.N;                            // nodes per lookahead
-        for (int c = grp; c < g.C; c += VD_BLOCK / 32) {
-            const int L = chain_len(g, blk, c);
-            if (L <= 0) continue;
-            const int i0 = fwd ? 0 : L - 1;
-            const int base = c * stride;
-            float carried = bestV[base + i0];
-            int src = i0;
-            int so = -nodes;                                // LC: (dist - 1) * nodes, kept incrementally
-            int la_src = -1, la_i = 0;                      // lookahead: source node, first node
-            float la_e = 0.f;                               // lane m < LA: energy at node la_i + m*di
-            if (hl == 0) newV[base + i0] = carried;
-            for (int n = 1, i = i0 + di; n < L; ++n, i += di) {
-                const int o = base + i;
-                // LC (scan-only launches, long chains): the node's phase-A result is read up front
-                // and the decision below is branch-free, which shortens the serial path per node
-                float eA = 0.f, vA = 0.f;
-                int sA = 0;
-                if constexpr (LC) {
-                    eA = bestE[o];
-                    vA = bestV[o];
-                    sA = bestS[o];
-                    so += nodes;
+        if constexpr (LC) {
+            // Long chains: the serial path visits only the nodes whose phase-A result replaces
+            // the carried value.  Every node first finds, from the speculative energies and in
+            // parallel, the next node that would replace its phase-A result within the
+            // speculation depth (-1: none there, -2: none up to the chain end).  A walk per
+            // chain then hops from replacement to replacement; a value that outlives the
+            // speculation depth is evaluated at the following nodes as in the scan below.
+            // The decisions are those of the node-by-node scan, bit for bit.
+            int* nxt = (int*)r_s;                           // [C][stride]; the E-step ratios are dead here
+            for (int k = tid; k < npix; k += VD_BLOCK) {
+                const BlockPix p = block_pix(g, blk, k);
+                if (!p.valid) continue;
+                const int L = chain_len(g, blk, p.c);
+                const int base = p.c * stride;
+                const int pos = fwd ? p.i : L - 1 - p.i;    // steps from the chain start
+                int nx = -1;
+                for (int d = 1; d <= g.spec; ++d) {
+                    if (pos + d >= L) { nx = -2; break; }
+                    const int j = p.i + d * di;
+                    const float e1 = specE[(d - 1) * nodes + base + j], eA = bestE[base + j];
+                    if (!((e1 < eA) || (e1 == eA && bestS[base + j] > 1))) { nx = j; break; }
                 }
-                float e1;
-                const int dist = LC ? (fwd ? i - src : src - i) : (i - src) * di;  // steps back to the carried value's node
-                if (dist <= g.spec) {
-                    e1 = LC ? specE[so + o] : specE[(dist - 1) * nodes + o];
-                } else if constexpr (!PR) {
-                    if (la_src != src || (i - la_i) * di >= LA) {
-                        la_src = src;
-                        la_i = i;
-                        const int m = hl / w.N, t = hl - m * w.N;
-                        const int im = i + m * di;
-                        float mine = 0.f;
-                        if (m < LA && im >= 0 && im < L) {
-                            const int kk = g.horizontal ? (c * g.seg + im) : (im * g.C + c);
-                            const BlockPix p = block_pix(g, blk, kk);
-                            Pix cx;
-                            pix_geometry<false>(w, B.P, B.flow, p.u, p.v, cx);
-                            mine = frame_cost<B2>(w, B.P, B.flow2, cx, carried, t);
-                        }
-                        const int mm = min(hl, LA - 1), imm = i + mm * di;
-                        const bool mine_node = hl < LA && imm >= 0 && imm < L;
-                        la_e = 0.f;
+                nxt[base + p.i] = nx;
+            }
+            __syncthreads();
+            if constexpr (!PR) {
+                // one wave per chain: the walk's state is uniform over the wave and kept in
+                // scalar registers, so a hop costs one LDS round trip and a few scalar
+                // instructions; a value that outlives the speculation depth is evaluated at
+                // the next 64 / N nodes at once, one lane per (node, frame)
+                const int wl = tid & 63;
+                const int LW = 64 / w.N;
+                for (int c = __builtin_amdgcn_readfirstlane(tid >> 6); c < g.C; c += VD_BLOCK / 64) {
+                    const int L = chain_len(g, blk, c);
+                    if (L <= 0) continue;
+                    const int base = c * stride;
+                    const int iend = fwd ? L : -1;
+                    for (int i = fwd ? 0 : L - 1; i != iend;) {
+                        const float carried = bestV[base + i];
+                        int ni = __builtin_amdgcn_readfirstlane(nxt[base + i]);
+                        if (ni == -1) {
+                            ni = iend;
+                            for (int j0 = i + (g.spec + 1) * di; (fwd ? j0 < L : j0 >= 0) && ni == iend; j0 += LW * di) {
+                                const int m = wl / w.N, t = wl - m * w.N;
+                                const int jm = j0 + m * di;
+                                float mine = 0.f;
+                                if (m < LW && jm >= 0 && jm < L) {
+                                    const int kk = g.horizontal ? (c * g.seg + jm) : (jm * g.C + c);
+                                    const BlockPix p = block_pix(g, blk, kk);
+                                    Pix cx;
+                                    pix_geometry<false>(w, B.P, B.flow, p.u, p.v, cx);
+                                    mine = frame_cost<B2>(w, B.P, B.flow2, cx, carried, t);
+                                }
+                                const int mm = min(wl, LW - 1), jmm = j0 + mm * di;
+                                const bool mine_node = wl < LW && jmm >= 0 && jmm < L;
+                                float la_e = 0.f;
 #pragma unroll
-                        for (int tt = 0; tt < VD_NMAX; ++tt) {
-                            if (tt < w.N) {
-                                const float ct = __shfl(mine, hbase + mm * w.N + tt);
-                                if (mine_node) la_e = fmaf(q_s[tt * nodes + base + imm], ct, la_e);
+                                for (int tt = 0; tt < VD_NMAX; ++tt) {
+                                    if (tt < w.N) {
+                                        const float ct = __shfl(mine, mm * w.N + tt);
+                                        if (mine_node) la_e = fmaf(q_s[tt * nodes + base + jmm], ct, la_e);
+                                    }
+                                }
+                                for (int mq = 0; mq < LW; ++mq) {
+                                    const int j = j0 + mq * di;
+                                    if (j < 0 || j >= L) break;
+                                    const float e1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(la_e), mq));
+                                    const float eA = bestE[base + j];
+                                    if (!((e1 < eA) || (e1 == eA && bestS[base + j] > 1))) { ni = j; break; }
+                                }
+                                ni = __builtin_amdgcn_readfirstlane(ni);
+                            }
+                        } else if (ni == -2) {
+                            ni = iend;
+                        }
+                        // nodes i .. ni (exclusive) carry node i's phase-A result
+                        const int cnt = (ni - i) * di;
+                        for (int m = wl; m < cnt; m += 64) newV[base + i + m * di] = carried;
+                        i = ni;
+                    }
+                }
+            } else {
+                // with priors: a group of 32 lanes per chain; a value that outlives the
+                // speculation depth is evaluated node by node (energy2_lanes)
+                for (int c = grp; c < g.C; c += VD_BLOCK / 32) {
+                    const int L = chain_len(g, blk, c);
+                    if (L <= 0) continue;
+                    const int base = c * stride;
+                    const int iend = fwd ? L : -1;
+                    for (int i = fwd ? 0 : L - 1; i != iend;) {
+                        const float carried = bestV[base + i];
+                        int ni = nxt[base + i];
+                        if (ni == -1) {
+                            ni = iend;
+                            for (int j = i + (g.spec + 1) * di; (fwd ? j < L : j >= 0) && ni == iend; j += di) {
+                                const int o = base + j;
+                                const int kk = g.horizontal ? (c * g.seg + j) : (j * g.C + c);
+                                const BlockPix p = block_pix(g, blk, kk);
+                                Pix cx;
+                                pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, cx);
+#pragma unroll
+                                for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) cx.q[t] = q_s[t * nodes + o];
+                                prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cx, rcur[o]);
+                                const float e1 = energy2_lanes<B2, PR>(w, B.P, B.flow2, B.prior, cx, carried, hl, hbase);
+                                const float eA = bestE[o];
+                                if (!((e1 < eA) || (e1 == eA && bestS[o] > 1))) ni = j;
+                            }
+                        } else if (ni == -2) {
+                            ni = iend;
+                        }
+                        const int cnt = (ni - i) * di;
+                        for (int m = hl; m < cnt; m += 32) newV[base + i + m * di] = carried;
+                        i = ni;
+                    }
+                }
+            }
+        } else {
+            for (int c = grp; c < g.C; c += VD_BLOCK / 32) {
+                const int L = chain_len(g, blk, c);
+                if (L <= 0) continue;
+                const int i0 = fwd ? 0 : L - 1;
+                const int base = c * stride;
+                float carried = bestV[base + i0];
+                int src = i0;
+                int la_src = -1, la_i = 0;                      // lookahead: source node, first node
+                float la_e = 0.f;                               // lane m < LA: energy at node la_i + m*di
+                if (hl == 0) newV[base + i0] = carried;
+                for (int n = 1, i = i0 + di; n < L; ++n, i += di) {
+                    const int o = base + i;
+                    float e1;
+                    const int dist = (i - src) * di;            // steps back to the carried value's node
+                    if (dist <= g.spec) {
+                        e1 = specE[(dist - 1) * nodes + o];
+                    } else if constexpr (!PR) {
+                        if (la_src != src || (i - la_i) * di >= LA) {
+                            la_src = src;
+                            la_i = i;
+                            const int m = hl / w.N, t = hl - m * w.N;
+                            const int im = i + m * di;
+                            float mine = 0.f;
+                            if (m < LA && im >= 0 && im < L) {
+                                const int kk = g.horizontal ? (c * g.seg + im) : (im * g.C + c);
+                                const BlockPix p = block_pix(g, blk, kk);
+                                Pix cx;
+                                pix_geometry<false>(w, B.P, B.flow, p.u, p.v, cx);
+                                mine = frame_cost<B2>(w, B.P, B.flow2, cx, carried, t);
+                            }
+                            const int mm = min(hl, LA - 1), imm = i + mm * di;
+                            const bool mine_node = hl < LA && imm >= 0 && imm < L;
+                            la_e = 0.f;
+#pragma unroll
+                            for (int tt = 0; tt < VD_NMAX; ++tt) {
+                                if (tt < w.N) {
+                                    const float ct = __shfl(mine, hbase + mm * w.N + tt);
+                                    if (mine_node) la_e = fmaf(q_s[tt * nodes + base + imm], ct, la_e);
+                                }
                             }
                         }
-                    }
-                    e1 = __shfl(la_e, hbase + (i - la_i) * di);
-                } else {
-                    // storage-order node i of chain c -> block linear index
-                    const int kk = g.horizontal ? (c * g.seg + i) : (i * g.C + c);
-                    const BlockPix p = block_pix(g, blk, kk);
-                    Pix cx;
-                    pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, cx);
+                        e1 = __shfl(la_e, hbase + (i - la_i) * di);
+                    } else {
+                        // storage-order node i of chain c -> block linear index
+                        const int kk = g.horizontal ? (c * g.seg + i) : (i * g.C + c);
+                        const BlockPix p = block_pix(g, blk, kk);
+                        Pix cx;
+                        pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, cx);
 #pragma unroll
-                    for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) cx.q[t] = q_s[t * nodes + o];
-                    prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cx, rcur[o]);
-                    e1 = energy2_lanes<B2, PR>(w, B.P, B.flow2, B.prior, cx, carried, hl, hbase);
-                }
-                if constexpr (LC) {
-                    const bool keep = (e1 < eA) | ((e1 == eA) & (sA > 1));
-                    carried = keep ? carried : vA;
-                    src = keep ? src : i;
-                    so = keep ? so : -nodes;
-                } else {
-                    eA = bestE[o];
+                        for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) cx.q[t] = q_s[t * nodes + o];
+                        prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cx, rcur[o]);
+                        e1 = energy2_lanes<B2, PR>(w, B.P, B.flow2, B.prior, cx, carried, hl, hbase);
+                    }
+                    const float eA = bestE[o];
                     const bool keep = (e1 < eA) || (e1 == eA && bestS[o] > 1);
                     if (!keep) { carried = bestV[o]; src = i; }
+                    if (hl == 0) newV[o] = carried;
                 }
-                if (hl == 0) newV[o] = carried;
             }
         }
     }
