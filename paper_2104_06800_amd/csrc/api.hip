@@ -455,7 +455,7 @@ void plan_level(BPlan& P, const std::vector<BWin>& W, int mode, MakeItem make) {
             vd::LevelItem it = make(bw.L);
             int nb = it.g.nblocks;
             const size_t lat = (size_t)it.g.h * it.g.w;
-            if (mode == 1) nb = (int)((lat * 4 + VD_BLOCK - 1) / VD_BLOCK);
+            if (mode == 1) nb = (int)((lat * VD_PA_LANES + VD_BLOCK - 1) / VD_BLOCK);
             if (mode == 2) nb = (int)((lat * it.g.spec + VD_BLOCK - 1) / VD_BLOCK);
             if (mode == 0 || mode == 3) lds = std::max(lds, vd::level_lds_bytes(it.g));
             items.push_back(it);

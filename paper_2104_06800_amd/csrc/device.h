@@ -19,6 +19,11 @@
 #define VD_GN_PIX 4
 #endif
 #define VD_SPEC 8       // maximum speculation depth of the chain scan
+// lanes per lattice node in the separate phase-A grid (a power of two; one Philox group of
+// four candidates per lane at K = 32)
+#ifndef VD_PA_LANES
+#define VD_PA_LANES 8
+#endif
 #define VD_LN2 0.69314718055994530942f
 #define VD_LOG2E 1.44269504088896340736f
 

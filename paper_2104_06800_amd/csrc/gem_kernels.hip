@@ -662,16 +662,16 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
 }
 
 // ----------------------------------------------------------------------------------
-// phase A as a separate grid: four lanes per level pixel.  Lane 0 takes slot 0, lane l
-// takes the Philox groups g = l, l + 4, ... (slots 3 + 4g .. 6 + 4g) and, on the local
-// level, lane 1 takes slot 2 first.  Each lane scans its slots in increasing order with
-// strict improvement and pruning at its own best, then the four lanes merge by (energy,
-// slot): the result equals the argmin over all slots with ties to the lowest slot.
+// phase A as a separate grid: VD_PA_LANES lanes per level pixel.  Lane 0 takes slot 0,
+// lane l takes the Philox groups g = l, l + VD_PA_LANES, ... (slots 3 + 4g .. 6 + 4g) and,
+// on the local level, lane 1 takes slot 2 first.  Each lane scans its slots in increasing
+// order with strict improvement and pruning at its own best, then the lanes merge by
+// (energy, slot): the result equals the argmin over all slots with ties to the lowest slot.
 // ----------------------------------------------------------------------------------
 template <bool B2, bool PR>
 __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, const LevelBufs& B, int blk) {
     const int gid = blk * VD_BLOCK + threadIdx.x;
-    const int li = gid >> 2, lane = gid & 3;
+    const int li = gid / VD_PA_LANES, lane = gid % VD_PA_LANES;
     const size_t lplane = (size_t)g.h * g.w;
     const bool valid = li < (int)lplane;
     float bE = __builtin_huge_valf(), bV = 0.f, r0 = 0.f;
@@ -697,7 +697,7 @@ __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, c
         }
         const int G = (w.K - 3 + 3) / 4;
         const uint32_t word2 = philox_word2(w.it, w.level, PURPOSE_CAND);
-        for (int gi = lane; gi < G; gi += 4) {
+        for (int gi = lane; gi < G; gi += VD_PA_LANES) {
             const uint4 r = philox10(make_uint4((uint32_t)li, (uint32_t)gi, word2, w.window_id), w.key0, w.key1);
             const uint32_t words[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
@@ -715,7 +715,7 @@ __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, c
         }
     }
 #pragma unroll
-    for (int off = 1; off < 4; off <<= 1) {
+    for (int off = 1; off < VD_PA_LANES; off <<= 1) {
         const float oE = __shfl_xor(bE, off), oV = __shfl_xor(bV, off);
         const int oS = __shfl_xor(bS, off);
         if (oE < bE || (oE == bE && oS < bS)) { bE = oE; bV = oV; bS = oS; }
@@ -1306,7 +1306,7 @@ hipError_t launch_level(const Win& w, const LevelGeom& g, const LevelBufs& b, in
 }
 
 hipError_t launch_phase_a(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st) {
-    const dim3 grid((unsigned)(((size_t)g.h * g.w * 4 + VD_BLOCK - 1) / VD_BLOCK));
+    const dim3 grid((unsigned)(((size_t)g.h * g.w * VD_PA_LANES + VD_BLOCK - 1) / VD_BLOCK));
     if (w.beta2) {
         if (w.P > 0) hipLaunchKernelGGL((k_phase_a<true, true>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
         else hipLaunchKernelGGL((k_phase_a<true, false>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
