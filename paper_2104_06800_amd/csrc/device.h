@@ -758,20 +758,32 @@ __device__ __forceinline__ void block_reduce(double* acc, double* red /* [NT/64]
 }
 
 // Deterministic sum of per-block records stored value-major, part[k * nb + b], b < nb:
-// thread i takes the blocks i, i + 256, ... (coalesced, independent loads), then a
-// fixed-order block reduction.  The NR sums are in red[0..NR-1] after the call (all
-// threads synchronised).
+// value k is summed by SL consecutive lanes (SL a power of two with NR * SL <= NT), lane l
+// taking the blocks l, l + SL, ... in order, then an xor tree over the SL lanes.  Few
+// levels of shuffles per value and many independent loads in flight per lane.  The NR
+// sums are in red[0..NR-1] after the call (all threads synchronised).
+template <int NR, int NT>
+constexpr int partial_slices() {
+    int sl = 64;
+    while (sl > 1 && NR * sl > NT) sl >>= 1;
+    return sl;
+}
+
 template <int NR, int NT = VD_BLOCK>
 __device__ __forceinline__ void reduce_partials(const double* part, unsigned nb, double* red) {
-    double acc[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-    for (unsigned b = threadIdx.x; b < nb; b += NT) {
-#pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k] += __builtin_nontemporal_load(part + (size_t)k * nb + b);
+    constexpr int SL = partial_slices<NR, NT>();
+    const int tid = threadIdx.x;
+    const int k = tid / SL, l = tid % SL;
+    double acc = 0.0;
+    if (k < NR) {
+        const double* pk = part + (size_t)k * nb;
+#pragma unroll 8
+        for (unsigned b = l; b < nb; b += SL) acc += __builtin_nontemporal_load(pk + b);
     }
+#pragma unroll
+    for (int off = SL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     __syncthreads();
-    block_reduce<NR, NT>(acc, red);
+    if (k < NR && l == 0) red[k] = acc;
     __syncthreads();
 }
 
