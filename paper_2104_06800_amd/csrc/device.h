@@ -13,10 +13,10 @@
 #define VD_BLOCK 256
 // pose Gauss-Newton launches: threads per block and pixels per thread and load batch
 #ifndef VD_GN_BLOCK
-#define VD_GN_BLOCK 256
+#define VD_GN_BLOCK 512
 #endif
 #ifndef VD_GN_PIX
-#define VD_GN_PIX 4
+#define VD_GN_PIX 2
 #endif
 #define VD_SPEC 8       // maximum speculation depth of the chain scan
 // lanes per lattice node in the separate phase-A grid (a power of two; one Philox group of
@@ -758,10 +758,12 @@ __device__ __forceinline__ void block_reduce(double* acc, double* red /* [NT/64]
 }
 
 // Deterministic sum of per-block records stored value-major, part[k * nb + b], b < nb:
-// value k is summed by SL consecutive lanes (SL a power of two with NR * SL <= NT), lane l
-// taking the blocks l, l + SL, ... in order, then an xor tree over the SL lanes.  Few
-// levels of shuffles per value and many independent loads in flight per lane.  The NR
-// sums are in red[0..NR-1] after the call (all threads synchronised).
+// value k is summed by SL consecutive lanes, lane l taking the blocks l, l + SL, ... in
+// order, then an xor tree over the SL lanes: few levels of shuffles per value and many
+// independent loads in flight per lane.  SL is the largest power of two up to 64 with
+// NR * SL <= NT: every kernel that reduces one kind of record uses the same NT, so they
+// all sum in the same order.  The NR sums are in red[0..NR-1] after the call (all threads
+// synchronised).
 template <int NR, int NT>
 constexpr int partial_slices() {
     int sl = 64;

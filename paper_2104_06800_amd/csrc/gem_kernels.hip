@@ -1075,8 +1075,8 @@ __global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn(Win w, PoseBufs B, int 
 // unsplit pass); after the window's last step, every frame's final pose into the FP32 /
 // FP64 tables and the caller's 6-vectors.
 __device__ __forceinline__ void pose_gn_solve_body(const PoseBufs& B, int N, int G, int s, unsigned nb) {
-    __shared__ double red[(VD_BLOCK / 64) * 29];
-    reduce_partials<kGnRec>(B.partials + (size_t)(s & 1) * kGnRec * nb, nb, red);
+    __shared__ double red[kGnRec];
+    reduce_partials<kGnRec, VD_GN_BLOCK>(B.partials + (size_t)(s & 1) * kGnRec * nb, nb, red);
     const int t = s / G + 1, k = s - (t - 1) * G;
     if (threadIdx.x == 0) {
         PoseD P = k == 0 ? B.PD[t - 1] : B.hist[s - 1];
@@ -1100,9 +1100,9 @@ __device__ __forceinline__ void pose_gn_solve_body(const PoseBufs& B, int N, int
 // Last step's solve, then every frame's final pose into the FP32 / FP64 copies and the
 // caller's 6-vectors.
 __device__ __forceinline__ void pose_gn_finish_body(const PoseBufs& B, int N, int G, unsigned nb) {
-    __shared__ double red[(VD_BLOCK / 64) * 29];
+    __shared__ double red[kGnRec];
     const int S = N * G;
-    reduce_partials<kGnRec>(B.partials + (size_t)((S - 1) & 1) * kGnRec * nb, nb, red);
+    reduce_partials<kGnRec, VD_GN_BLOCK>(B.partials + (size_t)((S - 1) & 1) * kGnRec * nb, nb, red);
     if (threadIdx.x == 0) {
         const int sp = S - 1, tp = sp / G + 1, kp = sp - (tp - 1) * G;
         PoseD P = (kp == 0) ? B.PD[tp - 1] : B.hist[sp - 1];
@@ -1122,7 +1122,7 @@ __device__ __forceinline__ void pose_gn_finish_body(const PoseBufs& B, int N, in
     }
 }
 
-__global__ void __launch_bounds__(VD_BLOCK) k_pose_gn_finish(PoseBufs B, int N, int G, unsigned nb) {
+__global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn_finish(PoseBufs B, int N, int G, unsigned nb) {
     pose_gn_finish_body(B, N, G, nb);
 }
 
@@ -1233,7 +1233,7 @@ __global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn_batch(const PoseItem* _
 }
 
 // step s's solve of every window that has the step, one block per window
-__global__ void __launch_bounds__(VD_BLOCK) k_pose_gn_solve_batch(const PoseItem* __restrict__ items, int s) {
+__global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn_solve_batch(const PoseItem* __restrict__ items, int s) {
     const PoseItem& it = items[blockIdx.x];
     if (s < it.S) pose_gn_solve_body(it.b, it.w.N, it.G, s, (unsigned)it.nblocks);
 }
@@ -1349,7 +1349,7 @@ hipError_t launch_pose_gn(const Win& w, const PoseBufs& b, int s, int G, int nbl
 }
 
 hipError_t launch_pose_gn_finish(const PoseBufs& b, int N, int G, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_pose_gn_finish, dim3(1), dim3(VD_BLOCK), 0, st, b, N, G, (unsigned)nblocks);
+    hipLaunchKernelGGL(k_pose_gn_finish, dim3(1), dim3(VD_GN_BLOCK), 0, st, b, N, G, (unsigned)nblocks);
     return hipGetLastError();
 }
 
@@ -1418,7 +1418,7 @@ hipError_t launch_pose_gn_batch(const PoseItem* items, const int* blk2item, int 
 }
 
 hipError_t launch_pose_gn_solve_batch(const PoseItem* items, int n_items, int s, hipStream_t st) {
-    hipLaunchKernelGGL(k_pose_gn_solve_batch, dim3((unsigned)n_items), dim3(VD_BLOCK), 0, st, items, s);
+    hipLaunchKernelGGL(k_pose_gn_solve_batch, dim3((unsigned)n_items), dim3(VD_GN_BLOCK), 0, st, items, s);
     return hipGetLastError();
 }
 
