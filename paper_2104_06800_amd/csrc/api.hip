@@ -375,11 +375,13 @@ int run_finalize(GemLaunch& L, int iter) {
     return VOLDOR_OK;
 }
 
-// One GEM iteration on a prepared launch; the pose tables are refreshed from the 6-vectors
-// first, as a separate voldor_gem_step call would.
-int run_iteration(GemLaunch& L, int it, bool layout) {
+// One GEM iteration on a prepared launch.  The first iteration of a call builds the pose
+// tables (and the flow layout) from the caller's 6-vectors; later ones find them already
+// built from the updated 6-vectors by the previous pose step's finish, with the same
+// functions, so the tables are those a separate voldor_gem_step call would build.
+int run_iteration(GemLaunch& L, int it, bool first) {
     int rc;
-    if ((rc = prep_poses(L, layout))) return rc;
+    if (first && (rc = prep_poses(L, true))) return rc;
     if ((rc = run_level(L, it, VOLDOR_LEVEL_COARSE, 1, 1, false))) return rc;
     if ((rc = run_level(L, it, VOLDOR_LEVEL_LOCAL, 1, 1, false))) return rc;
     return run_pose_step(L);
@@ -392,7 +394,6 @@ int run_window(GemLaunch& L, int first, int n_iters, int flags) {
     if (flags & VOLDOR_RUN_INIT) VD_CHECK(vd::launch_init(make_win(L.v, 0, 1), L.b->idepth, L.st), "init launch");
     for (int it = first; it < first + n_iters; ++it)
         if ((rc = run_iteration(L, it, it == first))) return rc;
-    if ((rc = prep_poses(L, false))) return rc;
     return run_finalize(L, first + n_iters - 1);
 }
 

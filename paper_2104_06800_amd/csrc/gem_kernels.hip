@@ -1071,6 +1071,21 @@ __global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn(Win w, PoseBufs B, int 
     pose_gn_body<B2>(w, B, s, G, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
+// frame i's final pose: the caller's 6-vector, then the FP32 / FP64 tables built from that
+// 6-vector exactly as the pose-table preparation at the start of a step builds them, so the
+// next iteration needs no separate preparation
+__device__ __forceinline__ void final_pose(const PoseBufs& B, int G, int i) {
+    const PoseD P = B.hist[(i + 1) * G - 1];
+    double v[6];
+    log_so3(P.R, v);
+    v[3] = P.t[0];
+    v[4] = P.t[1];
+    v[5] = P.t[2];
+    for (int k = 0; k < 6; ++k) B.pose[6 * i + k] = v[k];
+    pose_to_f(v, B.P + i);
+    posed_from_vec(v, B.PD + i);
+}
+
 // Step s's solve (one block, the same fixed-order reduction and solve as the prologue of the
 // unsplit pass); after the window's last step, every frame's final pose into the FP32 /
 // FP64 tables and the caller's 6-vectors.
@@ -1085,16 +1100,7 @@ __device__ __forceinline__ void pose_gn_solve_body(const PoseBufs& B, int N, int
     }
     if (s < N * G - 1) return;
     __syncthreads();
-    const int i = threadIdx.x;
-    if (i < N) {
-        const PoseD P = B.hist[(i + 1) * G - 1];
-        B.PD[i] = P;
-        posef_from_d(P, B.P + i);
-        log_so3(P.R, B.pose + 6 * i);
-        B.pose[6 * i + 3] = P.t[0];
-        B.pose[6 * i + 4] = P.t[1];
-        B.pose[6 * i + 5] = P.t[2];
-    }
+    if (threadIdx.x < N) final_pose(B, G, threadIdx.x);
 }
 
 // Last step's solve, then every frame's final pose into the FP32 / FP64 copies and the
@@ -1110,16 +1116,7 @@ __device__ __forceinline__ void pose_gn_finish_body(const PoseBufs& B, int N, in
         B.hist[sp] = P;
     }
     __syncthreads();
-    const int i = threadIdx.x;
-    if (i < N) {
-        const PoseD P = B.hist[(i + 1) * G - 1];
-        B.PD[i] = P;
-        posef_from_d(P, B.P + i);
-        log_so3(P.R, B.pose + 6 * i);
-        B.pose[6 * i + 3] = P.t[0];
-        B.pose[6 * i + 4] = P.t[1];
-        B.pose[6 * i + 5] = P.t[2];
-    }
+    if (threadIdx.x < N) final_pose(B, G, threadIdx.x);
 }
 
 __global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn_finish(PoseBufs B, int N, int G, unsigned nb) {
