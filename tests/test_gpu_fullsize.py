@@ -67,7 +67,10 @@ def oracle_bufs(p, w, b):
     return ob
 
 
-@pytest.mark.parametrize("level,it", [(0, 2), (1, 2), (1, 3)])
+# the coarse level in all four sweep directions: forward and backward rows (304 nodes) and
+# columns (88 nodes), long enough for multi-segment forward-backward scans and for values
+# that outlive the scan's speculation depth
+@pytest.mark.parametrize("level,it", [(0, 0), (0, 1), (0, 2), (0, 3), (1, 2), (1, 3)])
 def test_fullsize_rigidness_sampled(lib, state, level, it):
     w, b = state
     p = w["params"]
@@ -85,7 +88,7 @@ def test_fullsize_rigidness_sampled(lib, state, level, it):
     assert err.max() <= 1e-2
 
 
-@pytest.mark.parametrize("level,it", [(0, 2), (1, 2), (1, 3)])
+@pytest.mark.parametrize("level,it", [(0, 0), (0, 1), (0, 2), (0, 3), (1, 2), (1, 3)])
 def test_fullsize_depth_update_sampled(lib, state, level, it):
     w, b = state
     p = w["params"]
