@@ -474,7 +474,9 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             // chain then hops from replacement to replacement; a value that outlives the
             // speculation depth is evaluated at the following nodes as in the scan below.
             // The decisions are those of the node-by-node scan, bit for bit.
-            int* nxt = (int*)r_s;                           // [C][stride]; the E-step ratios are dead here
+            // [C][stride] (next replacement, phase-A value) per node, one 8-byte LDS read per hop;
+            // the E-step ratios are dead here
+            int2* hop = (int2*)r_s;
             for (int k = tid; k < npix; k += VD_BLOCK) {
                 const BlockPix p = block_pix(g, blk, k);
                 if (!p.valid) continue;
@@ -488,7 +490,7 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                     const float e1 = specE[(d - 1) * nodes + base + j], eA = bestE[base + j];
                     if (!((e1 < eA) || (e1 == eA && bestS[base + j] > 1))) { nx = j; break; }
                 }
-                nxt[base + p.i] = nx;
+                hop[base + p.i] = make_int2(nx, __float_as_int(bestV[base + p.i]));
             }
             __syncthreads();
             if constexpr (!PR) {
@@ -504,8 +506,9 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                     const int base = c * stride;
                     const int iend = fwd ? L : -1;
                     for (int i = fwd ? 0 : L - 1; i != iend;) {
-                        const float carried = bestV[base + i];
-                        int ni = __builtin_amdgcn_readfirstlane(nxt[base + i]);
+                        const int2 h = hop[base + i];
+                        const float carried = __int_as_float(h.y);
+                        int ni = __builtin_amdgcn_readfirstlane(h.x);
                         if (ni == -1) {
                             ni = iend;
                             for (int j0 = i + (g.spec + 1) * di; (fwd ? j0 < L : j0 >= 0) && ni == iend; j0 += LW * di) {
@@ -556,8 +559,9 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                     const int base = c * stride;
                     const int iend = fwd ? L : -1;
                     for (int i = fwd ? 0 : L - 1; i != iend;) {
-                        const float carried = bestV[base + i];
-                        int ni = nxt[base + i];
+                        const int2 h = hop[base + i];
+                        const float carried = __int_as_float(h.y);
+                        int ni = h.x;
                         if (ni == -1) {
                             ni = iend;
                             for (int j = i + (g.spec + 1) * di; (fwd ? j < L : j >= 0) && ni == iend; j += di) {
