@@ -74,7 +74,6 @@ __device__ __forceinline__ void robust(int kind, float scale, float r, float& ps
 
 __global__ void __launch_bounds__(VD_BLOCK)
 k_align_step(AlignArgs a, AlignBufs B) {
-    __shared__ double red[(VD_BLOCK / 64) * 29];
     __shared__ PoseF Tsh;
     const int tid = threadIdx.x;
     const int pair = blockIdx.y;
@@ -87,9 +86,10 @@ k_align_step(AlignArgs a, AlignBufs B) {
     const float* C2 = B.conf2 + (size_t)pair * plane;
     const float4* NB = B.normals + (size_t)pair * plane;
     const float is = 1.f / a.s;
-    double acc[29];
+    // per-thread sums in FP32 (a thread covers a few pixels), FP64 across threads and blocks
+    float acc[29];
 #pragma unroll
-    for (int k = 0; k < 29; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 29; ++k) acc[k] = 0.f;
     for (int j = blockIdx.x * VD_BLOCK + tid; j < (int)plane; j += gridDim.x * VD_BLOCK) {
         const float rho2 = R2[j], c2 = C2[j];
         if (!(rho2 > 0.f) || !isfinite(rho2) || !isfinite(c2)) continue;
@@ -118,15 +118,16 @@ k_align_step(AlignArgs a, AlignBufs B) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
 #pragma unroll
-            for (int l = i; l < 6; ++l) acc[k++] += (double)(W * J[i] * J[l]);
+            for (int l = i; l < 6; ++l) acc[k++] += W * J[i] * J[l];
         }
 #pragma unroll
-        for (int i = 0; i < 6; ++i) acc[22 + i] += (double)(W * J[i] * r);
-        acc[0] += (double)(c2 * psi);
-        acc[28] += 1.0;
+        for (int i = 0; i < 6; ++i) acc[22 + i] += W * J[i] * r;
+        acc[0] += c2 * psi;
+        acc[28] += 1.f;
     }
-    block_reduce<29>(acc, red);
-    if (tid < 29) B.partials[((size_t)pair * 29 + tid) * gridDim.x + blockIdx.x] = red[tid];
+    block_sum_transposed<29, VD_BLOCK>(acc, [&](int v, double sum) {
+        B.partials[((size_t)pair * 29 + v) * gridDim.x + blockIdx.x] = sum;
+    });
 }
 
 // One block per pair: sum the pair's block records (fixed order), then the FP64 solve and

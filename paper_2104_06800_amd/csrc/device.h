@@ -771,6 +771,30 @@ constexpr int partial_slices() {
     return sl;
 }
 
+// Block sum of NR per-thread FP32 values, transposed through LDS: the values go to
+// tr[v][thread] (the row stride keeps both the writes and the reads free of bank conflicts),
+// then value v is summed in FP64 by SL lanes in thread order and an xor tree over the SL
+// lanes; out(v, sum) is called once per value.  A fixed order, so every block sums alike.
+template <int NR, int NT, class F>
+__device__ __forceinline__ void block_sum_transposed(const float* a32, F&& out) {
+    constexpr int SL = partial_slices<NR, NT>();
+    constexpr int TS = NT + (SL < 32 ? SL : 0);
+    __shared__ float tr[NR * TS];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) tr[i * TS + tid] = a32[i];
+    __syncthreads();
+    const int v = tid / SL, l = tid % SL;
+    double acc = 0.0;
+    if (v < NR) {
+#pragma unroll 8
+        for (int i = l; i < NT; i += SL) acc += (double)tr[v * TS + i];
+    }
+#pragma unroll
+    for (int off = SL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (v < NR && l == 0) out(v, acc);
+}
+
 template <int NR, int NT = VD_BLOCK>
 __device__ __forceinline__ void reduce_partials(const double* part, unsigned nb, double* red) {
     constexpr int SL = partial_slices<NR, NT>();

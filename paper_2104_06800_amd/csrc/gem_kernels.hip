@@ -1050,24 +1050,9 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
         j0 += UB * stride;
         if (j0 < plane) load(j0);
     }
-    // block sum, transposed through LDS: value v is summed in FP64 by SL lanes (a row
-    // stride of VD_GN_BLOCK + 8 keeps both the writes and the reads free of bank
-    // conflicts), then an xor tree over the SL lanes
-    constexpr int TS = VD_GN_BLOCK + 8;
-    __shared__ float tr[kGnRec * TS];
-#pragma unroll
-    for (int i = 0; i < kGnRec; ++i) tr[i * TS + tid] = a32[i];
-    __syncthreads();
-    constexpr int SL = partial_slices<kGnRec, VD_GN_BLOCK>();
-    const int vv = tid / SL, l = tid % SL;
-    double acc = 0.0;
-    if (vv < kGnRec) {
-#pragma unroll 8
-        for (int i = l; i < VD_GN_BLOCK; i += SL) acc += (double)tr[vv * TS + i];
-    }
-#pragma unroll
-    for (int off = SL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (vv < kGnRec && l == 0) B.partials[((size_t)(s & 1) * kGnRec + vv) * nb + blk] = acc;
+    block_sum_transposed<kGnRec, VD_GN_BLOCK>(a32, [&](int v, double sum) {
+        B.partials[((size_t)(s & 1) * kGnRec + v) * nb + blk] = sum;
+    });
 }
 
 template <bool B2>
