@@ -228,8 +228,14 @@ __device__ inline bool chol6_solve(const double* A, const double* b, double* x) 
             for (int k = 0; k < j; ++k) s -= L[6 * i + k] * L[6 * j + k];
             if (i == j) {
                 if (!(s > tol) || !isfinite(s)) return false;
-                L[6 * i + i] = sqrt(s);
-                inv[i] = 1.0 / L[6 * i + i];
+                // 1 / sqrt(s): the hardware estimate and two Newton steps (full FP64
+                // accuracy, a short dependent chain instead of sqrt and a division)
+                const double hs = 0.5 * s;
+                double r = __builtin_amdgcn_rsq(s);
+                r = r * fma(-hs * r, r, 1.5);
+                r = r * fma(-hs * r, r, 1.5);
+                L[6 * i + i] = s * r;
+                inv[i] = r;
             } else {
                 L[6 * i + j] = s * inv[j];
             }
