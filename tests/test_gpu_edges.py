@@ -1,8 +1,9 @@
 """GPU parity on the degenerate and extreme window shapes: a single frame, the minimum of
 three slots (no random draws), the smallest and largest tiles (a tile larger than the
 image), a coarse stride of 1 (the lattice is the image) and 8, the maximum frame count and
-the maximum prior count, and a 2x2 image.  Each case runs the coarse pass on the GPU, then
-compares the local E-step and M-step and a pose step with the oracle from the same state.
+the maximum prior count, and a 2x2 image.  Each case compares the coarse E-step and M-step
+(a row and a column sweep), then the local E-step and M-step and a pose step with the
+oracle from the same state.
 """
 import numpy as np
 import pytest
@@ -68,11 +69,22 @@ def test_edge_window(lib, name):
           f"s={p['coarse_stride']} P={p.get('P', 0)}", flush=True)
     b = lib.alloc(p, w["flow"], w["pose_init"], w.get("prior_idepth"), w.get("prior_pose"), w.get("prior_weight"))
     lib.init_idepth(p, b)
-    it = 1
-    lib.rigidness_fb(p, b, it, 0)
-    lib.depth_update(p, b, it, 0)
     ob = ogem.alloc_buffers(p, w["flow"], w["pose_init"], w.get("prior_idepth"), w.get("prior_pose"),
                             w.get("prior_weight"))
+    for k in ("idepth", "pose"):
+        ob[k][...] = np_(b[k])
+    # coarse level, a row sweep (it 2) and a column sweep (it 1): the E-step's lane-group
+    # scan of each chain and the M-step's replacement walk, on this case's lattice
+    for it in (2, 1):
+        lib.rigidness_fb(p, b, it, 0)
+        ogem.rigidness_fb(p, ob, it, 0)
+        qc = np_(b["rigid_coarse"])
+        assert np.mean(np.abs(qc - ob["rigid_coarse"]) <= 1e-3) >= 0.995
+        assert np.abs(qc - ob["rigid_coarse"]).max() <= 1e-2
+        ob["rigid_coarse"][...] = qc
+        lib.depth_update(p, b, it, 0)
+        ogem.depth_update(p, ob, it, 0)
+        check_mstep(p, ob, ob["idepth"].copy(), np_(b["idepth_coarse"]), 0, it)
     for k in ("idepth", "idepth_coarse", "pose"):
         ob[k][...] = np_(b[k])
     # local E-step
