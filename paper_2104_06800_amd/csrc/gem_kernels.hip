@@ -477,6 +477,7 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             // [C][stride] (next replacement, phase-A value) per node, one 8-byte LDS read per hop;
             // the E-step ratios are dead here
             int2* hop = (int2*)r_s;
+            int* mark = (int*)(hop + nodes);                // [C][stride] replacement nodes of the walk
             for (int k = tid; k < npix; k += VD_BLOCK) {
                 const BlockPix p = block_pix(g, blk, k);
                 if (!p.valid) continue;
@@ -491,13 +492,15 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                     if (!((e1 < eA) || (e1 == eA && bestS[base + j] > 1))) { nx = j; break; }
                 }
                 hop[base + p.i] = make_int2(nx, __float_as_int(bestV[base + p.i]));
+                mark[base + p.i] = 0;
             }
             __syncthreads();
             if constexpr (!PR) {
                 // one wave per chain: the walk's state is uniform over the wave and kept in
-                // scalar registers, so a hop costs one LDS round trip and a few scalar
-                // instructions; a value that outlives the speculation depth is evaluated at
-                // the next 64 / N nodes at once, one lane per (node, frame)
+                // scalar registers, so a hop costs one LDS round trip, one mark and a few
+                // scalar instructions; a value that outlives the speculation depth is
+                // evaluated at the next 64 / N nodes at once, one lane per (node, frame).
+                // The nodes between two marks are filled afterwards by a prefix pass.
                 const int wl = tid & 63;
                 const int LW = 64 / w.N;
                 for (int c = __builtin_amdgcn_readfirstlane(tid >> 6); c < g.C; c += VD_BLOCK / 64) {
@@ -506,6 +509,7 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                     const int base = c * stride;
                     const int iend = fwd ? L : -1;
                     for (int i = fwd ? 0 : L - 1; i != iend;) {
+                        mark[base + i] = 1;                         // the same address on every lane
                         const int2 h = hop[base + i];
                         const float carried = __int_as_float(h.y);
                         int ni = __builtin_amdgcn_readfirstlane(h.x);
@@ -544,10 +548,20 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                         } else if (ni == -2) {
                             ni = iend;
                         }
-                        // nodes i .. ni (exclusive) carry node i's phase-A result
-                        const int cnt = (ni - i) * di;
-                        for (int m = wl; m < cnt; m += 64) newV[base + i + m * di] = carried;
                         i = ni;
+                    }
+                    // every node takes the phase-A value of the last mark at or before it along
+                    // the sweep: 64-node chunks, the marks of a chunk by ballot, the last mark
+                    // of the chunks before carried along (the chain head is always marked)
+                    int last = 0;
+                    for (int cb = 0; cb < L; cb += 64) {
+                        const int pos = cb + wl;
+                        const int ii = fwd ? pos : L - 1 - pos;
+                        const unsigned long long mk = __ballot(pos < L && mark[base + ii] != 0);
+                        const unsigned long long below = wl == 63 ? mk : mk & ((2ull << wl) - 1ull);
+                        const int src = below ? cb + 63 - __clzll(below) : last;
+                        if (pos < L) newV[base + ii] = bestV[base + (fwd ? src : L - 1 - src)];
+                        if (mk) last = cb + 63 - __clzll(mk);
                     }
                 }
             } else {
