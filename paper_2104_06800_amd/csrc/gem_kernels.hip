@@ -566,13 +566,15 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                 }
             } else {
                 // with priors: a group of 32 lanes per chain; a value that outlives the
-                // speculation depth is evaluated node by node (energy2_lanes)
+                // speculation depth is evaluated node by node (energy2_lanes); marks and the
+                // fill pass as above
                 for (int c = grp; c < g.C; c += VD_BLOCK / 32) {
                     const int L = chain_len(g, blk, c);
                     if (L <= 0) continue;
                     const int base = c * stride;
                     const int iend = fwd ? L : -1;
                     for (int i = fwd ? 0 : L - 1; i != iend;) {
+                        mark[base + i] = 1;
                         const int2 h = hop[base + i];
                         const float carried = __int_as_float(h.y);
                         int ni = h.x;
@@ -594,9 +596,18 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                         } else if (ni == -2) {
                             ni = iend;
                         }
-                        const int cnt = (ni - i) * di;
-                        for (int m = hl; m < cnt; m += 32) newV[base + i + m * di] = carried;
                         i = ni;
+                    }
+                    // the fill pass as above, 32-node chunks (this group's half of the ballot)
+                    int last = 0;
+                    for (int cb = 0; cb < L; cb += 32) {
+                        const int pos = cb + hl;
+                        const int ii = fwd ? pos : L - 1 - pos;
+                        const unsigned mk = (unsigned)(__ballot(pos < L && mark[base + ii] != 0) >> hbase);
+                        const unsigned below = hl == 31 ? mk : mk & ((2u << hl) - 1u);
+                        const int src = below ? cb + 31 - __clz(below) : last;
+                        if (pos < L) newV[base + ii] = bestV[base + (fwd ? src : L - 1 - src)];
+                        if (mk) last = cb + 31 - __clz(mk);
                     }
                 }
             }
