@@ -536,14 +536,15 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                                         if (mine_node) la_e = fmaf(q_s[tt * nodes + base + jmm], ct, la_e);
                                     }
                                 }
-                                for (int mq = 0; mq < LW; ++mq) {
-                                    const int j = j0 + mq * di;
-                                    if (j < 0 || j >= L) break;
-                                    const float e1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(la_e), mq));
-                                    const float eA = bestE[base + j];
-                                    if (!((e1 < eA) || (e1 == eA && bestS[base + j] > 1))) { ni = j; break; }
+                                // lane m < LW decides node j0 + m di; the first replacing
+                                // node in sweep order is the lowest such lane
+                                bool rep = false;
+                                if (mine_node) {
+                                    const float eA = bestE[base + jmm];
+                                    rep = !((la_e < eA) || (la_e == eA && bestS[base + jmm] > 1));
                                 }
-                                ni = __builtin_amdgcn_readfirstlane(ni);
+                                const unsigned long long rm = __ballot(rep);
+                                if (rm) ni = j0 + (__ffsll((long long)rm) - 1) * di;
                             }
                         } else if (ni == -2) {
                             ni = iend;
