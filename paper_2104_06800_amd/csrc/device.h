@@ -173,9 +173,21 @@ __device__ inline void exp_so3_small(const double w[3], double R[9]) {
     R[7] = a * w[0] + b * w[1] * w[2];
 }
 
-__device__ inline void posed_from_vec(const double* p, PoseD* out) {
-    exp_so3(p, out->R);
-    out->t[0] = p[3]; out->t[1] = p[4]; out->t[2] = p[5];
+// both pose tables of one 6-vector from one rotation: the FP32 table exactly as pose_to_f
+// builds it, and the FP64 rotation and translation
+__device__ inline void pose_tables_from_vec(const double* p, PoseF* f, PoseD* d) {
+    double R[9];
+    exp_so3(p, R);
+    for (int i = 0; i < 9; ++i) {
+        d->R[i] = R[i];
+        f->r[i] = (float)R[i];
+        f->d[i] = (float)(R[i] - ((i & 3) == 0 ? 1.0 : 0.0));
+    }
+    for (int i = 0; i < 3; ++i) {
+        d->t[i] = p[3 + i];
+        f->t[i] = (float)p[3 + i];
+    }
+    f->ident = (p[0] == 0.0 && p[1] == 0.0 && p[2] == 0.0 && p[3] == 0.0 && p[4] == 0.0 && p[5] == 0.0);
 }
 
 __device__ inline void posef_from_d(const PoseD& D, PoseF* out) {

@@ -13,8 +13,7 @@ __device__ __forceinline__ void pose_prep_body(const double* __restrict__ pose, 
                                                int P, PoseF* __restrict__ out, PoseD* __restrict__ outd) {
     const int i = threadIdx.x;
     if (i < N) {
-        pose_to_f(pose + 6 * i, out + i);
-        posed_from_vec(pose + 6 * i, outd + i);
+        pose_tables_from_vec(pose + 6 * i, out + i, outd + i);
     } else if (i < N + P) {
         pose_to_f(prior_pose + 6 * (i - N), out + i);
     }
@@ -1087,8 +1086,8 @@ __global__ void __launch_bounds__(VD_GN_BLOCK) k_pose_gn(Win w, PoseBufs B, int 
 }
 
 // frame i's final pose: the caller's 6-vector, then the FP32 / FP64 tables built from that
-// 6-vector exactly as the pose-table preparation at the start of a step builds them, so the
-// next iteration needs no separate preparation
+// 6-vector with the same function as the pose-table preparation at the start of a step, so
+// the next iteration needs no separate preparation
 __device__ __forceinline__ void final_pose(const PoseBufs& B, int G, int i) {
     const PoseD P = B.hist[(i + 1) * G - 1];
     double v[6];
@@ -1097,8 +1096,7 @@ __device__ __forceinline__ void final_pose(const PoseBufs& B, int G, int i) {
     v[4] = P.t[1];
     v[5] = P.t[2];
     for (int k = 0; k < 6; ++k) B.pose[6 * i + k] = v[k];
-    pose_to_f(v, B.P + i);
-    posed_from_vec(v, B.PD + i);
+    pose_tables_from_vec(v, B.P + i, B.PD + i);
 }
 
 // Step s's solve (one block, the same fixed-order reduction and solve as the prologue of the
