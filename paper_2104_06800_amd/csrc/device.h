@@ -565,15 +565,10 @@ __device__ __forceinline__ float frame_cost(const Win& w, const PoseF* __restric
     return ok ? flow_cost2<B2>(w, fmaf(ex, ex, ey * ey)) : 1.0f;
 }
 
-template <bool B2, bool PR>
-__device__ __forceinline__ float energy2_lanes(const Win& w, const PoseF* __restrict__ P,
-                                               const float4* __restrict__ flow2, const float* __restrict__ prior,
-                                               const Pix& c, float rho, int hl, int hbase) {
-    const float mine = hl < w.N ? frame_cost<B2>(w, P, flow2, c, rho, hl) : 0.f;
-    float E = 0.f;
-#pragma unroll
-    for (int t = 0; t < VD_NMAX; ++t)
-        if (t < w.N) E = fmaf(c.q[t], __shfl(mine, hbase + t), E);
+// E plus the prior terms of E_j(rho) in prior order (the tail of energy2 / energy2_lanes)
+template <bool PR>
+__device__ __forceinline__ float prior_terms(const Win& w, const PoseF* __restrict__ P, const float* __restrict__ prior,
+                                             const Pix& c, float rho, float E) {
     if (!PR) return E;
 #pragma unroll
     for (int k = 0; k < VD_PMAX; ++k) {
@@ -585,6 +580,18 @@ __device__ __forceinline__ float energy2_lanes(const Win& w, const PoseF* __rest
         }
     }
     return E;
+}
+
+template <bool B2, bool PR>
+__device__ __forceinline__ float energy2_lanes(const Win& w, const PoseF* __restrict__ P,
+                                               const float4* __restrict__ flow2, const float* __restrict__ prior,
+                                               const Pix& c, float rho, int hl, int hbase) {
+    const float mine = hl < w.N ? frame_cost<B2>(w, P, flow2, c, rho, hl) : 0.f;
+    float E = 0.f;
+#pragma unroll
+    for (int t = 0; t < VD_NMAX; ++t)
+        if (t < w.N) E = fmaf(c.q[t], __shfl(mine, hbase + t), E);
+    return prior_terms<PR>(w, P, prior, c, rho, E);
 }
 
 // E_j(rho) with pruning: all terms are non-negative and the FP32 running sum only grows, so

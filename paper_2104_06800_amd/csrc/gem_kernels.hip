@@ -566,8 +566,8 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                 }
             } else {
                 // with priors: a group of 32 lanes per chain; a value that outlives the
-                // speculation depth is evaluated node by node (energy2_lanes); marks and the
-                // fill pass as above
+                // speculation depth is evaluated at the next 32 / N nodes at once, with each
+                // node's prior terms on its own lane; marks and the fill pass as above
                 for (int c = grp; c < g.C; c += VD_BLOCK / 32) {
                     const int L = chain_len(g, blk, c);
                     if (L <= 0) continue;
@@ -580,18 +580,49 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                         int ni = h.x;
                         if (ni == -1) {
                             ni = iend;
-                            for (int j = i + (g.spec + 1) * di; (fwd ? j < L : j >= 0) && ni == iend; j += di) {
-                                const int o = base + j;
-                                const int kk = g.horizontal ? (c * g.seg + j) : (j * g.C + c);
-                                const BlockPix p = block_pix(g, blk, kk);
-                                Pix cx;
-                                pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, cx);
+                            for (int j0 = i + (g.spec + 1) * di; (fwd ? j0 < L : j0 >= 0) && ni == iend; j0 += LA * di) {
+                                // lane m * N + t: frame t at node j0 + m di; lane m < LA sums node
+                                // m's frame terms in frame order, then adds its prior terms, as
+                                // energy2_lanes does for one node
+                                const int m = hl / w.N, t = hl - m * w.N;
+                                const int jm = j0 + m * di;
+                                float mine = 0.f;
+                                if (m < LA && jm >= 0 && jm < L) {
+                                    const int kk = g.horizontal ? (c * g.seg + jm) : (jm * g.C + c);
+                                    const BlockPix p = block_pix(g, blk, kk);
+                                    Pix cx;
+                                    pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, cx);
+                                    mine = frame_cost<B2>(w, B.P, B.flow2, cx, carried, t);
+                                }
+                                const int mm = min(hl, LA - 1), jmm = j0 + mm * di;
+                                const bool mine_node = hl < LA && jmm >= 0 && jmm < L;
+                                const int on = base + (mine_node ? jmm : 0);
+                                Pix cn;
+                                if (mine_node) {
+                                    const int kk = g.horizontal ? (c * g.seg + jmm) : (jmm * g.C + c);
+                                    const BlockPix p = block_pix(g, blk, kk);
+                                    pix_geometry<PR>(w, B.P, B.flow, p.u, p.v, cn);
 #pragma unroll
-                                for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) cx.q[t] = q_s[t * nodes + o];
-                                prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cx, rcur[o]);
-                                const float e1 = energy2_lanes<B2, PR>(w, B.P, B.flow2, B.prior, cx, carried, hl, hbase);
-                                const float eA = bestE[o];
-                                if (!((e1 < eA) || (e1 == eA && bestS[o] > 1))) ni = j;
+                                    for (int tt = 0; tt < VD_NMAX; ++tt) if (tt < w.N) cn.q[tt] = q_s[tt * nodes + on];
+                                    prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cn, rcur[on]);
+                                }
+                                float e1 = 0.f;
+#pragma unroll
+                                for (int tt = 0; tt < VD_NMAX; ++tt) {
+                                    if (tt < w.N) {
+                                        const float ct = __shfl(mine, hbase + mm * w.N + tt);
+                                        if (mine_node) e1 = fmaf(cn.q[tt], ct, e1);
+                                    }
+                                }
+                                bool rep = false;
+                                if (mine_node) {
+                                    e1 = prior_terms<PR>(w, B.P, B.prior, cn, carried, e1);
+                                    const float eA = bestE[on];
+                                    rep = !((e1 < eA) || (e1 == eA && bestS[on] > 1));
+                                }
+                                // the first replacing node in sweep order: this group's lowest lane
+                                const unsigned rm = (unsigned)(__ballot(rep) >> hbase);
+                                if (rm) ni = j0 + (__ffs(rm) - 1) * di;
                             }
                         } else if (ni == -2) {
                             ni = iend;
