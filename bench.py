@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-window", action="store_true", help="skip the batch / learned-init / proposal parts")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="only the 64-window batch, its windows generated in this process (for profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -113,6 +115,12 @@ def main():
 
     from paper_2104_06800_amd import synth
     from paper_2104_06800_amd.binding import TIMER_COARSE, TIMER_LOCAL, TIMER_POSE, Voldor
+
+    if args.only_batch:
+        lib = Voldor(0)
+        print(json.dumps({"batch": batch_workload(lib, np, torch, args, pool=False)}), flush=True)
+        lib.close()
+        return
 
     t0 = time.time()
     w = synth.make_window(2, 0)
@@ -284,11 +292,18 @@ def align_workload(lib, np, torch, n_pairs=32, reps=5):
     return out
 
 
-def batch_workload(lib, np, torch, args):
+def batch_workload(lib, np, torch, args, pool=True):
     from paper_2104_06800_amd import synth
     t0 = time.time()
     specs = synth.batch_shapes()
-    wins = _pool_generate(synth.batch_window, specs)
+    if pool:
+        wins = _pool_generate(synth.batch_window, specs)
+    else:
+        wins = []
+        for i, sp in enumerate(specs):
+            wins.append(synth.batch_window(sp))
+            if i % 8 == 7:
+                log(f"batch: {i + 1} of {len(specs)} windows generated")
     log(f"batch: {len(wins)} windows generated in {time.time() - t0:.1f}s")
     items = []
     for w in wins:
