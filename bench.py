@@ -46,7 +46,7 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_CAND_FRAME = 50.0
 FLOPS_ESTEP_PER_PIXEL_FRAME = 65.0
 # Non-packed FP32 vector peak: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz.  Packed FP32
-# instructions are disabled in this build, which halves the 157.3 TFLOP/s published peak.
+# instructions are disabled when the library is compiled, which halves the 157.3 TFLOP/s published peak.
 PEAK_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 PEAK_BF16_TFLOPS = 2500.0           # dense BF16 matrix-core peak
 # stored (computed) channel counts of the proposal network's layers: (c_in, c_out, scale)

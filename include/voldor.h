@@ -125,7 +125,7 @@ int voldor_depth_update(voldor_ctx ctx, const voldor_window* win, const voldor_b
                         int iter, int level, void* stream);
 
 /* Scores candidate poses of frame t (1..N) (sec. III-A "Uncertainty-aware Pose Estimation":
- * the quantity its pose samples are judged by).  For each candidate: energy
+ * the quantity its pose samples are scored by).  For each candidate: energy
  * sum_j q_t^j log1p(L0/L1(r)) (invalid terms cost q log 2), the Gauss-Newton normal
  * equations H = sum w J^T J (upper triangle, row-major, 21 values) and g = sum w J^T e of
  * the residual e = p_t - o_t with IRLS weight w = q d cost / d r^2 and J the derivative
@@ -205,7 +205,7 @@ int voldor_timing_read(voldor_ctx ctx, int timer, double* total_ms, int64_t* lau
  * Learned depth / rigidness proposal.  The paper initialises depth at random (sec. III-A);
  * this project adds a small convolutional encoder-decoder that maps the flow stack of a
  * window to an initial inverse depth and initial rigidness maps, while plain GEM stays the
- * fallback and the judge of its error.  BF16 weights and activations, FP32 accumulation on
+ * fallback and the reference for its error.  BF16 weights and activations, FP32 accumulation on
  * the matrix cores, FP32 master weights and Adam.
  *
  * Layers (3x3, zero padding 1, NHWC; stored channel counts):

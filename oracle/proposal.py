@@ -3,7 +3,7 @@ stack of a window, FP64 (test infrastructure).
 
 The project's extension of the method (its initial depth is random in the paper, sec. III-A):
 a network maps the N flows to an initial inverse depth and initial rigidness maps, and GEM
-starts from them.  Plain GEM stays the fallback and the judge of the proposal's error.
+starts from them.  Plain GEM stays the fallback and the reference for the proposal's error.
 
 Architecture (3x3 convolutions, zero padding 1, NHWC; channel counts as stored, the real
 ones in brackets):
