@@ -18,6 +18,10 @@
 #ifndef VD_GN_PIX
 #define VD_GN_PIX 2
 #endif
+// pixels per thread whose loads are issued together (the grid is sized by VD_GN_PIX)
+#ifndef VD_GN_UB
+#define VD_GN_UB 4
+#endif
 #define VD_SPEC 8       // maximum speculation depth of the chain scan
 // lanes per lattice node in the separate phase-A grid (a power of two; one Philox group of
 // four candidates per lane at K = 32)

@@ -999,7 +999,7 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
     const float* __restrict__ rig = B.rigid + (size_t)(t - 1) * plane;
     float2* __restrict__ obs = B.obs;
     const int stride = (int)nb * VD_GN_BLOCK;
-    constexpr int UB = VD_GN_PIX;          // pixels per thread and batch: loads issued together
+    constexpr int UB = VD_GN_UB;           // pixels per thread and batch: loads issued together
     float rho[UB], q[UB], ox[UB], oy[UB];
     int jj[UB];
     auto load = [&](int j0) {
