@@ -999,7 +999,10 @@ __device__ __forceinline__ void pose_gn_body(const Win& w, const PoseBufs& B, in
     const float* __restrict__ rig = B.rigid + (size_t)(t - 1) * plane;
     float2* __restrict__ obs = B.obs;
     const int stride = (int)nb * VD_GN_BLOCK;
-    constexpr int UB = VD_GN_UB;           // pixels per thread and batch: loads issued together
+    // pixels per thread and batch, loads issued together: all of a thread's pixels for one
+    // window (one block per CU, registers to spare); two in the batched pass, whose many
+    // blocks per CU need the occupancy.  The pixel order, and so every sum, is the same.
+    constexpr int UB = SPLIT ? VD_GN_PIX : VD_GN_UB;
     float rho[UB], q[UB], ox[UB], oy[UB];
     int jj[UB];
     auto load = [&](int j0) {
