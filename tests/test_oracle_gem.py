@@ -374,3 +374,92 @@ def test_confidence_reduces_to_per_node_bayes():
     np.testing.assert_allclose(b["conf"].ravel(), C, atol=1e-12)
     assert st[5] == pytest.approx(C.sum(), rel=1e-12)
     assert st[2] + st[3] == 3 * lv.u.size
+
+
+# ----------------------------------------------------------------------------- prior transfer (Eq. 3)
+def _prior_window(H, W, prior_pose, prior_map, f=40.0):
+    w, win = small_window(N=1, H=H, W=W, P=1)
+    win = dict(win, fx=f, fy=f, cx=(W - 1) / 2 + 0.3, cy=(H - 1) / 2 - 0.2)
+    b = gem.alloc_buffers(win, w["flow"], w["pose_gt"], prior_map[None], np.asarray(prior_pose)[None])
+    return win, gem.Window(win, b)
+
+
+@pytest.mark.parametrize("tz", [0.8, -0.35])
+def test_prior_transfer_pure_forward_translation_closed_form(tz):
+    """Prior camera displaced by t_z along the optical axis: the point of pixel j at inverse
+    depth rho lies at depth 1/rho + t_z in the prior camera, so 1/phi_z = rho/(1 + rho t_z)
+    and it projects to c + (j - c)/(1 + rho t_z); the prior value is read at the nearest
+    pixel of that point (Eq. 3: l = pi(theta^j, T^_k), compared with 1/phi_z)."""
+    H, W = 30, 40
+    yy, xx = np.mgrid[0:H, 0:W]
+    prior = 0.1 + 0.003 * xx + 0.0011 * yy          # distinct value at every pixel
+    win, ww = _prior_window(H, W, [0, 0, 0, 0, 0, tz], prior)
+    rng = np.random.default_rng(21)
+    u = rng.integers(0, W, 400)
+    v = rng.integers(0, H, 400)
+    rho = rng.uniform(0.05, 1.0, 400)
+    z, ok = ww.prior_z(0, u, v, rho)
+    D = 1.0 + rho * tz
+    front = D > 0
+    lx = np.floor((u - win["cx"]) / np.where(front, D, 1) + win["cx"] + 0.5)
+    ly = np.floor((v - win["cy"]) / np.where(front, D, 1) + win["cy"] + 0.5)
+    inside = front & (lx >= 0) & (lx <= W - 1) & (ly >= 0) & (ly <= H - 1)
+    assert inside.sum() > 100 and (tz > 0 or (~inside).sum() > 5)
+    np.testing.assert_array_equal(ok, inside)
+    rh = 0.1 + 0.003 * lx + 0.0011 * ly
+    want = (rh - rho / D) / (win["prior_sigma_rel"] * rh)
+    np.testing.assert_allclose(z[inside], want[inside], rtol=1e-12, atol=1e-12)
+    assert (z[~inside] == 0).all()
+
+
+def test_prior_transfer_rotated_camera_matches_ray_caster():
+    """A rotated and translated prior camera looking at two planes that are fronto-parallel
+    to it (one in front of the other), its inverse-depth map ray-cast by the input
+    generator: at the true reference inverse depth every pixel whose transfer lands inside
+    one plane's image region has z = 0 to rounding, since the prior value is constant
+    over each plane.  A tilted third plane bounds z by the map's gradient over half a
+    pixel (nearest sampling).  A wrong direction of T^ or of the depth transfer breaks
+    both."""
+    H, W, f = 36, 48, 40.0
+    intr = (f, f, (W - 1) / 2 + 0.3, (H - 1) / 2 - 0.2)
+    Rk = synth._rot(np.deg2rad([3.0, -4.0, 2.0]))
+    tk = np.array([0.12, -0.05, 0.3])
+    axis = Rk[2]                                    # prior camera's optical axis, world frame
+    cam_c = -Rk.T @ tk                              # prior camera centre, world frame
+    planes_n, planes_d = [], []
+    for depth in (4.0, 9.0):                        # fronto-parallel to the prior camera
+        planes_n.append(-axis)
+        planes_d.append(-(axis @ cam_c + depth))
+    scene = synth.Scene(planes_n=np.array(planes_n), planes_d=np.array(planes_d),
+                        quads=[synth._quad([1.0, 0.3, 3.0], 25.0, 10.0, 0.9, 0.6)])
+    z_ref, obj_ref, _ = synth._raycast(scene, 0, H, W, intr, (np.eye(3), np.zeros(3)))
+    z_k, obj_k, _ = synth._raycast(scene, 0, H, W, intr, (Rk, tk))
+    pose_k = synth._as6((Rk, tk))
+    win, ww = _prior_window(H, W, pose_k, 1.0 / z_k, f=f)
+    win.update(cx=intr[2], cy=intr[3])
+    ww = gem.Window(win, ww.b)
+    V, U = np.mgrid[0:H, 0:W]
+    u, v = U.ravel(), V.ravel()
+    rho = 1.0 / z_ref.ravel()
+    z, ok = ww.prior_z(0, u, v, rho)
+    # where does each reference point land in the prior camera (generator's projection)
+    X = synth._rays(H, W, *intr, (np.eye(3), np.zeros(3)))[1].reshape(-1, 3) * z_ref.ravel()[:, None]
+    px, py, _ = synth._project(X, (Rk, tk), intr)
+    lx, ly = np.floor(px + 0.5).astype(int), np.floor(py + 0.5).astype(int)
+    inside = (lx >= 1) & (lx <= W - 2) & (ly >= 1) & (ly <= H - 2)
+    assert ok[inside].all()
+    lxc, lyc = np.clip(lx, 0, W - 1), np.clip(ly, 0, H - 1)
+    same_obj = obj_k[lyc, lxc] == obj_ref.ravel()   # the prior pixel sees the same surface
+    nb = np.stack([obj_k[np.clip(lyc + dy, 0, H - 1), np.clip(lxc + dx, 0, W - 1)]
+                   for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+    interior = inside & same_obj & (nb == obj_k[lyc, lxc]).all(0)
+    flat = interior & (obj_ref.ravel() < 100)
+    tilted = interior & (obj_ref.ravel() >= 100)
+    assert flat.sum() > 300 and tilted.sum() > 30
+    assert np.abs(z[flat]).max() < 1e-9
+    rk = 1.0 / z_k
+    gx = np.abs(rk[lyc, np.clip(lxc + 1, 0, W - 1)] - rk[lyc, lxc])
+    gy = np.abs(rk[np.clip(lyc + 1, 0, H - 1), lxc] - rk[lyc, lxc])
+    diff = np.abs(z * win["prior_sigma_rel"] * rk[lyc, lxc])   # |rho^(l) - 1/phi_z|
+    assert (diff[tilted] <= 0.5 * (gx + gy)[tilted] * 1.01 + 1e-12).all()
+    assert np.abs(z[tilted]).max() > 1e-6        # nearest sampling is visible there
