@@ -18,6 +18,7 @@ Modules
   fisk     log-logistic planar residual density, MIE energy terms, IRLS weight
   gem      E-step, M-step, pose step, depth priors, confidence, GEM iteration
   align    point-to-plane inverse-depth keyframe alignment
+  vc       visibility-coverage scores for VO stride and keyframe selection
   proposal the learned depth / rigidness proposal network (forward, backward, Adam)
 """
-from . import philox, geometry, fisk, gem, align, proposal  # noqa: F401
+from . import philox, geometry, fisk, gem, align, proposal, vc  # noqa: F401
