@@ -173,6 +173,21 @@ int voldor_finalize(voldor_ctx ctx, const voldor_window* win, const voldor_buffe
 int voldor_run(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
                int first_iter, int n_iters, int flags, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): voldor_run with the same arguments and
+ * the same results bit for bit, whose scratch is a static device array of
+ * VOLDOR_NOALLOC_SCRATCH_BYTES (64 MiB) per device instead of the context's grown buffer.
+ * It calls no allocating routine and records no timer events.  The array is loaded with the
+ * library's code object on each device it runs on and held until the process ends; its
+ * address is looked up when a context is created on that device.  It holds windows up to
+ * 1216x352 with N = 8; a window needing more scratch returns VOLDOR_EINVAL before anything is
+ * enqueued.  Every call on one device shares that array and leaves its contents behind
+ * (nothing in it needs clearing: each kernel writes what it later reads): calls that overlap
+ * on one device, on any streams or contexts, race and must be serialised by the caller. */
+#define VOLDOR_NOALLOC_SCRATCH_BYTES (64u << 20)
+int voldor_run_noalloc(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
+                       int first_iter, int n_iters, int flags, void* stream);
+
 /* n_windows independent windows (wins[i] with bufs[i]; shapes, N, K, priors may differ),
  * each as voldor_run from iteration 0 with the same n_iters and flags (VOLDOR_RUN_INIT),
  * bit for bit.  Each

@@ -16,6 +16,7 @@ COARSE, LOCAL = 0, 1
 RUN_INIT, RUN_NO_GRAPH = 1, 2
 TIMER_LOCAL, TIMER_COARSE, TIMER_POSE = 0, 1, 2
 NET_PARAMS = 470560
+NOALLOC_SCRATCH_BYTES = 64 << 20
 SCORE_LEN = 29
 STATS_LEN = 8
 MAX_FRAMES, MAX_PRIORS = 8, 4
@@ -58,7 +59,7 @@ class AlignParams(ctypes.Structure):
 EXPORTS = sorted(["voldor_ctx_create", "voldor_ctx_destroy", "voldor_last_error", "voldor_lattice_shape",
                   "voldor_init_idepth", "voldor_rigidness_fb", "voldor_depth_update", "voldor_level_step",
                   "voldor_pose_score", "voldor_pose_step", "voldor_gem_step", "voldor_finalize",
-                  "voldor_run", "voldor_batch_run", "voldor_timing", "voldor_timing_read",
+                  "voldor_run", "voldor_run_noalloc", "voldor_batch_run", "voldor_timing", "voldor_timing_read",
                   "voldor_net_refresh", "voldor_proposal_forward", "voldor_proposal_train_step",
                   "voldor_conv3x3_bf16", "voldor_conv3x3_bf16_backward",
                   "voldor_align_p2p"])
@@ -86,6 +87,7 @@ def load_library(path=LIB):
     lib.voldor_gem_step.argtypes = [V, W, B, I, V]
     lib.voldor_finalize.argtypes = [V, W, B, I, V]
     lib.voldor_run.argtypes = [V, W, B, I, I, I, V]
+    lib.voldor_run_noalloc.argtypes = [V, W, B, I, I, I, V]
     lib.voldor_batch_run.argtypes = [V, I, W, B, I, I, V]
     lib.voldor_timing.argtypes = [V, I]
     lib.voldor_timing_read.argtypes = [V, I, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -240,6 +242,12 @@ class Voldor:
         iters = p.get("iters", 5) if iters is None else iters
         self._check(_LIB.voldor_run(self._h, make_window(p), self._bufs(p, b), first_iter, iters,
                                     RUN_INIT if init else 0, _stream(stream)), "voldor_run")
+
+    def run_noalloc(self, p, b, iters=None, init=True, first_iter=0, stream=None):
+        """As run, with the library's static per-device scratch (no allocation)."""
+        iters = p.get("iters", 5) if iters is None else iters
+        self._check(_LIB.voldor_run_noalloc(self._h, make_window(p), self._bufs(p, b), first_iter, iters,
+                                            RUN_INIT if init else 0, _stream(stream)), "voldor_run_noalloc")
 
     def batch_run(self, windows, iters, init=True, graph=True, stream=None):
         """windows: list of (params, buffers); every window runs iters iterations, batched

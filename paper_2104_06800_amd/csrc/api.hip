@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -17,7 +18,45 @@
 using vdc::fail;
 using vdc::hip_fail;
 
+// Scratch of voldor_run_noalloc: one copy per device, loaded with the code object and held
+// until the process ends.  Host code never passes this name to a kernel (on the host it is
+// a stand-in, not a device address); it uses the per-device address that
+// hipGetSymbolAddress returns at context creation.
+static __device__ __align__(256) unsigned char scratch[VOLDOR_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+// device address of `scratch` per device ordinal, looked up once with that device current
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+hipError_t g_noalloc_err[kMaxDevices] = {};
+
+// Looks up the address of the static scratch on the current device (ordinal dev), once.
+void noalloc_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[dev]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        g_noalloc_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        return;
+    }
+    g_noalloc_ptr[dev] = p;
+    g_noalloc_err[dev] = hipSuccess;
+}
+
+void* noalloc_base(int dev, hipError_t* err) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    *err = g_noalloc_err[dev];
+    return g_noalloc_ptr[dev];
+}
 
 constexpr size_t kMaxBatch = 4096;         // candidates per pose_score call / pairs per align call
 constexpr size_t kLevelLdsMax = 150 * 1024;
@@ -196,6 +235,7 @@ struct GemLaunch {
     int gn_blocks;
     int pose_blocks;
     int max_level_blocks;
+    bool timers = true;   // bracket launches with the context's timers (when enabled)
     struct { size_t head, f2, hist, obs, ll, red, pa; } sz;
 };
 
@@ -320,7 +360,7 @@ int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll)
     const vd::LevelBufs B = level_bufs(L, level, want_ll);
     hipEvent_t t0 = nullptr;
     const int timer = level == VOLDOR_LEVEL_COARSE ? VOLDOR_TIMER_COARSE : VOLDOR_TIMER_LOCAL;
-    const bool timed = level == VOLDOR_LEVEL_COARSE || (do_e && do_m);
+    const bool timed = L.timers && (level == VOLDOR_LEVEL_COARSE || (do_e && do_m));
     if (timed) VD_CHECK(timer_start(ctx, timer, L.st, &t0), "timer event");
     if (level == VOLDOR_LEVEL_COARSE && do_m) {
         // few long chains: E-step per chain, phase A over the whole lattice, then the
@@ -343,7 +383,7 @@ int run_pose_step(GemLaunch& L) {
     const int G = L.v->pose_gn_steps;
     if (G == 0) return VOLDOR_OK;
     hipEvent_t t0 = nullptr;
-    VD_CHECK(timer_start(ctx, VOLDOR_TIMER_POSE, L.st, &t0), "timer event");
+    if (L.timers) VD_CHECK(timer_start(ctx, VOLDOR_TIMER_POSE, L.st, &t0), "timer event");
     for (int s = 0; s < L.v->N * G; ++s)
         VD_CHECK(vd::launch_pose_gn(w, B, s, G, L.gn_blocks, L.st), "pose step launch");
     VD_CHECK(vd::launch_pose_gn_finish(B, L.v->N, G, L.gn_blocks, L.st), "pose finish launch");
@@ -709,6 +749,7 @@ int voldor_ctx_create(voldor_ctx* out, int device_ordinal) {
         delete c;
         return fail(nullptr, VOLDOR_EDEVICE, "cannot raise the LDS limit of the level kernel");
     }
+    noalloc_setup(device_ordinal);
     *out = c;
     return VOLDOR_OK;
 }
@@ -861,6 +902,29 @@ int voldor_run(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, 
     VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
     GemLaunch L;
     if ((rc = gem_prepare(ctx, v, b, st, L))) return rc;
+    return run_window(L, first_iter, n_iters, flags);
+}
+
+int voldor_run_noalloc(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int first_iter,
+                       int n_iters, int flags, void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    if (!b->conf || !b->stats) return fail(ctx, VOLDOR_EINVAL, "null conf/stats pointer");
+    if (n_iters < 1 || first_iter < 0 || (int64_t)first_iter + n_iters > 0xffffff)
+        return fail(ctx, VOLDOR_EINVAL, "need n_iters >= 1 and first_iter >= 0");
+    if (flags & ~VOLDOR_RUN_INIT) return fail(ctx, VOLDOR_EINVAL, "unknown flags 0x%x", flags);
+    GemLaunch L;
+    L.ctx = ctx; L.v = v; L.b = b; L.st = (hipStream_t)stream;
+    L.timers = false;
+    const size_t need = gem_layout(v, 1, L);
+    if (need > (size_t)VOLDOR_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, VOLDOR_EINVAL, "window %dx%d with N=%d needs %zu bytes of scratch; the static area holds %zu",
+                    v->W, v->H, v->N, need, (size_t)VOLDOR_NOALLOC_SCRATCH_BYTES);
+    hipError_t e = hipSuccess;
+    void* base = noalloc_base(ctx->device, &e);
+    if (!base) return hip_fail(ctx, e, "static scratch address of this device");
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    gem_carve((char*)base, L);
     return run_window(L, first_iter, n_iters, flags);
 }
 
