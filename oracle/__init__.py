@@ -19,6 +19,7 @@ Modules
   gem      E-step, M-step, pose step, depth priors, confidence, GEM iteration
   align    point-to-plane inverse-depth keyframe alignment
   vc       visibility-coverage scores for VO stride and keyframe selection
+  pose_sample  Monte-Carlo P3P pose samples, meanshift mode and pose covariance
   proposal the learned depth / rigidness proposal network (forward, backward, Adam)
 """
-from . import philox, geometry, fisk, gem, align, proposal, vc  # noqa: F401
+from . import philox, geometry, fisk, gem, align, proposal, vc, pose_sample  # noqa: F401
