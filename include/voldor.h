@@ -142,6 +142,33 @@ int voldor_pose_score(voldor_ctx ctx, const voldor_window* win, const voldor_buf
 int voldor_pose_step(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf,
                      void* stream);
 
+/* The paper's pose M-step (sec. III-A "Uncertainty-aware Pose Estimation", its sampling
+ * equation), an alternative to voldor_pose_step: for frames t = 1..N in order (each frame's
+ * observations use the already updated pose of frame t-1), S pose samples, each the P3P
+ * solution (of those nearest the frame's current pose in the kernel metric) of three pixels
+ * drawn with probability proportional to q_t -- a Philox draw picks a pixel, a second
+ * accepts it when below q_t and the pixel has a depth and an observation
+ * o_t = p_{t-1} + X_t(p_{t-1}), up to `tries` attempts per point; counter (sample,
+ * point * tries + attempt, (iter << 8) | (t << 4) | 2, window id); the frame's pose becomes
+ * the mode of the samples found by meanshift with the Gaussian kernel
+ * diag(sigma_w^2 I, (sigma_t_rel |t|)^2 I) in the left-update chart of the pose step,
+ * started at the current pose.  Its uncertainty Sigma_t (cov_out [N][36], FP64 device, or
+ * NULL) is fitted to the samples from the mode by iterated 3-sigma inlier fits, each inlier
+ * covariance divided by P(chi2_8 <= 9) / P(chi2_6 <= 9) so that a Gaussian's own covariance
+ * is the fixed point, eigenvalues floored at eps.  info_out [N][4] (or NULL): valid
+ * samples, inliers, meanshift steps, fit rounds.  A frame without valid samples keeps its
+ * pose.  FP64 throughout. */
+#define VOLDOR_POSE_MAX_SAMPLES 4096
+typedef struct {
+    int32_t samples;           /* S, 1..4096                                           */
+    int32_t tries;             /* draw attempts per point, 1..64                       */
+    double sigma_w;            /* kernel std of the rotation coordinates (rad)         */
+    double sigma_t_rel;        /* kernel std of the translation coordinates / |t|      */
+    double eps;                /* eigenvalue floor of Sigma_t                          */
+} voldor_sample_params;
+int voldor_pose_sample(voldor_ctx ctx, const voldor_window* win, const voldor_buffers* buf, int iter,
+                       const voldor_sample_params* sp, double* cov_out, double* info_out, void* stream);
+
 /* One pass of one level: its E-step immediately followed by its M-step (same chains,
  * direction iter mod 4), fused in a single launch; equivalent to voldor_rigidness_fb then
  * voldor_depth_update on the same level. */
@@ -200,6 +227,30 @@ int voldor_run_noalloc(voldor_ctx ctx, const voldor_window* win, const voldor_bu
  * is launched.  The first call for a set waits for the stream once (table upload). */
 int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, const voldor_buffers* bufs,
                      int n_iters, int flags, void* stream);
+
+/* Launch knobs (tuning).  Settings that change how the work is split over the chip and
+ * never what is computed: every run gives the same results bit for bit whatever they are.
+ * 0 keeps a knob's default.
+ *   local_chains  local-level chain segments per block (default: as many as fit the block,
+ *                 8 for 32x32 tiles); fewer means more, lighter blocks
+ *   local_spec    speculation depth of the local scan, 1..8 (default 2): predecessor
+ *                 energies evaluated ahead in the parallel phase
+ *   coarse_spec   speculation depth of the coarse scan, 1..8 (default 8)
+ *   coarse_lanes  lanes per lattice node of the coarse phase-A grid, 4, 8 or 16 (default 8;
+ *                 the batched run keeps 8) */
+typedef struct {
+    int32_t local_chains;
+    int32_t local_spec;
+    int32_t coarse_spec;
+    int32_t coarse_lanes;
+} voldor_knobs;
+
+/* Sets (knobs != NULL) or removes (NULL) the knobs of every window with the same H, W, N,
+ * n_candidates and presence of priors as `bucket` (host structs).  Drops a captured batch
+ * graph. */
+int voldor_set_knobs(voldor_ctx ctx, const voldor_window* bucket, const voldor_knobs* knobs);
+/* The knobs that calls on `win` use (zeros: defaults). */
+int voldor_get_knobs(voldor_ctx ctx, const voldor_window* win, voldor_knobs* out);
 
 /* Launch timers (measurement).  The library brackets launches of each enabled timer class
  * with HIP events on the launch stream: VOLDOR_TIMER_LOCAL = the fused local-level E+M
@@ -280,6 +331,23 @@ int voldor_conv3x3_bf16_backward(voldor_ctx ctx, int32_t H, int32_t W, int32_t C
                                  int32_t stride, int32_t up, const uint16_t* x, const uint16_t* w_t,
                                  const uint16_t* dy, float* dx, float* dw, float* db, void* stream);
 
+/* Learned start of one GEM window: the network on buf->flow writes buf->idepth and buf->rigid,
+ * with tnorm = |t| of buf->pose's frame 1 read on the device.  Where its output is unusable
+ * (a non-finite depth logit anywhere, or a non-finite or zero tnorm) the whole window takes
+ * voldor_init_idepth's random start instead and *fallback_out (device int32, or NULL) is set
+ * to 1, else 0.  voldor_run(first_iter 0, k iterations, flags 0) then runs GEM from it; after
+ * a fallback, voldor_run(first_iter k, I - k iterations, flags 0) completes plain GEM's
+ * I-iteration run bit for bit.  H and W even. */
+int voldor_proposal_start(voldor_ctx ctx, const voldor_net* net, const voldor_window* win, const voldor_buffers* buf,
+                          int32_t* fallback_out, void* stream);
+
+/* voldor_batch_run with every window started by the proposal network as voldor_proposal_start
+ * does (VOLDOR_RUN_INIT is ignored): windows with odd H or W, and windows whose network
+ * output is unusable, take the random start (fallback_out[i] = 1, device int32 [n_windows],
+ * or NULL).  The starts are part of the captured graph. */
+int voldor_batch_run_learned(voldor_ctx ctx, const voldor_net* net, int n_windows, const voldor_window* wins,
+                             const voldor_buffers* bufs, int n_iters, int flags, int32_t* fallback_out, void* stream);
+
 /* Keyframe-alignment parameters (sec. III-B, Eqs. 10, 12). */
 typedef struct {
     int32_t H, W;
@@ -303,6 +371,36 @@ typedef struct {
 int voldor_align_p2p(voldor_ctx ctx, const voldor_align_params* ap, int n_pairs,
                      const float* idepth1, const float* idepth2, const float* conf2,
                      double* pose_inout, double* cov_out, double* stats_out, int32_t* status_out,
+                     void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Visibility-coverage scores (sec. III-A "VO Stride and Keyframe Selection", its VC
+ * equation): frame 1 carries an inverse-depth map, frame 2 only a pose.  A depth pixel is
+ * a pixel of frame 1 with finite inverse depth > 0 (and conf >= conf_min when conf is
+ * given).  visibility = share of depth pixels whose projection (FP64, in front of camera 2)
+ * has its nearest pixel inside frame 2's H x W image; coverage = share of frame 2's
+ * cell x cell blocks (ragged at the far edges) holding at least one such nearest pixel;
+ * VC = 2 / (visibility^-1 + coverage^-1), 0 when either is 0.
+ * ------------------------------------------------------------------------------- */
+#define VOLDOR_VC_MAX_POSES 1024
+#define VOLDOR_VC_OUT_LEN 5    /* visibility, coverage, VC, visible depth pixels, covered cells */
+
+typedef struct {
+    int32_t H, W;              /* image size of both frames                            */
+    float fx, fy, cx, cy;      /* pinhole intrinsics of both frames                    */
+    int32_t cell;              /* coverage cell size in pixels, 1..1024                */
+    float conf_min;            /* depth-pixel confidence threshold (when conf is set)  */
+} voldor_vc_params;
+
+/* Scores of frame 1 (idepth [H][W] FP32, conf [H][W] FP32 or NULL) against n_poses poses of
+ * frame 2 (poses [n][6] FP64, mapping frame-1 points to frame 2), 1 <= n_poses <= 1024:
+ * out [n][5] FP64 as VOLDOR_VC_OUT_LEN lists; first_below (one int32, or NULL) receives the
+ * index of the first pose whose VC is below tau, or n_poses when none is.  With the poses
+ * of a batch's frames relative to its reference and tau = tau_stride, that index is the next
+ * batch's reference; with the pose of the latest keyframe and tau = tau_keyframe, 0 makes
+ * the reference a keyframe.  All device memory. */
+int voldor_vc_scores(voldor_ctx ctx, const voldor_vc_params* vp, const float* idepth, const float* conf,
+                     int n_poses, const double* poses, double tau, double* out, int32_t* first_below,
                      void* stream);
 
 #ifdef __cplusplus

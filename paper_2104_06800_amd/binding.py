@@ -17,6 +17,7 @@ RUN_INIT, RUN_NO_GRAPH = 1, 2
 TIMER_LOCAL, TIMER_COARSE, TIMER_POSE = 0, 1, 2
 NET_PARAMS = 470560
 NOALLOC_SCRATCH_BYTES = 64 << 20
+VC_OUT_LEN, VC_MAX_POSES = 5, 1024
 SCORE_LEN = 29
 STATS_LEN = 8
 MAX_FRAMES, MAX_PRIORS = 8, 4
@@ -59,10 +60,28 @@ class AlignParams(ctypes.Structure):
 EXPORTS = sorted(["voldor_ctx_create", "voldor_ctx_destroy", "voldor_last_error", "voldor_lattice_shape",
                   "voldor_init_idepth", "voldor_rigidness_fb", "voldor_depth_update", "voldor_level_step",
                   "voldor_pose_score", "voldor_pose_step", "voldor_gem_step", "voldor_finalize",
-                  "voldor_run", "voldor_run_noalloc", "voldor_batch_run", "voldor_timing", "voldor_timing_read",
+                  "voldor_run", "voldor_run_noalloc", "voldor_batch_run", "voldor_batch_run_learned",
+                  "voldor_proposal_start", "voldor_timing", "voldor_timing_read",
                   "voldor_net_refresh", "voldor_proposal_forward", "voldor_proposal_train_step",
                   "voldor_conv3x3_bf16", "voldor_conv3x3_bf16_backward",
-                  "voldor_align_p2p"])
+                  "voldor_align_p2p", "voldor_vc_scores", "voldor_set_knobs", "voldor_get_knobs",
+                  "voldor_pose_sample"])
+
+
+class Knobs(ctypes.Structure):
+    _fields_ = [("local_chains", ctypes.c_int32), ("local_spec", ctypes.c_int32),
+                ("coarse_spec", ctypes.c_int32), ("coarse_lanes", ctypes.c_int32)]
+
+
+class SampleParams(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int32), ("tries", ctypes.c_int32), ("sigma_w", ctypes.c_double),
+                ("sigma_t_rel", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+class VcParams(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("cell", ctypes.c_int32), ("conf_min", ctypes.c_float)]
 
 
 def load_library(path=LIB):
@@ -89,7 +108,12 @@ def load_library(path=LIB):
     lib.voldor_run.argtypes = [V, W, B, I, I, I, V]
     lib.voldor_run_noalloc.argtypes = [V, W, B, I, I, I, V]
     lib.voldor_batch_run.argtypes = [V, I, W, B, I, I, V]
+    lib.voldor_batch_run_learned.argtypes = [V, P(Net), I, W, B, I, I, V, V]
+    lib.voldor_proposal_start.argtypes = [V, P(Net), W, B, V, V]
     lib.voldor_timing.argtypes = [V, I]
+    lib.voldor_set_knobs.argtypes = [V, W, P(Knobs)]
+    lib.voldor_pose_sample.argtypes = [V, W, B, I, P(SampleParams), V, V, V]
+    lib.voldor_get_knobs.argtypes = [V, W, P(Knobs)]
     lib.voldor_timing_read.argtypes = [V, I, P(ctypes.c_double), P(ctypes.c_int64)]
     F = ctypes.c_float
     lib.voldor_net_refresh.argtypes = [V, P(Net), V]
@@ -98,6 +122,7 @@ def load_library(path=LIB):
     lib.voldor_conv3x3_bf16.argtypes = [V, I, I, I, I, I, I, I, V, V, V, V, V, V, V]
     lib.voldor_conv3x3_bf16_backward.argtypes = [V, I, I, I, I, I, I, V, V, V, V, V, V, V]
     lib.voldor_align_p2p.argtypes = [V, P(AlignParams), I, V, V, V, V, V, V, V, V]
+    lib.voldor_vc_scores.argtypes = [V, P(VcParams), V, V, I, V, ctypes.c_double, V, V, V]
     for n in EXPORTS:
         if n not in ("voldor_ctx_destroy", "voldor_last_error"):
             getattr(lib, n).restype = ctypes.c_int
@@ -258,6 +283,43 @@ class Voldor:
         flags = (RUN_INIT if init else 0) | (0 if graph else RUN_NO_GRAPH)
         self._check(_LIB.voldor_batch_run(self._h, n, wins, bufs, iters, flags, _stream(stream)), "voldor_batch_run")
 
+    def pose_sample(self, p, b, it, sp, stream=None):
+        """The sampled pose M-step over frames 1..N (updates b["pose"]); sp: dict of
+        SampleParams fields.  Returns (cov [N][36], info [N][4]) FP64 device tensors."""
+        dev = b["pose"].device
+        cov = torch.zeros((p["N"], 36), dtype=torch.float64, device=dev)
+        info = torch.zeros((p["N"], 4), dtype=torch.float64, device=dev)
+        s = SampleParams(**{k: sp[k] for k, _ in SampleParams._fields_})
+        self._check(_LIB.voldor_pose_sample(self._h, make_window(p), self._bufs(p, b), it, ctypes.byref(s), _ptr(cov),
+                                            _ptr(info), _stream(stream)), "voldor_pose_sample")
+        return cov, info
+
+    def set_knobs(self, p, knobs=None):
+        """Launch knobs (dict of Knobs fields; None removes) for windows shaped like p."""
+        k = None if knobs is None else ctypes.byref(Knobs(**{n: int(knobs.get(n, 0)) for n, _ in Knobs._fields_}))
+        self._check(_LIB.voldor_set_knobs(self._h, make_window(p), k), "voldor_set_knobs")
+
+    def get_knobs(self, p):
+        k = Knobs()
+        self._check(_LIB.voldor_get_knobs(self._h, make_window(p), ctypes.byref(k)), "voldor_get_knobs")
+        return {n: getattr(k, n) for n, _ in Knobs._fields_}
+
+    def batch_run_learned(self, net, windows, iters, graph=True, fallback=None, stream=None):
+        """batch_run with every window started by the proposal network; fallback (int32
+        device tensor [n] or None) receives 1 where a window took the random start."""
+        n = len(windows)
+        wins = (Window * n)(*[make_window(p) for p, _ in windows])
+        bufs = (Buffers * n)(*[self._bufs(p, b) for p, b in windows])
+        flags = 0 if graph else RUN_NO_GRAPH
+        self._check(_LIB.voldor_batch_run_learned(self._h, ctypes.byref(self._net(net)), n, wins, bufs, iters, flags,
+                                                  _ptr(fallback), _stream(stream)), "voldor_batch_run_learned")
+
+    def proposal_start(self, net, p, b, fallback=None, stream=None):
+        """The proposal network's start of window (p, b): writes b's idepth and rigid; fallback
+        (int32 device tensor [1] or None) receives 1 where the random start replaced it."""
+        self._check(_LIB.voldor_proposal_start(self._h, ctypes.byref(self._net(net)), make_window(p), self._bufs(p, b),
+                                               _ptr(fallback), _stream(stream)), "voldor_proposal_start")
+
     def timing(self, enable, timers=(TIMER_LOCAL, TIMER_COARSE, TIMER_POSE)):
         """Starts (afresh) or stops the launch timers of the given classes."""
         mask = sum(1 << t for t in set(timers)) if enable else 0
@@ -353,3 +415,21 @@ class Voldor:
                                           _ptr(pose_inout), _ptr(cov), _ptr(stats), _ptr(status),
                                           _stream(stream)), "voldor_align_p2p")
         return cov, stats, status
+
+    def vc_scores(self, vp, idepth, conf, poses, tau, stream=None):
+        """Visibility-coverage scores of frame 1's idepth [H][W] (conf [H][W] or None) against
+        poses [n][6]: returns (out [n][5] FP64 device tensor, first index with VC < tau)."""
+        dev = idepth.device
+        poses = torch.as_tensor(poses, dtype=torch.float64).to(dev).reshape(-1, 6).contiguous()
+        if idepth.dtype != torch.float32 or not idepth.is_cuda or not idepth.is_contiguous() \
+                or tuple(idepth.shape) != (vp["H"], vp["W"]):
+            raise VoldorError("idepth must be a contiguous FP32 [H][W] device tensor")
+        if conf is not None and (conf.dtype != torch.float32 or conf.shape != idepth.shape or not conf.is_contiguous()):
+            raise VoldorError("conf must be a contiguous FP32 [H][W] device tensor")
+        n = poses.shape[0]
+        out = torch.zeros((n, 5), dtype=torch.float64, device=dev)
+        first = torch.zeros(1, dtype=torch.int32, device=dev)
+        a = VcParams(**{k: vp[k] for k, _ in VcParams._fields_})
+        self._check(_LIB.voldor_vc_scores(self._h, ctypes.byref(a), _ptr(idepth), _ptr(conf), n, _ptr(poses),
+                                          float(tau), _ptr(out), _ptr(first), _stream(stream)), "voldor_vc_scores")
+        return out, first

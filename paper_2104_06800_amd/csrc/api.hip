@@ -188,7 +188,19 @@ vd::Win make_win(const voldor_window* v, int it, int level, const voldor_buffers
     return w;
 }
 
-vd::LevelGeom make_geom(const voldor_window* v, const vd::Win& w, int level, int it) {
+// Effective launch knobs of a window: the context's entry for its (H, W, N, K, prior)
+// bucket, else the defaults (all zero).
+voldor_knobs knobs_for(voldor_ctx ctx, const voldor_window* v) {
+    voldor_knobs k;
+    std::memset(&k, 0, sizeof(k));
+    if (!ctx) return k;
+    for (const auto& e : ctx->knobs)
+        if (e.H == v->H && e.W == v->W && e.N == v->N && e.K == v->n_candidates && e.prior == (v->P > 0))
+            return e.k;
+    return k;
+}
+
+vd::LevelGeom make_geom(const voldor_window* v, const vd::Win& w, int level, int it, const voldor_knobs& kn) {
     vd::LevelGeom g;
     g.horizontal = ((it & 3) % 2 == 0);
     if (level == VOLDOR_LEVEL_COARSE) {
@@ -200,13 +212,16 @@ vd::LevelGeom make_geom(const voldor_window* v, const vd::Win& w, int level, int
     }
     // one lane per (chain, frame) in the forward-backward phase: C * N <= block size
     g.C = std::max(1, std::min(VD_BLOCK / g.seg, VD_BLOCK / v->N));
+    if (level == VOLDOR_LEVEL_LOCAL && kn.local_chains > 0) g.C = std::min(g.C, kn.local_chains);
     const int axis = g.horizontal ? g.w : g.h;
     const int lines = g.horizontal ? g.h : g.w;
     g.nseg = (axis + g.seg - 1) / g.seg;
     g.nblocks = g.nseg * ((lines + g.C - 1) / g.C);
     // speculation depth of the chain scan: the coarse level's long chains carry a value over
     // many nodes, so it speculates deeper (phase A2 cost grows with the depth, misses shrink)
-    g.spec = level == VOLDOR_LEVEL_COARSE ? VD_SPEC : 2;
+    g.spec = level == VOLDOR_LEVEL_COARSE ? (kn.coarse_spec > 0 ? kn.coarse_spec : VD_SPEC)
+                                          : (kn.local_spec > 0 ? kn.local_spec : 2);
+    g.pa_lanes = kn.coarse_lanes > 0 ? kn.coarse_lanes : VD_PA_LANES;
     // a fused local pass keeps its E-step frame costs when there are no priors and the
     // block still fits 5 per CU (32 KB of the 160 KB LDS)
     g.ncost = 0;
@@ -236,15 +251,17 @@ struct GemLaunch {
     int pose_blocks;
     int max_level_blocks;
     bool timers = true;   // bracket launches with the context's timers (when enabled)
+    voldor_knobs kn;      // launch knobs of the window (results do not depend on them)
     struct { size_t head, f2, hist, obs, ll, red, pa; } sz;
 };
 
 // Launch dimensions of one window and the byte size of its scratch.
 size_t gem_layout(const voldor_window* v, int n_cand, GemLaunch& L) {
+    L.kn = knobs_for(L.ctx, v);
     vd::Win w0 = make_win(v, 0, 1);
     int mx = 0;
     for (int lvl = 0; lvl < 2; ++lvl)
-        for (int d = 0; d < 2; ++d) mx = std::max(mx, make_geom(v, w0, lvl, d).nblocks);
+        for (int d = 0; d < 2; ++d) mx = std::max(mx, make_geom(v, w0, lvl, d, L.kn).nblocks);
     L.max_level_blocks = mx;
     const int64_t npix = (int64_t)v->H * v->W;
     // ~4 pixels per thread: enough blocks to fill the chip, few partial records
@@ -354,7 +371,7 @@ vd::FinalBufs final_bufs(const GemLaunch& L) {
 int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll) {
     voldor_ctx ctx = L.ctx;
     const vd::Win w = make_win(L.v, it, level, L.b);
-    const vd::LevelGeom g = make_geom(L.v, w, level, it);
+    const vd::LevelGeom g = make_geom(L.v, w, level, it, L.kn);
     const size_t lds = vd::level_lds_bytes(g);
     if (lds > kLevelLdsMax) return fail(ctx, VOLDOR_EINVAL, "chain segment too long for LDS (%zu bytes)", lds);
     const vd::LevelBufs B = level_bufs(L, level, want_ll);
@@ -409,7 +426,7 @@ int run_finalize(GemLaunch& L, int iter) {
     int rc;
     if ((rc = run_level(L, iter, VOLDOR_LEVEL_LOCAL, 1, 0, true))) return rc;
     const vd::Win w = make_win(L.v, iter, 1, L.b);
-    const vd::LevelGeom g = make_geom(L.v, w, 1, iter);
+    const vd::LevelGeom g = make_geom(L.v, w, 1, iter, L.kn);
     const vd::FinalBufs B = final_bufs(L);
     VD_CHECK(vd::launch_finalize(w, B, g.nblocks, L.st), "finalize launch");
     return VOLDOR_OK;
@@ -560,7 +577,8 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
             vd::LevelItem x;
             std::memset(&x, 0, sizeof(x));
             x.w = make_win(L.v, it, level, L.b);
-            x.g = make_geom(L.v, x.w, level, it);
+            x.g = make_geom(L.v, x.w, level, it, L.kn);
+            x.g.pa_lanes = VD_PA_LANES;             // the batched phase-A grid keeps 8 lanes
             x.b = level_bufs(L, level, want_ll);
             x.do_e = do_e;
             x.do_m = do_m;
@@ -614,7 +632,7 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
         vd::LevelItem x;
         std::memset(&x, 0, sizeof(x));
         x.w = make_win(L.v, last, VOLDOR_LEVEL_LOCAL, L.b);
-        x.g = make_geom(L.v, x.w, VOLDOR_LEVEL_LOCAL, last);
+        x.g = make_geom(L.v, x.w, VOLDOR_LEVEL_LOCAL, last, L.kn);
         x.b = level_bufs(L, VOLDOR_LEVEL_LOCAL, true);
         x.do_e = 1;
         x.do_m = 0;
@@ -627,7 +645,7 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
         std::memset(&x, 0, sizeof(x));
         x.w = make_win(L.v, last, VOLDOR_LEVEL_LOCAL, L.b);
         x.b = final_bufs(L);
-        x.n_ll = make_geom(L.v, x.w, VOLDOR_LEVEL_LOCAL, last).nblocks;
+        x.n_ll = make_geom(L.v, x.w, VOLDOR_LEVEL_LOCAL, last, L.kn).nblocks;
         x.nblocks = (int)(((int64_t)L.v->H * L.v->W + VD_BLOCK - 1) / VD_BLOCK);
         fin_all.push_back(x);
     }
@@ -928,29 +946,45 @@ int voldor_run_noalloc(voldor_ctx ctx, const voldor_window* v, const voldor_buff
     return run_window(L, first_iter, n_iters, flags);
 }
 
-int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, const voldor_buffers* bufs,
-                     int n_iters, int flags, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The batched run, optionally with every window started by the proposal network (net set):
+// windows the network can take (even H and W) get its start, with the random start where
+// its output is unusable (fallback_out[i] = 1); the others take the random start.
+int batch_run_impl(voldor_ctx ctx, const voldor_net* net, int n_windows, const voldor_window* wins,
+                   const voldor_buffers* bufs, int n_iters, int flags, int32_t* fallback_out, hipStream_t st) {
     if (!ctx) return VOLDOR_EINVAL;
     if (n_windows < 1 || n_windows > (int)kMaxBatch || !wins || !bufs)
         return fail(ctx, VOLDOR_EINVAL, "bad window batch");
     if (n_iters < 1 || n_iters > 0xffffff) return fail(ctx, VOLDOR_EINVAL, "n_iters must be >= 1");
     if (flags & ~(VOLDOR_RUN_INIT | VOLDOR_RUN_NO_GRAPH)) return fail(ctx, VOLDOR_EINVAL, "unknown flags 0x%x", flags);
+    if (net && (!net->params || !net->wbf16)) return fail(ctx, VOLDOR_EINVAL, "null network pointer");
+    if (net) flags &= ~VOLDOR_RUN_INIT;        // the starts come from the network (or its fallback)
     int rc;
     for (int i = 0; i < n_windows; ++i) {
         if ((rc = check_window(ctx, &wins[i], &bufs[i]))) return rc;
         if (!bufs[i].conf || !bufs[i].stats) return fail(ctx, VOLDOR_EINVAL, "null conf/stats pointer (window %d)", i);
     }
-    hipStream_t st = (hipStream_t)stream;
     VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
     const bool use_graph = !(flags & VOLDOR_RUN_NO_GRAPH);
     // the same windows, buffers and settings as the captured graph: replay it
-    std::vector<char> key(sizeof(int) * 2 + n_windows * (sizeof(voldor_window) + sizeof(voldor_buffers)));
+    const voldor_net no_net = {};
+    const voldor_net& nk = net ? *net : no_net;
+    std::vector<char> key(sizeof(int) * 2 + sizeof(voldor_net) + sizeof(void*) +
+                          n_windows * (sizeof(voldor_window) + sizeof(voldor_buffers)));
     {
         char* k = key.data();
         const int hdr[2] = {n_iters, flags & VOLDOR_RUN_INIT};
         std::memcpy(k, hdr, sizeof(hdr));
-        std::memcpy(k + sizeof(hdr), wins, n_windows * sizeof(voldor_window));
-        std::memcpy(k + sizeof(hdr) + n_windows * sizeof(voldor_window), bufs, n_windows * sizeof(voldor_buffers));
+        k += sizeof(hdr);
+        std::memcpy(k, &nk, sizeof(voldor_net));
+        k += sizeof(voldor_net);
+        std::memcpy(k, &fallback_out, sizeof(void*));
+        k += sizeof(void*);
+        std::memcpy(k, wins, n_windows * sizeof(voldor_window));
+        std::memcpy(k + n_windows * sizeof(voldor_window), bufs, n_windows * sizeof(voldor_buffers));
     }
     if (use_graph && ctx->graph_exec && key == ctx->batch_key) {
         VD_CHECK(hipGraphLaunch(ctx->graph_exec, st), "hipGraphLaunch");
@@ -972,6 +1006,15 @@ int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, c
     drop_graph(ctx);
     if ((rc = vdc::ensure_buffer(ctx, &ctx->batch_ws, &ctx->batch_ws_bytes, total, st))) return rc;
     for (int i = 0; i < n_windows; ++i) gem_carve((char*)ctx->batch_ws + offs[i], W[i].L);
+    auto net_ok = [&](const voldor_window& v) { return !(v.H & 1) && !(v.W & 1) && (int64_t)v.H * v.W <= (1 << 26); };
+    if (net) {
+        // the network's workspace for the largest window, allocated before any capture
+        int64_t best = 0;
+        int bi = -1;
+        for (int i = 0; i < n_windows; ++i)
+            if (net_ok(wins[i]) && (int64_t)wins[i].H * wins[i].W > best) { best = (int64_t)wins[i].H * wins[i].W; bi = i; }
+        if (bi >= 0 && (rc = vdc::net_workspace(ctx, wins[bi].H, wins[bi].W, st))) return rc;
+    }
     BPlan plan;
     if ((rc = build_plan(ctx, W, n_iters, flags, plan))) return rc;
     if ((rc = vdc::ensure_buffer(ctx, &ctx->batch_tab, &ctx->batch_tab_bytes, plan.host.size(), st))) return rc;
@@ -980,10 +1023,27 @@ int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, c
     VD_CHECK(hipMemcpyAsync(tables, ctx->batch_host.data(), ctx->batch_host.size(), hipMemcpyHostToDevice, st),
              "table upload");
     VD_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
-    if (!use_graph) return enqueue_plan(ctx, plan, tables, st);
+    auto enqueue = [&](hipStream_t s) -> int {
+        if (net) {
+            for (int i = 0; i < n_windows; ++i) {
+                const voldor_window& v = wins[i];
+                const voldor_buffers& b = bufs[i];
+                int32_t* fo = fallback_out ? fallback_out + i : nullptr;
+                int* flag = nullptr;
+                if (net_ok(v)) {
+                    int r = vdc::proposal_start(ctx, net, v.H, v.W, v.N, b.flow, b.pose, v.idepth_min, v.idepth_max,
+                                                b.idepth, b.rigid, &flag, s);
+                    if (r) return r;
+                }
+                VD_CHECK(vd::launch_init_if(make_win(&v, 0, 1), b.idepth, flag, fo, s), "start launch");
+            }
+        }
+        return enqueue_plan(ctx, plan, tables, s);
+    };
+    if (!use_graph) return enqueue(st);
     if (!ctx->cap_stream) VD_CHECK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "stream create");
     VD_CHECK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed), "begin capture");
-    rc = enqueue_plan(ctx, plan, tables, ctx->cap_stream);
+    rc = enqueue(ctx->cap_stream);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
     if (rc) {
@@ -995,6 +1055,69 @@ int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, c
     VD_CHECK(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0), "graph instantiate");
     ctx->batch_key = key;
     VD_CHECK(hipGraphLaunch(ctx->graph_exec, st), "hipGraphLaunch");
+    return VOLDOR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, const voldor_buffers* bufs,
+                     int n_iters, int flags, void* stream) {
+    return batch_run_impl(ctx, nullptr, n_windows, wins, bufs, n_iters, flags, nullptr, (hipStream_t)stream);
+}
+
+int voldor_batch_run_learned(voldor_ctx ctx, const voldor_net* net, int n_windows, const voldor_window* wins,
+                             const voldor_buffers* bufs, int n_iters, int flags, int32_t* fallback_out, void* stream) {
+    if (ctx && !net) return fail(ctx, VOLDOR_EINVAL, "null network");
+    return batch_run_impl(ctx, net, n_windows, wins, bufs, n_iters, flags, fallback_out, (hipStream_t)stream);
+}
+
+int voldor_proposal_start(voldor_ctx ctx, const voldor_net* net, const voldor_window* v, const voldor_buffers* b,
+                          int32_t* fallback_out, void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    int* flag = nullptr;
+    if ((rc = vdc::proposal_start(ctx, net, v->H, v->W, v->N, b->flow, b->pose, v->idepth_min, v->idepth_max,
+                                  b->idepth, b->rigid, &flag, st)))
+        return rc;
+    VD_CHECK(vd::launch_init_if(make_win(v, 0, 1), b->idepth, flag, fallback_out, st), "fallback launch");
+    return VOLDOR_OK;
+}
+
+int voldor_set_knobs(voldor_ctx ctx, const voldor_window* bucket, const voldor_knobs* knobs) {
+    if (!ctx) return VOLDOR_EINVAL;
+    if (!bucket) return fail(ctx, VOLDOR_EINVAL, "null bucket window");
+    auto same = [&](const voldor_ctx_s::KnobEntry& e) {
+        return e.H == bucket->H && e.W == bucket->W && e.N == bucket->N && e.K == bucket->n_candidates &&
+               e.prior == (bucket->P > 0);
+    };
+    if (knobs) {
+        const voldor_knobs& k = *knobs;
+        if (k.local_chains < 0 || k.local_chains > VD_BLOCK) return fail(ctx, VOLDOR_EINVAL, "local_chains outside 0..%d", VD_BLOCK);
+        if (k.local_spec < 0 || k.local_spec > VD_SPEC || k.coarse_spec < 0 || k.coarse_spec > VD_SPEC)
+            return fail(ctx, VOLDOR_EINVAL, "speculation depths outside 0..%d", VD_SPEC);
+        if (k.coarse_lanes != 0 && k.coarse_lanes != 4 && k.coarse_lanes != 8 && k.coarse_lanes != 16)
+            return fail(ctx, VOLDOR_EINVAL, "coarse_lanes must be 0, 4, 8 or 16");
+    }
+    // a batch graph captured with the old knobs would no longer match the table
+    drop_graph(ctx);
+    for (auto& e : ctx->knobs)
+        if (same(e)) {
+            if (knobs) e.k = *knobs;
+            else { e = ctx->knobs.back(); ctx->knobs.pop_back(); }
+            return VOLDOR_OK;
+        }
+    if (knobs) ctx->knobs.push_back({bucket->H, bucket->W, bucket->N, bucket->n_candidates, bucket->P > 0, *knobs});
+    return VOLDOR_OK;
+}
+
+int voldor_get_knobs(voldor_ctx ctx, const voldor_window* win, voldor_knobs* out) {
+    if (!ctx) return VOLDOR_EINVAL;
+    if (!win || !out) return fail(ctx, VOLDOR_EINVAL, "null pointer");
+    *out = knobs_for(ctx, win);
     return VOLDOR_OK;
 }
 
@@ -1025,6 +1148,81 @@ int voldor_timing_read(voldor_ctx ctx, int timer, double* total_ms, int64_t* lau
         ctx->ev_pool.push_back(p.second);
     }
     rec.clear();
+    return VOLDOR_OK;
+}
+
+int voldor_pose_sample(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, int iter,
+                       const voldor_sample_params* sp, double* cov_out, double* info_out, void* stream) {
+    int rc = check_window(ctx, v, b);
+    if (rc) return rc;
+    if (!sp) return fail(ctx, VOLDOR_EINVAL, "null sampling parameters");
+    if (iter < 0 || iter > 0xffffff) return fail(ctx, VOLDOR_EINVAL, "bad iter");
+    if (sp->samples < 1 || sp->samples > VOLDOR_POSE_MAX_SAMPLES)
+        return fail(ctx, VOLDOR_EINVAL, "samples outside 1..%d", VOLDOR_POSE_MAX_SAMPLES);
+    if (sp->tries < 1 || sp->tries > 64) return fail(ctx, VOLDOR_EINVAL, "tries outside 1..64");
+    if (!(sp->sigma_w > 0) || !(sp->sigma_t_rel > 0) || !(sp->eps > 0) || !std::isfinite(sp->sigma_w) ||
+        !std::isfinite(sp->sigma_t_rel))
+        return fail(ctx, VOLDOR_EINVAL, "kernel widths and eps must be > 0");
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    rc = vdc::ensure_buffer(ctx, &ctx->scratch, &ctx->scratch_bytes, sizeof(double) * 12 * (size_t)sp->samples, st);
+    if (rc) return rc;
+    vd::PoseSampleArgs a;
+    a.H = v->H; a.W = v->W; a.N = v->N;
+    a.fx = v->fx; a.fy = v->fy; a.cx = v->cx; a.cy = v->cy;
+    a.S = sp->samples; a.tries = sp->tries; a.it = iter;
+    a.sigma_w = sp->sigma_w; a.sigma_t_rel = sp->sigma_t_rel; a.eps = sp->eps;
+    a.key0 = (uint32_t)(v->seed & 0xffffffffu);
+    a.key1 = (uint32_t)(v->seed >> 32);
+    a.window_id = v->window_id;
+    vd::PoseSampleBufs B;
+    B.flow = (const float2*)b->flow;
+    B.idepth = b->idepth;
+    B.rigid = b->rigid;
+    B.pose = b->pose;
+    B.samples = (double*)ctx->scratch;
+    B.cov = cov_out;
+    B.info = info_out;
+    VD_CHECK(vd::launch_pose_sample(a, B, st), "pose sampling launch");
+    return VOLDOR_OK;
+}
+
+int voldor_vc_scores(voldor_ctx ctx, const voldor_vc_params* vp, const float* idepth, const float* conf,
+                     int n_poses, const double* poses, double tau, double* out, int32_t* first_below,
+                     void* stream) {
+    if (!ctx) return VOLDOR_EINVAL;
+    if (!vp) return fail(ctx, VOLDOR_EINVAL, "null params");
+    if (vp->H < 1 || vp->W < 1 || (int64_t)vp->H * vp->W > (1 << 28)) return fail(ctx, VOLDOR_EINVAL, "bad image size");
+    if (!(vp->fx > 0) || !(vp->fy > 0) || !std::isfinite(vp->cx) || !std::isfinite(vp->cy))
+        return fail(ctx, VOLDOR_EINVAL, "bad intrinsics");
+    if (vp->cell < 1 || vp->cell > 1024) return fail(ctx, VOLDOR_EINVAL, "cell outside 1..1024");
+    if (n_poses < 1 || n_poses > VOLDOR_VC_MAX_POSES)
+        return fail(ctx, VOLDOR_EINVAL, "n_poses outside 1..%d", VOLDOR_VC_MAX_POSES);
+    if (!idepth || !poses || !out) return fail(ctx, VOLDOR_EINVAL, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    vd::VcArgs a;
+    a.H = vp->H; a.W = vp->W; a.cell = vp->cell;
+    a.hc = (vp->H + vp->cell - 1) / vp->cell;
+    a.wc = (vp->W + vp->cell - 1) / vp->cell;
+    a.words = (int)(((int64_t)a.hc * a.wc + 31) / 32);
+    a.n = n_poses;
+    a.fx = vp->fx; a.fy = vp->fy; a.cx = vp->cx; a.cy = vp->cy;
+    a.conf_min = vp->conf_min;
+    a.tau = tau;
+    const size_t rt_bytes = align_up(sizeof(double) * 12 * (size_t)n_poses);
+    const size_t cnt_bytes = align_up(sizeof(uint32_t) * (size_t)(n_poses + 1));
+    const size_t bit_bytes = align_up(sizeof(uint32_t) * (size_t)a.words * n_poses);
+    int rc = vdc::ensure_buffer(ctx, &ctx->scratch, &ctx->scratch_bytes, rt_bytes + cnt_bytes + bit_bytes, st);
+    if (rc) return rc;
+    char* base = (char*)ctx->scratch;
+    vd::VcBufs B;
+    B.idepth = idepth; B.conf = conf; B.pose = poses;
+    B.RT = (double*)base;
+    B.count = (uint32_t*)(base + rt_bytes);
+    B.bits = (uint32_t*)(base + rt_bytes + cnt_bytes);
+    B.out = out; B.first_below = first_below;
+    VD_CHECK(vd::launch_vc(a, B, st), "visibility-coverage launch");
     return VOLDOR_OK;
 }
 

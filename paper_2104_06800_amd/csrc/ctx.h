@@ -27,6 +27,12 @@ struct voldor_ctx_s {
     hipStream_t cap_stream = nullptr; // capture stream (default priority, non-blocking)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    struct KnobEntry {                // launch knobs per (H, W, N, K, prior) bucket
+        int32_t H, W, N, K;
+        bool prior;
+        voldor_knobs k;
+    };
+    std::vector<KnobEntry> knobs;
     int n_cu = 256;
     unsigned timing = 0;              // enabled timer classes, bit (1 << timer)
     std::vector<hipEvent_t> ev_pool;                                   // idle events
@@ -43,6 +49,12 @@ const char* create_error();
 // Grows *buf (device memory on ctx's device) to at least need bytes; the old contents are
 // not kept.  Waits for st before freeing a smaller buffer.
 int ensure_buffer(voldor_ctx ctx, void** buf, size_t* cap, size_t need, hipStream_t st);
+// Proposal network (proposal_api.hip): sizes the context's network workspace for an H x W
+// input; runs the network on a window's flows and writes its start (inverse depth, rigidness)
+// with *flag (device) set where the output is unusable.
+int net_workspace(voldor_ctx ctx, int H, int W, hipStream_t st);
+int proposal_start(voldor_ctx ctx, const voldor_net* net, int H, int W, int N, const float* flow, const double* pose,
+                   float rmin, float rmax, float* idepth, float* rigid, int** flag, hipStream_t st);
 
 }  // namespace vdc
 

@@ -39,6 +39,15 @@ __global__ void __launch_bounds__(VD_BLOCK) k_init_idepth(Win w, float* __restri
     init_body(w, idepth, blockIdx.x);
 }
 
+// the random start where a learned start raised its fallback flag (always without a flag);
+// the flag is copied out
+__global__ void __launch_bounds__(VD_BLOCK)
+k_init_idepth_if(Win w, float* __restrict__ idepth, const int* __restrict__ flag, int32_t* __restrict__ out) {
+    const int f = flag ? *flag : 1;
+    if (out && blockIdx.x == 0 && threadIdx.x == 0) *out = f;
+    if (f) init_body(w, idepth, blockIdx.x);
+}
+
 // ----------------------------------------------------------------------------------
 // row-pair flow layout for the bilinear samples of frames t >= 2:
 // F2[t][y][x] = (X_t(x, y), X_t(x, y + 1)), y <= H - 2
@@ -722,16 +731,22 @@ k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
 }
 
 // ----------------------------------------------------------------------------------
-// phase A as a separate grid: VD_PA_LANES lanes per level pixel.  Lane 0 takes slot 0,
-// lane l takes the Philox groups g = l, l + VD_PA_LANES, ... (slots 3 + 4g .. 6 + 4g) and,
-// on the local level, lane 1 takes slot 2 first.  Each lane scans its slots in increasing
-// order with strict improvement and pruning at its own best, then the lanes merge by
-// (energy, slot): the result equals the argmin over all slots with ties to the lowest slot.
+// phase A as a separate grid: LANES lanes per level pixel (4, 8 or 16).  Lane 0 takes slot
+// 0; with up to 8 lanes, lane l takes the Philox groups g = l, l + LANES, ... (slots
+// 3 + 4g .. 6 + 4g); with 16, lanes 2h and 2h + 1 share the groups of h, each taking two of
+// a group's four slots.  On the local level lane 1 takes slot 2 first.  Each lane scans its
+// slots in increasing order with strict improvement and pruning at its own best, then the
+// lanes merge by (energy, slot): the result equals the argmin over all slots with ties to
+// the lowest slot, whatever LANES is.
 // ----------------------------------------------------------------------------------
-template <bool B2, bool PR>
+template <bool B2, bool PR, int LANES = VD_PA_LANES>
 __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, const LevelBufs& B, int blk) {
+    constexpr int SUB = LANES > 8 ? LANES / 8 : 1;        // lanes per Philox group
+    constexpr int GSTRIDE = LANES / SUB;                  // groups advance by this much
+    constexpr int MPER = 4 / SUB;                         // slots of a group per lane
     const int gid = blk * VD_BLOCK + threadIdx.x;
-    const int li = gid / VD_PA_LANES, lane = gid % VD_PA_LANES;
+    const int li = gid / LANES, lane = gid % LANES;
+    const int gl = lane / SUB, part = lane - gl * SUB;
     const size_t lplane = (size_t)g.h * g.w;
     const bool valid = li < (int)lplane;
     float bE = __builtin_huge_valf(), bV = 0.f, r0 = 0.f;
@@ -757,11 +772,11 @@ __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, c
         }
         const int G = (w.K - 3 + 3) / 4;
         const uint32_t word2 = philox_word2(w.it, w.level, PURPOSE_CAND);
-        for (int gi = lane; gi < G; gi += VD_PA_LANES) {
+        for (int gi = gl; gi < G; gi += GSTRIDE) {
             const uint4 r = philox10(make_uint4((uint32_t)li, (uint32_t)gi, word2, w.window_id), w.key0, w.key1);
             const uint32_t words[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
+            for (int m = part * MPER; m < (part + 1) * MPER; ++m) {
                 const int slot = 3 + 4 * gi + m;
                 if (slot < w.K) {
                     const float uu = unit24(words[m]);
@@ -775,7 +790,7 @@ __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, c
         }
     }
 #pragma unroll
-    for (int off = 1; off < VD_PA_LANES; off <<= 1) {
+    for (int off = 1; off < LANES; off <<= 1) {
         const float oE = __shfl_xor(bE, off), oV = __shfl_xor(bV, off);
         const int oS = __shfl_xor(bS, off);
         if (oE < bE || (oE == bE && oS < bS)) { bE = oE; bV = oV; bS = oS; }
@@ -787,9 +802,9 @@ __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, c
     }
 }
 
-template <bool B2, bool PR>
+template <bool B2, bool PR, int LANES>
 __global__ void __launch_bounds__(VD_BLOCK) k_phase_a(Win w, LevelGeom g, LevelBufs B) {
-    phase_a_body<B2, PR>(w, g, B, xcd_block(blockIdx.x, gridDim.x));
+    phase_a_body<B2, PR, LANES>(w, g, B, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ----------------------------------------------------------------------------------
@@ -1343,6 +1358,13 @@ hipError_t launch_init(const Win& w, float* idepth, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_init_if(const Win& w, float* idepth, const int* flag, int32_t* out, hipStream_t st) {
+    const int n = w.H * w.W;
+    hipLaunchKernelGGL(k_init_idepth_if, dim3((n + VD_BLOCK - 1) / VD_BLOCK), dim3(VD_BLOCK), 0, st, w, idepth, flag,
+                       out);
+    return hipGetLastError();
+}
+
 hipError_t launch_level(const Win& w, const LevelGeom& g, const LevelBufs& b, int do_e, int do_m, hipStream_t st) {
     const size_t lds = level_lds_bytes(g);
     const bool lc = do_m == 2 || (w.level == 0 && do_m == 0);
@@ -1362,16 +1384,23 @@ hipError_t launch_level(const Win& w, const LevelGeom& g, const LevelBufs& b, in
     return hipGetLastError();
 }
 
-hipError_t launch_phase_a(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st) {
-    const dim3 grid((unsigned)(((size_t)g.h * g.w * VD_PA_LANES + VD_BLOCK - 1) / VD_BLOCK));
+template <int LANES>
+hipError_t launch_phase_a_lanes(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st) {
+    const dim3 grid((unsigned)(((size_t)g.h * g.w * LANES + VD_BLOCK - 1) / VD_BLOCK));
     if (w.beta2) {
-        if (w.P > 0) hipLaunchKernelGGL((k_phase_a<true, true>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
-        else hipLaunchKernelGGL((k_phase_a<true, false>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+        if (w.P > 0) hipLaunchKernelGGL((k_phase_a<true, true, LANES>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+        else hipLaunchKernelGGL((k_phase_a<true, false, LANES>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
     } else {
-        if (w.P > 0) hipLaunchKernelGGL((k_phase_a<false, true>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
-        else hipLaunchKernelGGL((k_phase_a<false, false>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+        if (w.P > 0) hipLaunchKernelGGL((k_phase_a<false, true, LANES>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
+        else hipLaunchKernelGGL((k_phase_a<false, false, LANES>), grid, dim3(VD_BLOCK), 0, st, w, g, b);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_phase_a(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st) {
+    if (g.pa_lanes == 4) return launch_phase_a_lanes<4>(w, g, b, st);
+    if (g.pa_lanes == 16) return launch_phase_a_lanes<16>(w, g, b, st);
+    return launch_phase_a_lanes<8>(w, g, b, st);
 }
 
 hipError_t launch_phase_a2(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st) {

@@ -20,6 +20,7 @@ struct LevelGeom {
     int nblocks;
     int spec;          // speculation depth of the chain scan
     int ncost;         // frames of E-step costs kept for a fused pass's M-step (0: none)
+    int pa_lanes;      // lanes per lattice node of the separate phase-A grid (4, 8 or 16)
 };
 
 struct LevelBufs {
@@ -90,6 +91,47 @@ struct AlignBufs {
     double* partials;
 };
 
+// Visibility-coverage scores: frame 1's inverse depth against n poses of frame 2.
+struct VcArgs {
+    int H, W;
+    int cell, hc, wc;          // coverage cell size and the cell grid of frame 2
+    int words;                 // 32-bit words of one pose's coverage bitmap
+    int n;                     // poses
+    double fx, fy, cx, cy;
+    float conf_min;
+    double tau;
+};
+
+struct VcBufs {
+    const float* idepth;       // [H][W]
+    const float* conf;         // [H][W] or null
+    const double* pose;        // [n][6]
+    double* RT;                // [n][12] scratch: R row-major, t
+    uint32_t* count;           // [1 + n] scratch: depth pixels, visible per pose
+    uint32_t* bits;            // [n][words] scratch: coverage bitmaps
+    double* out;               // [n][5]
+    int32_t* first_below;      // [1] or null
+};
+
+// Sampled pose M-step (Monte-Carlo P3P, meanshift, covariance fit) of frames 1..N.
+struct PoseSampleArgs {
+    int H, W, N;
+    double fx, fy, cx, cy;
+    int S, tries, it;
+    double sigma_w, sigma_t_rel, eps;
+    uint32_t key0, key1, window_id;
+};
+
+struct PoseSampleBufs {
+    const float2* flow;        // [N][H][W]
+    const float* idepth;       // [H][W]
+    const float* rigid;        // [N][H][W]
+    double* pose;              // [N][6] in/out
+    double* samples;           // [S][12] scratch: R (9), t (3), NaN when void
+    double* cov;               // [N][36] or null
+    double* info;              // [N][4] or null
+};
+
 // ---- batched launches over many windows: one item per window and launch; a block finds
 // its item through blk2item[global block] and its block index within the window as
 // (global block - begin).  Global blocks are XCD-remapped first.
@@ -134,6 +176,7 @@ size_t level_lds_bytes(const LevelGeom& g);
 hipError_t launch_pose_prep(const double* pose, int N, const double* prior_pose, int P, PoseF* out, PoseD* outd,
                             hipStream_t st);
 hipError_t launch_init(const Win& w, float* idepth, hipStream_t st);
+hipError_t launch_init_if(const Win& w, float* idepth, const int* flag, int32_t* out, hipStream_t st);
 hipError_t launch_flow_pairs(const float2* flow, float4* f2, int N, int H, int W, hipStream_t st);
 hipError_t launch_level(const Win& w, const LevelGeom& g, const LevelBufs& b, int do_e, int do_m, hipStream_t st);
 hipError_t launch_phase_a(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st);
@@ -158,6 +201,8 @@ hipError_t launch_finalize_batch(const FinalItem* items, const int* blk2item, in
                                  hipStream_t st);
 hipError_t launch_finalize_finish_batch(const FinalItem* items, int n_items, hipStream_t st);
 
+hipError_t launch_vc(const VcArgs& a, const VcBufs& b, hipStream_t st);
+hipError_t launch_pose_sample(const PoseSampleArgs& a, const PoseSampleBufs& b, hipStream_t st);
 hipError_t launch_align_prepare(const AlignArgs& a, const AlignBufs& b, hipStream_t st);
 hipError_t launch_align_step(const AlignArgs& a, const AlignBufs& b, int final_pass, int nblocks, hipStream_t st);
 

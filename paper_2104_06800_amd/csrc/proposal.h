@@ -74,6 +74,8 @@ hipError_t launch_bgrad(const uint16_t* dy, int Mpix, int C, int nchunks, float*
 hipError_t launch_sum_chunks(const float* part, int n, int nchunks, float* out, hipStream_t st);
 hipError_t launch_heads(const float* o, int HW, int N, float tnorm, float rmin, float rmax, float* rho, float* q,
                         hipStream_t st);
+hipError_t launch_start_heads(const float* o, int HW, int N, const double* pose, float rmin, float rmax, float* rho,
+                              float* q, int* flag, hipStream_t st);
 hipError_t launch_loss(const float* o, int HW, int N, float tnorm, const float* rho_t, const float* q_t,
                        const uint8_t* mask, float lam, float* inv_cnt, uint16_t* dout, double* part, double* loss,
                        hipStream_t st);

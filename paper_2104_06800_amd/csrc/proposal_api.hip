@@ -29,6 +29,7 @@ int wgrad_chunks(int Cout, int Cin, int Mpix) {
 struct Acts {
     uint16_t *x, *a1, *a2, *a3, *a4, *a5;
     float* o;
+    int* flag;          // learned start: fallback flag
     // training
     uint16_t *go, *g5, *g4, *g3, *g2, *g1;
     float* dup;
@@ -48,7 +49,7 @@ int check_net_shape(voldor_ctx ctx, int H, int W, int N) {
 int layout(voldor_ctx ctx, int H, int W, bool train, hipStream_t st, Acts& A) {
     const size_t HW = (size_t)H * W, HW2 = (size_t)(H / 2) * (W / 2);
     const size_t b16 = sizeof(uint16_t);
-    size_t sz[20];
+    size_t sz[24];
     int k = 0;
     sz[k++] = al(HW * 16 * b16);     // x
     sz[k++] = al(HW * 64 * b16);     // a1
@@ -57,6 +58,7 @@ int layout(voldor_ctx ctx, int H, int W, bool train, hipStream_t st, Acts& A) {
     sz[k++] = al(HW2 * 128 * b16);   // a4
     sz[k++] = al(HW * 64 * b16);     // a5
     sz[k++] = al(HW * 32 * sizeof(float));   // o
+    sz[k++] = al(sizeof(int));                // flag
     const int nfwd = k;
     sz[k++] = al(HW * 32 * b16);     // go
     sz[k++] = al(HW * 64 * b16);     // g5
@@ -75,8 +77,8 @@ int layout(voldor_ctx ctx, int H, int W, bool train, hipStream_t st, Acts& A) {
     int rc = vdc::ensure_buffer(ctx, &ctx->net_ws, &ctx->net_ws_bytes, total, st);
     if (rc) return rc;
     char* p = (char*)ctx->net_ws;
-    void** slots[18] = {(void**)&A.x, (void**)&A.a1, (void**)&A.a2, (void**)&A.a3, (void**)&A.a4, (void**)&A.a5,
-                        (void**)&A.o, (void**)&A.go, (void**)&A.g5, (void**)&A.g4, (void**)&A.g3, (void**)&A.g2,
+    void** slots[19] = {(void**)&A.x, (void**)&A.a1, (void**)&A.a2, (void**)&A.a3, (void**)&A.a4, (void**)&A.a5,
+                        (void**)&A.o, (void**)&A.flag, (void**)&A.go, (void**)&A.g5, (void**)&A.g4, (void**)&A.g3, (void**)&A.g2,
                         (void**)&A.g1, (void**)&A.dup, (void**)&A.wpart, (void**)&A.bpart, (void**)&A.lpart,
                         (void**)&A.inv_cnt};
     std::memset(&A, 0, sizeof(A));
@@ -168,6 +170,28 @@ int check_conv(voldor_ctx ctx, int H, int W, int Cin, int Cout, int stride, int 
 }
 
 }  // namespace
+
+namespace vdc {
+
+int net_workspace(voldor_ctx ctx, int H, int W, hipStream_t st) {
+    Acts A;
+    return layout(ctx, H, W, false, st, A);
+}
+
+int proposal_start(voldor_ctx ctx, const voldor_net* net, int H, int W, int N, const float* flow, const double* pose,
+                   float rmin, float rmax, float* idepth, float* rigid, int** flag, hipStream_t st) {
+    int rc;
+    if ((rc = check_net_shape(ctx, H, W, N))) return rc;
+    if (!net || !net->params || !net->wbf16) return fail(ctx, VOLDOR_EINVAL, "null network pointer");
+    Acts A;
+    if ((rc = layout(ctx, H, W, false, st, A))) return rc;
+    if ((rc = run_forward(ctx, net, H, W, N, flow, A, st))) return rc;
+    VD_CHECK(vp::launch_start_heads(A.o, H * W, N, pose, rmin, rmax, idepth, rigid, A.flag, st), "start heads launch");
+    *flag = A.flag;
+    return VOLDOR_OK;
+}
+
+}  // namespace vdc
 
 extern "C" {
 

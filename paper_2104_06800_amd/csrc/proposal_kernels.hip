@@ -315,6 +315,36 @@ __global__ void k_heads(const float* __restrict__ o, int HW, int N, float tnorm,
 }
 
 // ---------------------------------------------------------------------------------------
+// learned start of a GEM window: tnorm = |t| of frame 1's pose (FP64, on the device); a
+// non-finite depth logit or an unusable tnorm raises the window's fallback flag (cleared by
+// k_flag_clear beforehand), in which case the caller's random start replaces every pixel
+// ---------------------------------------------------------------------------------------
+__global__ void k_flag_clear(int* __restrict__ flag) { *flag = 0; }
+
+__global__ void k_start_heads(const float* __restrict__ o, int HW, int N, const double* __restrict__ pose,
+                              float rmin, float rmax, float* __restrict__ rho, float* __restrict__ q,
+                              int* __restrict__ flag) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const double t0 = pose[3], t1 = pose[4], t2 = pose[5];
+    const float tnorm = (float)sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+    const bool tn_ok = isfinite(tnorm) && tnorm > 0.f;
+    if (j >= HW) return;
+    const float* oj = o + (size_t)j * VP_C_HEAD;
+    const bool ok = tn_ok && isfinite(oj[0]);
+    if (!ok) atomicOr(flag, 1);
+    rho[j] = ok ? fminf(fmaxf(softplusf(oj[0]) / tnorm, rmin), rmax) : rmin;
+    for (int t = 0; t < N; ++t) q[(size_t)t * HW + j] = sigmoidf(oj[1 + t]);
+}
+
+hipError_t launch_start_heads(const float* o, int HW, int N, const double* pose, float rmin, float rmax, float* rho,
+                              float* q, int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, st, flag);
+    hipLaunchKernelGGL(k_start_heads, dim3((HW + 255) / 256), dim3(256), 0, st, o, HW, N, pose, rmin, rmax, rho, q,
+                       flag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
 // loss: L = mean_mask |softplus(o_0) - rho_t tnorm| + lam mean BCE(sigmoid(o_t), q_t); its
 // gradient w.r.t. o (BF16, zero on unused channels) and per-block FP64 partial sums
 // [L1 sum, mask count, BCE sum]

@@ -125,6 +125,39 @@ def load(path):
     return params, meta
 
 
+def learned_run(lib, net, p, b, iters, full_iters=None, fallback=None):
+    """GEM from the proposal's start: the network's start of the window (library kernels,
+    with the random start where its output is unusable), then iterations 0 .. iters-1 and the
+    final E-step.  After a fallback the run continues to plain GEM's full schedule
+    (full_iters, default the window's iteration count), which equals plain GEM's run bit for
+    bit.  Returns True when the start fell back.  One device-to-host read (the flag)."""
+    full = p["iters"] if full_iters is None else full_iters
+    fb = torch.zeros(1, dtype=torch.int32, device=b["idepth"].device) if fallback is None else fallback
+    lib.proposal_start(net, p, b, fb)
+    lib.run(p, b, iters=iters, init=False)
+    fell_back = bool(int(fb.cpu()[0]))
+    if fell_back and iters < full:
+        lib.run(p, b, iters=full - iters, init=False, first_iter=iters)
+    return fell_back
+
+
+def judged_run(lib, net, p, b, iters):
+    """Plain GEM as the judge of the learned start: the learned start's run (learned_run with
+    iters iterations) and plain GEM's full run on a copy of the window's buffers; the window
+    keeps the one with the lower final MIE energy (a non-finite energy always loses).
+    Returns "learned" or "plain"."""
+    plain = {k: (v.clone() if torch.is_tensor(v) else v) for k, v in b.items()}
+    learned_run(lib, net, p, b, iters)
+    lib.run(p, plain, iters=p["iters"])
+    e_l, e_p = (float(x["stats"][1].cpu()) for x in (b, plain))
+    if np.isfinite(e_l) and (not np.isfinite(e_p) or e_l <= e_p):
+        return "learned"
+    for k, v in plain.items():
+        if torch.is_tensor(v):
+            b[k].copy_(v)
+    return "plain"
+
+
 def _timed(fn, reps=3):
     """Median wall time (ms) of fn() on the current stream, synchronised."""
     ts = []
@@ -160,13 +193,13 @@ def compare(lib, net, windows, max_iters=None, reps=3, warm=True):
         tn = tnorm_of(w["pose_init"])
 
         def learned(k):
-            # warm start: the last k iterations of the schedule (narrow perturbations)
+            # the network's start (written into the window's buffers by the library), then k
+            # iterations; warm: the last k of the schedule (narrow perturbations)
             b["pose"].copy_(pose0)
-            rho, _, _ = lib.proposal_forward(net, b["flow"], tn, p["idepth_min"], p["idepth_max"])
-            b["idepth"].copy_(rho)
+            lib.proposal_start(net, p, b)
             lib.run(p, b, iters=k, init=False, first_iter=p["iters"] - k if warm else 0)
 
-        t_net = _timed(lambda: lib.proposal_forward(net, b["flow"], tn, p["idepth_min"], p["idepth_max"]), reps)
+        t_net = _timed(lambda: lib.proposal_start(net, p, b), reps)
         errs, times = [], []
         for k in range(1, I + 1):
             times.append(_timed(lambda: learned(k), reps))

@@ -37,7 +37,7 @@ def frac_close_rel(a, b, rel=1e-3):
     return float(np.mean(np.abs(a - b) <= rel * np.abs(b)))
 
 
-def check_mstep(p, ob, rho_before, gpu_rho, level, it, groups=None, frac_bar=None):
+def check_mstep(p, ob, rho_before, gpu_rho, level, it, groups=None, frac_bar=None, report=None):
     """M-step check on the pixels of `groups` (default: every chain of the level).
 
     ob          oracle buffers holding the state the M-step used (q, poses, priors, coarse
@@ -55,7 +55,15 @@ def check_mstep(p, ob, rho_before, gpu_rho, level, it, groups=None, frac_bar=Non
     flow term's validity decision on the edge of the sampling grid (within EDGE_EPS; FP32 and
     FP64 may decide it differently); at most max(2, 0.1%) of the pixels may be such cases.
     Exact agreement with the oracle's own sweep is returned (and asserted when frac_bar is
-    given).
+    given).  With a dict as `report`, it also receives measured reasons for disagreement:
+      flat        fraction of pixels whose candidate set under the oracle's own sweep (its
+                  predecessor value in slot 1) has a second distinct value within TIE_TOL of
+                  the best energy: both are correct picks there
+      disagree    fraction of pixels differing from the oracle's sweep by more than 1e-3
+      cascade     fraction of those disagreements whose chain predecessor already differed
+                  (the predecessor slot is then another value on the two sides)
+      flat_first  fraction of those disagreements whose predecessor agreed (so both sides
+                  had the same candidates): each is a flat pixel by the validity check
     Returns (fraction agreeing with the oracle to 1e-3, pixels checked)."""
     lv = ogem.Level(p, level)
     coarse = level == ogem.COARSE
@@ -75,6 +83,7 @@ def check_mstep(p, ob, rho_before, gpu_rho, level, it, groups=None, frac_bar=Non
                                                                    np.minimum(lv.u // s, wc - 1)]
     checked = 0
     edge_cases = 0
+    n_flat = n_dis = n_casc = 0
     for g in groups:
         n, L = g.shape
         flat = g.ravel()
@@ -82,9 +91,27 @@ def check_mstep(p, ob, rho_before, gpu_rho, level, it, groups=None, frac_bar=Non
         pred = np.concatenate([cur[:, :1], got[g[:, :-1]]], axis=1)
         slot2 = cur if coarse else rc_all[g]
         rand = ogem.candidates_random(p, lv, it, level, rho_cur[flat], flat).reshape(n, L, -1)
-        cand = np.concatenate([cur[..., None], pred[..., None], slot2[..., None], rand, got[g][..., None]], axis=2)
+        opred = np.concatenate([cur[:, :1], ref[g[:, :-1]]], axis=1)
+        cand = np.concatenate([cur[..., None], pred[..., None], slot2[..., None], rand, got[g][..., None],
+                               opred[..., None]], axis=2)
         qhat = w.prior_posteriors(lv.u[flat], lv.v[flat], rho_cur[flat])
-        E = w.energy(lv.u[flat], lv.v[flat], cand.reshape(n * L, K + 1), q[:, flat], qhat).reshape(n, L, K + 1)
+        E = w.energy(lv.u[flat], lv.v[flat], cand.reshape(n * L, K + 2), q[:, flat], qhat).reshape(n, L, K + 2)
+        # the oracle's own candidate set: its sweep's predecessor value in slot 1
+        oset = np.concatenate([cand[..., :1], cand[..., K + 1:], cand[..., 2:K]], axis=2)
+        oE = np.concatenate([E[..., :1], E[..., K + 1:], E[..., 2:K]], axis=2)
+        if coarse:
+            oE[..., 2] = np.inf
+        ob_best = oE.min(axis=2)
+        vbest = np.take_along_axis(oset, np.argmin(oE, axis=2)[..., None], axis=2)
+        other = np.abs(oset - vbest) > MEMBER_TOL * np.abs(vbest)
+        second = np.where(other, oE, np.inf).min(axis=2)
+        is_flat = second - ob_best <= TIE_TOL * (1.0 + np.abs(ob_best))
+        dis = np.abs(got[g] - ref[g]) > 1e-3 * np.abs(ref[g])
+        pdiff = np.abs(pred - opred) > 1e-3 * np.abs(opred)
+        n_flat += int(is_flat.sum())
+        n_dis += int(dis.sum())
+        n_casc += int((dis & pdiff).sum())
+        E = E[..., :K + 1]
         if coarse:
             E[..., 2] = np.inf
         best = E[..., :K].min(axis=2)
@@ -114,6 +141,10 @@ def check_mstep(p, ob, rho_before, gpu_rho, level, it, groups=None, frac_bar=Non
     assert edge_cases <= max(2, 1e-3 * checked), f"{edge_cases} validity-edge decisions in {checked} pixels"
     pix_all = np.concatenate([g.ravel() for g in groups])
     frac = frac_close_rel(got[pix_all], ref[pix_all])
+    if report is not None:
+        report.update(flat=n_flat / max(checked, 1), disagree=n_dis / max(checked, 1),
+                      cascade=n_casc / max(n_dis, 1), flat_first=(n_dis - n_casc) / max(n_dis, 1),
+                      pixels=checked)
     if frac_bar is not None:
         assert frac >= frac_bar, f"only {frac:.4f} of M-step results agree with the oracle's sweep"
     return frac, checked

@@ -193,3 +193,88 @@ def test_network_rejects_odd_sizes(lib):
     net = lib.net_alloc(flat(params))
     with pytest.raises(VoldorError):
         lib.proposal_forward(net, torch.from_numpy(flow[:, :7]).contiguous().cuda(), 1.0, 0.01, 1.0)
+
+
+# ----------------------------------------------------------------------------- learned start
+WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.dirname(
+    __import__("os").path.abspath(__file__))), "paper_2104_06800_amd", "weights", "proposal_n6.npz")
+
+
+def _host(b, keys=("idepth", "rigid", "pose", "conf", "stats")):
+    torch.cuda.synchronize()
+    return {k: b[k].cpu().numpy().copy() for k in keys}
+
+
+def test_nan_weights_fall_back_to_plain_gem(lib):
+    """Unusable network output (NaN weights): the start falls back to the random start and
+    the run continues to plain GEM's full schedule, equal to plain GEM bit for bit."""
+    from paper_2104_06800_amd import proposal as pr, synth
+    w = synth.make_window(4, 1_000_100, H=96, W=128)
+    p = w["params"]
+    params = np.full(pr.init_params(0, p["N"]).shape, np.nan, dtype=np.float32)
+    net = lib.net_alloc(params)
+    a = lib.alloc(p, w["flow"], w["pose_init"])
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    assert pr.learned_run(lib, net, p, a, 4, fallback=fb)
+    assert int(fb.cpu()[0]) == 1
+    b = lib.alloc(p, w["flow"], w["pose_init"])
+    lib.run(p, b, iters=p["iters"])
+    ha, hb = _host(a), _host(b)
+    for k in ha:
+        assert np.array_equal(ha[k], hb[k]), k
+
+
+def test_trained_start_does_not_fall_back_and_batch_matches(lib):
+    """The trained network's start on windows of several shapes (one odd-sized, which takes
+    the random start) in one batched, graph-captured run equals the per-window calls bit for
+    bit, with the fallback flags of the per-window calls."""
+    from paper_2104_06800_amd import proposal as pr, synth
+    params, _ = pr.load(WEIGHTS)
+    net = lib.net_alloc(params)
+    ws = [synth.make_window(4, 1_000_200, H=96, W=128), synth.make_window(2, 1_000_201, H=80, W=160, N=4),
+          synth.make_window(3, 1_000_202, H=64, W=96, N=5), synth.make_window(1, 1_000_203, H=45, W=64)]
+    iters = 3
+    single, flags = [], []
+    for w in ws:
+        p = w["params"]
+        b = lib.alloc(p, w["flow"], w["pose_init"], w.get("prior_idepth"), w.get("prior_pose"))
+        fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+        if p["H"] % 2 == 0 and p["W"] % 2 == 0:
+            lib.proposal_start(net, p, b, fb)
+        else:
+            lib.init_idepth(p, b)
+            fb.fill_(1)
+        lib.run(p, b, iters=iters, init=False)
+        single.append(_host(b))
+        flags.append(int(fb.cpu()[0]))
+    assert flags == [0, 0, 0, 1]
+    batch = [(w["params"], lib.alloc(w["params"], w["flow"], w["pose_init"], w.get("prior_idepth"),
+                                     w.get("prior_pose"))) for w in ws]
+    fbs = torch.full((len(ws),), -1, dtype=torch.int32, device="cuda")
+    for rep in range(2):                          # capture, then replay
+        lib.batch_run_learned(net, batch, iters, fallback=fbs)
+        assert fbs.cpu().tolist() == flags
+        for (_, b), ref in zip(batch, single):
+            got = _host(b)
+            for k in got:
+                assert np.array_equal(got[k], ref[k]), k
+        for (p, b), w in zip(batch, ws):
+            b["pose"].copy_(torch.as_tensor(w["pose_init"], dtype=torch.float64))
+
+
+def test_learned_start_reaches_plain_error_in_fewer_ms(lib):
+    """What the trained network gains on held-out 640x480 street windows (seeds not used in
+    training): GEM from the network's start reaches plain GEM's median static inverse-depth
+    error (median over windows, after median scaling) with fewer iterations, and in fewer
+    wall-clock ms including the network."""
+    from paper_2104_06800_amd import proposal as pr
+    params, _ = pr.load(WEIGHTS)
+    net = lib.net_alloc(params)
+    test = pr.generate(list(range(pr.TEST_SEED0, pr.TEST_SEED0 + 12)), 12)
+    print(f"learned gain: {len(test)} held-out windows", flush=True)
+    summ = pr.summarize(pr.compare(lib, net, test, warm=False))
+    print("learned gain:", {k: v for k, v in summ.items() if k != "err_learned_by_iters"})
+    print("error by iterations:", np.round(summ["err_learned_by_iters"], 4))
+    assert summ["iters_to_plain"] is not None and summ["iters_to_plain"] < 10
+    assert summ["ms_to_plain_error"] < summ["ms_plain"]
+    assert summ["err_learned_full"] < summ["err_plain"]

@@ -102,6 +102,32 @@ def test_batch_run_equals_individual_runs(lib):
         assert np.isfinite(hx["stats"]).all()
 
 
+def test_batched_windows_meet_the_oracle(lib):
+    """Each window of a batch (64x48 N=3; 70x53 N=4 with a depth prior; 61x40 N=5 on 16x16
+    tiles) against the oracle's plain GEM run independently from the same seed: 5
+    iterations from the Philox initial depth, then the final E-step and statistics."""
+    from oracle import gem as ogem
+    ws = windows()
+    iters = 5
+    batch = [(w["params"], alloc(lib, w)) for w in ws]
+    print("batch vs oracle:", [(p["W"], p["H"], p["N"], p.get("P", 0)) for p, _ in batch], flush=True)
+    lib.batch_run(batch, iters)
+    for w, (p, b) in zip(ws, batch):
+        g = host(b)
+        ob = ogem.alloc_buffers(p, w["flow"], w["pose_init"], w.get("prior_idepth"), w.get("prior_pose"))
+        ost = ogem.run(p, ob, iters=iters)
+        rho_frac = np.mean(np.abs(g["idepth"] - ob["idepth"]) <= 1e-3 * ob["idepth"])
+        q_frac = np.mean(np.abs(g["rigid"] - ob["rigid"]) <= 1e-3)
+        dpose = np.abs(g["pose"] - ob["pose"]).max()
+        print(f"{p['W']}x{p['H']} N={p['N']} P={p.get('P', 0)}: rho {rho_frac:.4f} q {q_frac:.4f} "
+              f"pose {dpose:.2e} loglik {g['stats'][0]:.9g} / {ost[0]:.9g} energy {g['stats'][1]:.9g} / "
+              f"{ost[1]:.9g}", flush=True)
+        assert rho_frac >= 0.99 and q_frac >= 0.99
+        assert dpose <= 1e-4
+        assert g["stats"][0] == pytest.approx(ost[0], rel=1e-3)
+        assert g["stats"][1] == pytest.approx(ost[1], rel=1e-3)
+
+
 def test_batch_graph_replay_and_direct_launches_agree(lib):
     """The captured graph, its replay on a later identical call and the uncaptured batched
     launches all give the individual runs' results."""

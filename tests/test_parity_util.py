@@ -26,8 +26,10 @@ def run_mstep(level, it=1):
 @pytest.mark.parametrize("level", [0, 1])
 def test_checker_accepts_identical_result(level):
     p, ob, rb, res = run_mstep(level)
-    frac, n = check_mstep(p, ob, rb, res.astype(np.float32), level, 1)
+    rep = {}
+    frac, n = check_mstep(p, ob, rb, res.astype(np.float32), level, 1, report=rep)
     assert frac == 1.0 and n == res.size
+    assert rep["disagree"] == 0.0 and rep["cascade"] == 0.0 and 0.0 <= rep["flat"] < 0.5
 
 
 def test_checker_rejects_a_planted_worse_choice():
