@@ -161,3 +161,147 @@ def align_p2p(ap, idepth1, idepth2, conf2, pose_inout):
         stats[i] = s
         status[i] = st
     return cov, stats, status
+
+
+# --------------------------------------------------------------------------- #
+# 7-DoF alignment: relative motion and scale, Levenberg-Marquardt
+# --------------------------------------------------------------------------- #
+LM_LAMBDA0 = 1e-4
+LM_LAMBDA_MIN, LM_LAMBDA_MAX = 1e-12, 1e12
+
+
+def linearize_sim3(ap, rho1, nrm, nvalid, rho2, conf2, pose, s):
+    """Eq. 10 with both the motion T (camera 2 -> camera 1) and the relative depth scale s
+    unknown (sec. III-B: "we estimate both their relative motion T and scale factor s").
+    Reading: map 1's geometry is scaled by s, so the plane of pixel l passes through s P1(l):
+      r = rho1 <n, s P1 - Q> / (s Q_z),
+    which reduces to Eq. 9's 1/(s theta1) - 1/phi_z for a fronto-parallel plane.  The
+    unknowns are updated by the left pose update and s <- s exp(d sigma).
+    Returns H (7x7), g (7), cost, count."""
+    Hm6, g6, cost, cnt, r, J6, ok = _sim3_terms(ap, rho1, nrm, nvalid, rho2, conf2, pose, s)
+    return Hm6, g6, cost, cnt
+
+
+def _sim3_terms(ap, rho1, nrm, nvalid, rho2, conf2, pose, s):
+    fx, fy, cx, cy = ap["fx"], ap["fy"], ap["cx"], ap["cy"]
+    H_, W_ = rho1.shape
+    V, U = np.mgrid[0:H_, 0:W_]
+    rho2 = np.asarray(rho2, dtype=np.float64)
+    c2 = np.asarray(conf2, dtype=np.float64)
+    ok = np.isfinite(rho2) & (rho2 > 0) & np.isfinite(c2)
+    r2s = np.where(ok, rho2, 1.0)
+    X2 = geo.rays(U, V, fx, fy, cx, cy) / r2s[..., None]
+    R, t = geo.pose_rt(pose)
+    Q = X2 @ R.T + t
+    Qz = Q[..., 2]
+    ok &= Qz > 0
+    Qzs = np.where(ok, Qz, 1.0)
+    lx = np.floor(fx * Q[..., 0] / Qzs + cx + 0.5)
+    ly = np.floor(fy * Q[..., 1] / Qzs + cy + 0.5)
+    ok &= (lx >= 1) & (lx <= W_ - 2) & (ly >= 1) & (ly <= H_ - 2)
+    li = np.where(ok, lx, 1).astype(np.int64)
+    lj = np.where(ok, ly, 1).astype(np.int64)
+    ok &= nvalid[lj, li]
+    n = nrm[lj, li]
+    r1 = np.where(ok, np.asarray(rho1, dtype=np.float64)[lj, li], 1.0)
+    P1 = geo.rays(li, lj, fx, fy, cx, cy) / r1[..., None]
+    nQ = (n * Q).sum(-1)
+    r = r1 * ((n * P1).sum(-1) * s - nQ) / (s * Qzs)
+    # dr/dQ = -(1/Qz) (rho1 n / s + r e_z);  dr/dsigma = s dr/ds = rho1 <n, Q> / (s Qz)
+    drdQ = -(r1[..., None] * n / s) / Qzs[..., None]
+    drdQ[..., 2] -= r / Qzs
+    qx, qy, qz = Q[..., 0], Q[..., 1], Q[..., 2]
+    J = np.zeros(Q.shape[:-1] + (7,))
+    a0, a1, a2 = drdQ[..., 0], drdQ[..., 1], drdQ[..., 2]
+    J[..., 0] = -a1 * qz + a2 * qy
+    J[..., 1] = a0 * qz - a2 * qx
+    J[..., 2] = -a0 * qy + a1 * qx
+    J[..., 3:6] = drdQ
+    J[..., 6] = r1 * nQ / (s * Qzs)
+    psi, w = robust(np.where(ok, r, 0.0), ap["robust"], ap["robust_scale"])
+    Wt = np.where(ok, c2 * w, 0.0).ravel()
+    Jv = np.where(ok[..., None], J, 0.0).reshape(-1, 7)
+    rv = np.where(ok, r, 0.0).ravel()
+    Hm = np.einsum("n,ni,nj->ij", Wt, Jv, Jv)
+    g = np.einsum("n,ni,n->i", Wt, Jv, rv)
+    cost = float(np.where(ok, c2 * psi, 0.0).sum())
+    return Hm, g, cost, int(ok.sum()), rv, Jv, ok
+
+
+def cholesky_solve_n(A, b):
+    """Solve A x = b by Cholesky (any size); None if A is not numerically positive definite."""
+    n = len(b)
+    L = np.zeros((n, n))
+    for i in range(n):
+        for j in range(i + 1):
+            s = A[i, j] - L[i, :j] @ L[j, :j]
+            if i == j:
+                if not s > 1e-300 * max(1.0, abs(A[i, i])):
+                    return None
+                L[i, i] = np.sqrt(s)
+            else:
+                L[i, j] = s / L[j, j]
+    y = np.zeros(n)
+    for i in range(n):
+        y[i] = (b[i] - L[i, :i] @ y[:i]) / L[i, i]
+    x = np.zeros(n)
+    for i in range(n - 1, -1, -1):
+        x[i] = (y[i] - L[i + 1:, i] @ x[i + 1:]) / L[i, i]
+    return x
+
+
+def align_pair_sim3(ap, rho1, rho2, conf2, pose0, s0):
+    """Levenberg-Marquardt on (T, s) (sec. III-B, Eq. 12 "optimized using Levenberg-Marquardt"):
+    each of ap['gn_steps'] evaluations tries the step solving (H + lambda diag(H)) d = -g at
+    the last accepted state; a trial with a lower cost is accepted (lambda / 10), otherwise
+    rejected (lambda * 10); lambda starts at 1e-4.  The covariance of (T, log s) is H^-1 at the
+    accepted state (7x7).  Returns (pose, s, cov, stats [cost0, cost, count, accepted steps],
+    status)."""
+    nrm, nvalid = normals(rho1, ap["fx"], ap["fy"], ap["cx"], ap["cy"], ap["normal_disc_rel"])
+    pose = np.asarray(pose0, dtype=np.float64).copy()
+    s = float(s0)
+    Hm, g, cost, cnt = linearize_sim3(ap, rho1, nrm, nvalid, rho2, conf2, pose, s)
+    cost0 = cost
+    lam = LM_LAMBDA0
+    accepted = 0
+    status = 0
+    for _ in range(ap["gn_steps"]):
+        A = Hm + lam * np.diag(np.diag(Hm))
+        d = cholesky_solve_n(A, -g)
+        if d is None:
+            status = ESINGULAR
+            break
+        tp = geo.left_update(pose, d[:6])
+        ts = s * np.exp(d[6])
+        Ht, gt, ct, nt = linearize_sim3(ap, rho1, nrm, nvalid, rho2, conf2, tp, ts)
+        if ct < cost:
+            pose, s, Hm, g, cost, cnt = tp, ts, Ht, gt, ct, nt
+            lam = max(lam / 10.0, LM_LAMBDA_MIN)
+            accepted += 1
+        else:
+            lam = min(lam * 10.0, LM_LAMBDA_MAX)
+    cov = np.full((7, 7), np.nan)
+    if status == 0:
+        cols = [cholesky_solve_n(Hm, e) for e in np.eye(7)]
+        if any(c is None for c in cols):
+            status = ESINGULAR
+        else:
+            cov = np.array(cols).T
+    return pose, s, cov, np.array([cost0, cost, cnt, accepted], dtype=np.float64), status
+
+
+def align_sim3(ap, idepth1, idepth2, conf2, pose_inout, scale_inout):
+    """All pairs: updates pose_inout [n][6] and scale_inout [n]; returns cov [n][49],
+    stats [n][4], status [n]."""
+    n = len(idepth1)
+    cov = np.zeros((n, 49))
+    stats = np.zeros((n, 4))
+    status = np.zeros(n, dtype=np.int32)
+    for i in range(n):
+        p, s, c, st, code = align_pair_sim3(ap, idepth1[i], idepth2[i], conf2[i], pose_inout[i], scale_inout[i])
+        pose_inout[i] = p
+        scale_inout[i] = s
+        cov[i] = c.ravel()
+        stats[i] = st
+        status[i] = code
+    return cov, stats, status
