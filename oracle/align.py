@@ -228,28 +228,6 @@ def _sim3_terms(ap, rho1, nrm, nvalid, rho2, conf2, pose, s):
     return Hm, g, cost, int(ok.sum()), rv, Jv, ok
 
 
-def cholesky_solve_n(A, b):
-    """Solve A x = b by Cholesky (any size); None if A is not numerically positive definite."""
-    n = len(b)
-    L = np.zeros((n, n))
-    for i in range(n):
-        for j in range(i + 1):
-            s = A[i, j] - L[i, :j] @ L[j, :j]
-            if i == j:
-                if not s > 1e-300 * max(1.0, abs(A[i, i])):
-                    return None
-                L[i, i] = np.sqrt(s)
-            else:
-                L[i, j] = s / L[j, j]
-    y = np.zeros(n)
-    for i in range(n):
-        y[i] = (b[i] - L[i, :i] @ y[:i]) / L[i, i]
-    x = np.zeros(n)
-    for i in range(n - 1, -1, -1):
-        x[i] = (y[i] - L[i + 1:, i] @ x[i + 1:]) / L[i, i]
-    return x
-
-
 def align_pair_sim3(ap, rho1, rho2, conf2, pose0, s0):
     """Levenberg-Marquardt on (T, s) (sec. III-B, Eq. 12 "optimized using Levenberg-Marquardt"):
     each of ap['gn_steps'] evaluations tries the step solving (H + lambda diag(H)) d = -g at
@@ -267,7 +245,7 @@ def align_pair_sim3(ap, rho1, rho2, conf2, pose0, s0):
     status = 0
     for _ in range(ap["gn_steps"]):
         A = Hm + lam * np.diag(np.diag(Hm))
-        d = cholesky_solve_n(A, -g)
+        d = cholesky_solve(A, -g)
         if d is None:
             status = ESINGULAR
             break
@@ -282,7 +260,7 @@ def align_pair_sim3(ap, rho1, rho2, conf2, pose0, s0):
             lam = min(lam * 10.0, LM_LAMBDA_MAX)
     cov = np.full((7, 7), np.nan)
     if status == 0:
-        cols = [cholesky_solve_n(Hm, e) for e in np.eye(7)]
+        cols = [cholesky_solve(Hm, e) for e in np.eye(7)]
         if any(c is None for c in cols):
             status = ESINGULAR
         else:
