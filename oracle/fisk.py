@@ -79,3 +79,42 @@ def prior_posterior(z, log_kappa, pi_hat):
         odds = np.where(pi_hat > 0, (1.0 - pi_hat) / np.where(pi_hat > 0, pi_hat, 1.0), np.inf)
         q = 1.0 / (1.0 + odds * np.exp(a))
     return np.where(pi_hat > 0, q, 0.0)
+
+
+# --------------------------------------------------------------------------- #
+# depth priors from an external source: empirical residual model (sec. III-A, the text after
+# the prior energy: priors of known external sources such as stereo replace Eq. 3 by an
+# empirical residual model, as VOLDOR does for the flow)
+# --------------------------------------------------------------------------- #
+def disparity_residual(rho_hat, inv_phi, fb):
+    """Signed disparity residual (px) of a prior value rho^ against the transferred candidate
+    1/phi_z: disparity = fb * inverse depth, fb = focal length times baseline."""
+    return fb * (np.asarray(rho_hat, dtype=np.float64) - np.asarray(inv_phi, dtype=np.float64))
+
+
+def disparity_log_ratio(r, alpha, beta, D):
+    """log(p0 / p1) for a signed disparity residual r: inlier density p1(r) = f_Fisk(|r|) / 2
+    (the magnitude log-logistic, the sign equally likely; maximal at 0 for beta <= 1, floored
+    at |r| = 1e-3 alpha for beta < 1), outlier density p0 = 1 / D (uniform over a disparity
+    range of width D)."""
+    a = np.maximum(np.abs(np.asarray(r, dtype=np.float64)), 1e-3 * alpha if beta < 1 else 0.0)
+    z = a / alpha
+    log_p1 = np.log(beta / alpha) + (beta - 1.0) * np.log(np.where(z > 0, z, 1.0)) - 2.0 * np.log1p(z ** beta) \
+        - np.log(2.0)
+    if beta != 1.0:
+        log_p1 = np.where(z > 0, log_p1, -np.inf if beta > 1 else np.inf)
+    return -np.log(D) - log_p1
+
+
+def disparity_prior_term(r, alpha, beta, D):
+    """MIE cost -log(p1 / (p0 + p1)) = softplus(log(p0 / p1)) of one disparity prior term."""
+    return np.logaddexp(0.0, disparity_log_ratio(r, alpha, beta, D))
+
+
+def disparity_prior_posterior(r, alpha, beta, D, pi_hat):
+    """q = pi p1 / (pi p1 + (1 - pi) p0) at the current depth."""
+    pi_hat = np.asarray(pi_hat, dtype=np.float64)
+    a = disparity_log_ratio(r, alpha, beta, D)
+    with np.errstate(divide="ignore", over="ignore"):
+        odds = np.where(pi_hat > 0, (1.0 - pi_hat) / np.where(pi_hat > 0, pi_hat, 1.0), np.inf)
+        return 1.0 / (1.0 + odds * np.exp(a))

@@ -96,6 +96,11 @@ class Window:
         self.L0 = win["outlier_density"]
         self.flow = np.asarray(bufs["flow"], dtype=np.float64)
         self.log_kappa = fisk.prior_log_kappa(win["prior_sigma_rel"], win["prior_uniform_rel"])
+        # prior model: 0 Gaussian-uniform mixture on inverse depth (Eq. 3); 1 empirical
+        # log-logistic model of the disparity residual (external stereo priors), with
+        # prior_sigma_rel its scale (px), prior_fisk_beta its shape, prior_uniform_rel the
+        # width (px) of the outlier disparity range and prior_disp_scale = f * baseline
+        self.disparity = int(win.get("prior_model", 0)) == 1
 
     def rays(self, u, v):
         return geo.rays(u, v, *self.intr)
@@ -147,7 +152,9 @@ class Window:
     def prior_z(self, k, u, v, rho):
         """Normalised inverse-depth difference z = (rho^(l) - 1/phi_z) / sigma for prior k,
         with l the nearest pixel of the transfer of the candidate into prior camera k.
-        Reading of the garbled l = pi(theta_2^j, T^_k): theta_2 is the candidate depth."""
+        Reading of the garbled l = pi(theta_2^j, T^_k): theta_2 is the candidate depth.
+        With the empirical disparity model (prior_model 1) z is the signed disparity
+        residual fb (rho^(l) - 1/phi_z) instead."""
         rho = np.asarray(rho, dtype=np.float64)
         u = np.broadcast_to(np.reshape(u, np.shape(u) + (1,) * (rho.ndim - np.ndim(u))), rho.shape)
         v = np.broadcast_to(np.reshape(v, np.shape(v) + (1,) * (rho.ndim - np.ndim(v))), rho.shape)
@@ -163,8 +170,26 @@ class Window:
         ok = inside & np.isfinite(rh) & (rh > 0)
         rh = np.where(ok, rh, 1.0)
         inv_phi = rho / np.where(zok, Q[..., 2], 1.0)           # 1 / phi_z = rho / (rho Q_z)
-        z = (rh - inv_phi) / (self.win["prior_sigma_rel"] * rh)
+        if self.disparity:
+            z = fisk.disparity_residual(rh, inv_phi, self.win["prior_disp_scale"])
+        else:
+            z = (rh - inv_phi) / (self.win["prior_sigma_rel"] * rh)
         return np.where(ok, z, 0.0), ok
+
+    def prior_cost(self, z):
+        """MIE cost of a prior term with a valid transfer (Eq. 4 on Eq. 3's mixture, or on the
+        empirical disparity model)."""
+        if self.disparity:
+            w = self.win
+            return fisk.disparity_prior_term(z, w["prior_sigma_rel"], w["prior_fisk_beta"], w["prior_uniform_rel"])
+        return fisk.prior_term(z, self.log_kappa)
+
+    def prior_q(self, z, pi_hat):
+        if self.disparity:
+            w = self.win
+            return fisk.disparity_prior_posterior(z, w["prior_sigma_rel"], w["prior_fisk_beta"],
+                                                  w["prior_uniform_rel"], pi_hat)
+        return fisk.prior_posterior(z, self.log_kappa, pi_hat)
 
     def prior_weight(self, k, u, v):
         pw = self.b.get("prior_weight")
@@ -177,7 +202,7 @@ class Window:
         out = np.zeros((self.P,) + np.shape(u))
         for k in range(self.P):
             z, ok = self.prior_z(k, u, v, rho)
-            out[k] = np.where(ok, fisk.prior_posterior(z, self.log_kappa, self.prior_weight(k, u, v)), 0.0)
+            out[k] = np.where(ok, self.prior_q(z, self.prior_weight(k, u, v)), 0.0)
         return out
 
     # -- total per-pixel energy (Eq. 5) ---------------------------------------
@@ -190,7 +215,7 @@ class Window:
         E = np.einsum("tn,tnk->nk", q, cost)
         for k in range(self.P):
             z, ok = self.prior_z(k, u, v, rho)
-            term = np.where(ok, fisk.prior_term(z, self.log_kappa), fisk.LOG2)
+            term = np.where(ok, self.prior_cost(z), fisk.LOG2)
             E = E + np.where(qhat[k][:, None] > 0, qhat[k][:, None] * term, 0.0)
         return E
 

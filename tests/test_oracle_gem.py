@@ -463,3 +463,68 @@ def test_prior_transfer_rotated_camera_matches_ray_caster():
     diff = np.abs(z * win["prior_sigma_rel"] * rk[lyc, lxc])   # |rho^(l) - 1/phi_z|
     assert (diff[tilted] <= 0.5 * (gx + gy)[tilted] * 1.01 + 1e-12).all()
     assert np.abs(z[tilted]).max() > 1e-6        # nearest sampling is visible there
+
+
+# ----------------------------------------------------------------------------- empirical disparity prior model
+@pytest.mark.parametrize("beta", [1.0, 0.7])
+def test_disparity_model_matches_fisk_law(beta):
+    """Inlier density of a signed disparity residual: the log-logistic law of |r| halved
+    (scipy's fisk), a density on the line; the MIE cost and posterior from their
+    definitions."""
+    from scipy import integrate, stats
+    a, D = 0.6, 64.0
+    r = np.array([-5.0, -0.7, -0.01, 0.02, 0.3, 1.1, 9.0])
+    p1 = stats.fisk.pdf(np.abs(r), c=beta, scale=a) / 2
+    p0 = 1.0 / D
+    np.testing.assert_allclose(fisk.disparity_log_ratio(r, a, beta, D), np.log(p0 / p1), rtol=1e-12)
+    np.testing.assert_allclose(fisk.disparity_prior_term(r, a, beta, D), -np.log(p1 / (p0 + p1)), rtol=1e-12)
+    pi = 0.35
+    np.testing.assert_allclose(fisk.disparity_prior_posterior(r, a, beta, D, pi), pi * p1 / (pi * p1 + (1 - pi) * p0),
+                               rtol=1e-12)
+    # mass on the line: the law's CDF z^b / (1 + z^b); below |r| = 1e-3 a the density of a
+    # shape < 1 is floored, so the integral starts past the floor there
+    lo = 0.0 if beta == 1.0 else 2e-3 * a
+    half = integrate.quad(lambda x: np.exp(-fisk.disparity_log_ratio(x, a, beta, D)) / D, lo, np.inf, limit=200)[0]
+    z = lo / a
+    assert 2 * half == pytest.approx(1.0 - z ** beta / (1 + z ** beta), rel=1e-6)
+
+
+def test_disparity_transfer_closed_form():
+    """The transfer under pure forward translation with the disparity model: z is the
+    disparity residual fb (rho^(l) - rho / (1 + rho t_z))."""
+    H, W, tz, fb = 30, 40, -0.35, 389.0
+    yy, xx = np.mgrid[0:H, 0:W]
+    prior = 0.1 + 0.003 * xx + 0.0011 * yy
+    win, ww = _prior_window(H, W, [0, 0, 0, 0, 0, tz], prior)
+    win.update(prior_model=1, prior_disp_scale=fb, prior_fisk_beta=1.0)
+    ww = gem.Window(win, ww.b)
+    rng = np.random.default_rng(23)
+    u, v, rho = rng.integers(0, W, 300), rng.integers(0, H, 300), rng.uniform(0.05, 1.0, 300)
+    z, ok = ww.prior_z(0, u, v, rho)
+    D = 1.0 + rho * tz
+    lx = np.floor((u - win["cx"]) / D + win["cx"] + 0.5)
+    ly = np.floor((v - win["cy"]) / D + win["cy"] + 0.5)
+    inside = (lx >= 0) & (lx <= W - 1) & (ly >= 0) & (ly <= H - 1)
+    np.testing.assert_array_equal(ok, inside)
+    np.testing.assert_allclose(z[inside], fb * (0.1 + 0.003 * lx + 0.0011 * ly - rho / D)[inside], rtol=1e-12)
+
+
+def test_disparity_prior_alone_pins_depth():
+    """No flow weight (q = 0), the disparity model with an identity-pose prior: every pixel
+    whose prior value is among its candidates takes it (the density peaks at r = 0), and a
+    pass from elsewhere never moves a pixel away from its prior."""
+    w, win = small_window(N=3, P=1)
+    win.update(prior_model=1, prior_disp_scale=200.0, prior_fisk_beta=1.0, prior_sigma_rel=0.5,
+               prior_uniform_rel=100.0)
+    H, W = win["H"], win["W"]
+    rng = np.random.default_rng(12)
+    prior = rng.uniform(0.1, 0.9, (1, H, W))
+    b = gem.alloc_buffers(win, w["flow"], w["pose_gt"], prior, np.zeros((1, 6)))
+    b["rigid"][...] = 0.0
+    b["idepth"][...] = prior[0]
+    gem.depth_update(win, b, 0, 1)
+    assert np.array_equal(b["idepth"], prior[0])
+    b["idepth"][...] = np.clip(prior[0] * 1.3, 0.02, 1.25)
+    before = np.abs(b["idepth"] - prior[0])
+    gem.depth_update(win, b, 5, 1)
+    assert (np.abs(b["idepth"] - prior[0]) <= before + 1e-15).all()
