@@ -494,14 +494,52 @@ def pose_step(win, bufs, it=0):
 # --------------------------------------------------------------------------- #
 # init, iteration, confidence (Eq. 6)
 # --------------------------------------------------------------------------- #
+def prior_bootstrap(win, bufs, rounds=2):
+    """Inverse depth of every reference pixel read off the first depth prior (sec. III-A:
+    VOLDOR+ starts from explicit priors where VOLDOR bootstraps its hidden variables
+    deterministically).  The value sought makes the transfer into prior 0's camera meet the
+    prior at the pixel it lands on: with X = x~ / rho, R X + t has depth a / rho + t_z
+    (a = r_3 . x~), so 1 / phi_z = rho^(l) solves to rho = rho^(l) a / (1 - rho^(l) t_z).
+    l depends on rho; two fixed-point rounds start from the prior's value at the same pixel
+    (for an identity prior pose the first round is exact).  Returns (rho, ok); ok is false
+    where a round lands outside the image or behind the camera, or meets a hole (NaN or
+    non-positive value) or a non-positive solution."""
+    H, W = win["H"], win["W"]
+    fx, fy, cx, cy = win["fx"], win["fy"], win["cx"], win["cy"]
+    V, U = np.mgrid[0:H, 0:W]
+    x = geo.rays(U, V, fx, fy, cx, cy)
+    R, t = geo.pose_rt(bufs["prior_pose"][0])
+    pri = np.asarray(bufs["prior_idepth"][0], dtype=np.float64)
+    a = x @ R[2]
+    rho = pri.copy()
+    ok = np.isfinite(rho) & (rho > 0)
+    for _ in range(rounds):
+        Q = x @ R.T / np.where(ok, rho, 1.0)[..., None] + t
+        lx, ly, zok = geo.project(Q, fx, fy, cx, cy)
+        lx = np.floor(lx + 0.5)
+        ly = np.floor(ly + 0.5)
+        ok &= zok & (lx >= 0) & (lx <= W - 1) & (ly >= 0) & (ly <= H - 1)
+        rh = pri[np.where(ok, ly, 0).astype(np.int64), np.where(ok, lx, 0).astype(np.int64)]
+        den = 1.0 - rh * t[2]
+        ok &= np.isfinite(rh) & (rh > 0) & (den > 0) & (a > 0)
+        rho = np.where(ok, rh * a / np.where(ok, den, 1.0), 0.0)
+    return rho, ok
+
+
 def init_idepth(win, bufs):
-    """Random initial inverse depth: rho_min + u (rho_max - rho_min), u from Philox
-    (pixel index, group 0, iteration 0, local level, purpose INIT), first word."""
+    """Initial inverse depth.  Random rho_min + u (rho_max - rho_min), u from Philox (pixel
+    index, group 0, iteration 0, local level, purpose INIT), first word; with a depth prior
+    (P >= 1, unless init_random is set) every pixel that prior_bootstrap resolves starts at
+    that value instead, clamped to [rho_min, rho_max]."""
     H, W = win["H"], win["W"]
     u = philox.uniforms(np.arange(H * W), 0, 0, LOCAL, philox.PURPOSE_INIT, win["window_id"],
                         win["seed"])[:, 0]
     lo, hi = win["idepth_min"], win["idepth_max"]
-    bufs["idepth"][...] = (lo + u * (hi - lo)).reshape(H, W)
+    rho = (lo + u * (hi - lo)).reshape(H, W)
+    if win.get("P", 0) >= 1 and not win.get("init_random", 0) and bufs.get("prior_idepth") is not None:
+        boot, ok = prior_bootstrap(win, bufs)
+        rho = np.where(ok, np.clip(boot, lo, hi), rho)
+    bufs["idepth"][...] = rho
 
 
 def gem_step(win, bufs, it):

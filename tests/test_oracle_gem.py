@@ -465,6 +465,116 @@ def test_prior_transfer_rotated_camera_matches_ray_caster():
     assert np.abs(z[tilted]).max() > 1e-6        # nearest sampling is visible there
 
 
+# ----------------------------------------------------------------------------- initial depth from a prior
+@pytest.mark.parametrize("tz", [0.8, -0.35])
+def test_prior_bootstrap_forward_translation_closed_form(tz):
+    """A fronto-parallel plane at depth Z seen by a prior camera displaced by t_z along the
+    optical axis: its prior map is 1/(Z + t_z) everywhere, and the start value must be the
+    true 1/Z at every pixel whose transfer stays inside the prior image (all of them for
+    t_z > 0; for t_z < 0 the border pixels land outside and stay random)."""
+    H, W, Z = 30, 40, 3.0
+    prior = np.full((H, W), 1.0 / (Z + tz))
+    win, ww = _prior_window(H, W, [0, 0, 0, 0, 0, tz], prior)
+    rho, ok = gem.prior_bootstrap(win, ww.b)
+    np.testing.assert_allclose(rho[ok], 1.0 / Z, rtol=1e-13)
+    if tz > 0:
+        assert ok.all()
+    else:
+        # a point at inverse depth r lands at c + (j - c) / (1 + r t_z); both rounds must land
+        # inside: the first from the prior's own value 1/(Z + t_z), the second from 1/Z
+        V, U = np.mgrid[0:H, 0:W]
+        inside = np.ones((H, W), dtype=bool)
+        for r in (1.0 / (Z + tz), 1.0 / Z):
+            D = 1.0 + r * tz
+            lx = np.floor((U - win["cx"]) / D + win["cx"] + 0.5)
+            ly = np.floor((V - win["cy"]) / D + win["cy"] + 0.5)
+            inside &= (lx >= 0) & (lx <= W - 1) & (ly >= 0) & (ly <= H - 1)
+        assert 50 < (~inside).sum() < inside.sum()
+        np.testing.assert_array_equal(ok, inside)
+
+
+def test_prior_bootstrap_two_rounds_on_a_varying_map():
+    """Forward translation t_z = 0.6 over a prior map that varies per pixel: each round reads
+    the map where the previous value lands, c + (j - c) / (1 + r t_z), and solves
+    rho = rho^(l) / (1 - rho^(l) t_z) (r_3 . x~ = 1 without rotation); the second round
+    starts from the first round's value."""
+    H, W, tz = 30, 40, 0.6
+    yy, xx = np.mgrid[0:H, 0:W]
+    prior = 0.2 + 0.004 * xx + 0.002 * yy
+    win, ww = _prior_window(H, W, [0, 0, 0, 0, 0, tz], prior)
+    rho, ok = gem.prior_bootstrap(win, ww.b)
+    assert ok.all()
+    r = prior.copy()
+    for _ in range(2):
+        D = 1.0 + r * tz
+        lx = np.floor((xx - win["cx"]) / D + win["cx"] + 0.5).astype(int)
+        ly = np.floor((yy - win["cy"]) / D + win["cy"] + 0.5).astype(int)
+        rh = prior[ly, lx]
+        r = rh / (1.0 - rh * tz)
+    np.testing.assert_allclose(rho, r, rtol=1e-13)
+    one, _ = gem.prior_bootstrap(win, ww.b, rounds=1)
+    assert (one != rho).sum() > 50           # the second round moves many pixels
+
+
+def test_prior_bootstrap_rotated_camera_matches_ray_caster():
+    """A rotated and translated prior camera in front of two planes fronto-parallel to it,
+    its inverse-depth map ray-cast by the input generator: the start value equals the true
+    reference inverse depth to rounding wherever the transfer lands well inside the plane
+    region the reference pixel sees (the prior is constant there, so any landing pixel on
+    that plane gives the exact solution).  A wrong direction of T^, a dropped r_3 . x~
+    factor or a wrong sign of t_z breaks it."""
+    H, W, f = 36, 48, 40.0
+    intr = (f, f, (W - 1) / 2 + 0.3, (H - 1) / 2 - 0.2)
+    Rk = synth._rot(np.deg2rad([3.0, -4.0, 2.0]))
+    tk = np.array([0.12, -0.05, 0.3])
+    axis, cam_c = Rk[2], -Rk.T @ tk
+    scene = synth.Scene(planes_n=np.array([-axis, -axis]),
+                        planes_d=np.array([-(axis @ cam_c + 4.0), -(axis @ cam_c + 9.0)]),
+                        quads=[synth._quad([1.0, 0.3, 3.0], 25.0, 10.0, 0.9, 0.6)])
+    z_ref, obj_ref, _ = synth._raycast(scene, 0, H, W, intr, (np.eye(3), np.zeros(3)))
+    z_k, obj_k, _ = synth._raycast(scene, 0, H, W, intr, (Rk, tk))
+    win, ww = _prior_window(H, W, synth._as6((Rk, tk)), 1.0 / z_k, f=f)
+    win.update(cx=intr[2], cy=intr[3])
+    rho, ok = gem.prior_bootstrap(win, gem.Window(win, ww.b).b)
+    X = synth._rays(H, W, *intr, (np.eye(3), np.zeros(3)))[1].reshape(-1, 3) * z_ref.ravel()[:, None]
+    px, py, _ = synth._project(X, (Rk, tk), intr)
+    lx, ly = np.floor(px + 0.5).astype(int), np.floor(py + 0.5).astype(int)
+    lxc, lyc = np.clip(lx, 0, W - 1), np.clip(ly, 0, H - 1)
+    inside = (lx >= 2) & (lx <= W - 3) & (ly >= 2) & (ly <= H - 3)
+    nb = np.stack([obj_k[np.clip(lyc + dy, 0, H - 1), np.clip(lxc + dx, 0, W - 1)]
+                   for dy in range(-2, 3) for dx in range(-2, 3)])
+    flat = inside & (obj_ref.ravel() < 100) & (nb == obj_ref.ravel()).all(0)
+    assert flat.sum() > 300
+    # the start at the same pixel lands near the true l; every such pixel resolves exactly
+    good = flat & ok.ravel()
+    assert good.sum() >= 0.95 * flat.sum()
+    np.testing.assert_allclose(rho.ravel()[good], 1.0 / z_ref.ravel()[good], rtol=1e-10)
+
+
+def test_init_idepth_uses_prior_where_it_resolves():
+    """Identity prior pose: the start is the prior clamped to [rho_min, rho_max] at every
+    finite positive prior pixel and the random start (bit for bit) at holes; init_random
+    restores the random start everywhere."""
+    H, W = 20, 24
+    rng = np.random.default_rng(3)
+    prior = rng.uniform(0.0, 1.6, (H, W))
+    prior[rng.uniform(size=(H, W)) < 0.2] = np.nan
+    prior[0, :3] = [0.0, -0.2, np.inf]
+    win, ww = _prior_window(H, W, np.zeros(6), prior)
+    win = dict(win, idepth_min=0.05, idepth_max=1.25)
+    b = ww.b
+    gem.init_idepth(win, b)
+    start = b["idepth"].copy()
+    gem.init_idepth(dict(win, P=0), b)
+    rand = b["idepth"].copy()
+    gem.init_idepth(dict(win, init_random=1), b)
+    np.testing.assert_array_equal(b["idepth"], rand)
+    good = np.isfinite(prior) & (prior > 0)
+    np.testing.assert_array_equal(start[good], np.clip(prior[good], 0.05, 1.25))
+    np.testing.assert_array_equal(start[~good], rand[~good])
+    assert (~good).sum() > 50 and (prior[good] > 1.25).sum() > 10 and (prior[good] < 0.05).sum() > 5
+
+
 # ----------------------------------------------------------------------------- empirical disparity prior model
 @pytest.mark.parametrize("beta", [1.0, 0.7])
 def test_disparity_model_matches_fisk_law(beta):
