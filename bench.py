@@ -192,22 +192,16 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import gem as ogem
-        ob = ogem.alloc_buffers(p, w["flow"], w["pose_init"])
-        ogem.init_idepth(p, ob)
-        t0 = time.perf_counter()
-        ogem.gem_step(p, ob, 0)
-        cs = time.perf_counter() - t0
-        cpu = {"value": round(H * W * N / cs, 1), "unit": "pixel-frame updates/s", "cores": 1,
-               "kind": "oracle", "sample": f"GEM iteration 0 of the same {W}x{H} N={N} K={K} window "
-                                           f"(FP64 numpy, single thread), {cs:.1f} s"}
-        log(f"oracle: {cs:.1f} s for one iteration -> {cpu['value']:.0f} pixel-frame updates/s")
+        cpu = cpu_baseline(w, H, W, N, K)
 
     extra = {}
     if not args.only_window:
+        extra["vc"] = vc_workload(lib, np, torch, w, b)
+        extra["hierarchy"] = hierarchy_sweep(lib, np, torch, w)
         extra["batch"] = batch_workload(lib, np, torch, args)
         extra["learned_init"], extra["proposal"] = learned_init(lib, np, torch)
         extra["align"] = align_workload(lib, np, torch)
+        extra["keyframe"] = keyframe_workload(lib, np, torch)
 
     out = {
         "metric": "GEM pixel-frame updates/s at 1216x352 N=6",
@@ -231,6 +225,52 @@ def main():
     }
     print(json.dumps(out), flush=True)
     lib.close()
+
+
+def _oracle_iteration(w):
+    """GEM iteration 0 of a window by the FP64 oracle, single-threaded; returns seconds."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import gem as ogem
+    p = w["params"]
+    ob = ogem.alloc_buffers(p, w["flow"], w["pose_init"])
+    ogem.init_idepth(p, ob)
+    t0 = time.perf_counter()
+    ogem.gem_step(p, ob, 0)
+    return time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, H, W, N, K):
+    """The FP64 oracle as it stands on this host: GEM iteration 0 of the benchmark window on one
+    core, then the same iteration of independent copies of the window on every core of the
+    GPU's host share at once (windows are independent, so that is the oracle's throughput on
+    all cores)."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    cs1 = _oracle_iteration(w)
+    one = H * W * N / cs1
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        per = list(ex.map(_oracle_iteration, [w] * cores))
+    wall = time.perf_counter() - t0
+    allc = cores * H * W * N / max(per)
+    log(f"oracle: {cs1:.1f} s for one iteration on one core -> {one:.0f} pixel-frame updates/s; "
+        f"{cores} cores at once: {max(per):.1f} s each (wall {wall:.1f} s) -> {allc:.0f}")
+    return {"value": round(allc, 1), "unit": "pixel-frame updates/s", "cores": cores, "kind": "oracle",
+            "value_one_core": round(one, 1), "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "sample": f"GEM iteration 0 of the same {W}x{H} N={N} K={K} window (FP64 numpy): once on one "
+                      f"core ({cs1:.1f} s), then {cores} independent copies at once, one per core "
+                      f"({max(per):.1f} s)"}
 
 
 def _pool_generate(fn, items, workers=16):
@@ -292,6 +332,87 @@ def align_workload(lib, np, torch, n_pairs=32, reps=5):
     return out
 
 
+def _keyframe_pair(k):
+    from paper_2104_06800_amd import synth
+    return synth.keyframe_pair(k)
+
+
+def keyframe_workload(lib, np, torch, n_pairs=32, reps=5):
+    """The prior-window workload: 2 x n_pairs indoor 640x480, N=8 windows with one depth prior
+    each (ground truth with 5% multiplicative noise and 10% holes, 6-DoF motion <= 5 deg /
+    0.3 m), GEM on each (timed per window), then the n_pairs keyframe alignments on the GEM
+    outputs and window b's confidence in one call: Huber delta 0.02, 10 Gauss-Newton steps,
+    started from the chained visual-odometry estimate (the true relative pose moved by up to
+    1 deg and 3 cm per axis)."""
+    from scipy.spatial.transform import Rotation
+    from paper_2104_06800_amd import synth
+    t0 = time.time()
+    pairs = _pool_generate(_keyframe_pair, list(range(n_pairs)))
+    log(f"keyframe: {n_pairs} pairs ({2 * n_pairs} prior windows) generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda", 0)
+    maps1, maps2, confs, errs, win_ms = [], [], [], [], []
+    for wa, wb, _ in pairs:
+        for w, tgt in ((wa, "a"), (wb, "b")):
+            p = w["params"]
+            b = lib.alloc(p, w["flow"], w["pose_init"], w["prior_idepth"], w["prior_pose"])
+            pose0 = b["pose"].clone()
+            lib.run(p, b, iters=p["iters"])            # warm-up (and the result: runs are deterministic)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            b["pose"].copy_(pose0)
+            e0.record()
+            lib.run(p, b, iters=p["iters"])
+            e1.record()
+            torch.cuda.synchronize()
+            win_ms.append(e0.elapsed_time(e1))
+            rho = b["idepth"].cpu().numpy()
+            errs.append(float(np.median(np.abs(rho - w["idepth_gt"]) / w["idepth_gt"])))
+            if tgt == "a":
+                maps1.append(rho)
+            else:
+                maps2.append(rho)
+                confs.append(b["conf"].cpu().numpy())
+            del b
+    p = pairs[0][0]["params"]
+    H, W, N, I = p["H"], p["W"], p["N"], p["iters"]
+    fx, fy, cx, cy = pairs[0][0]["intr"]
+    ap = dict(H=H, W=W, fx=fx, fy=fy, cx=cx, cy=cy, robust=0, robust_scale=0.02, gn_steps=10,
+              normal_disc_rel=0.2, scale_s=1.0)
+    rng = np.random.default_rng(11)
+    truth = np.stack([pr[2] for pr in pairs])
+    start = np.stack([synth.vo_start(rng, x) for x in truth])
+    t = lambda a, dt=torch.float32: torch.as_tensor(np.stack(a), dtype=dt, device=dev).contiguous()
+    r1, r2, c2 = t(maps1), t(maps2), t(confs)
+    pose = torch.as_tensor(start, dtype=torch.float64, device=dev)
+    lib.align_p2p(ap, r1, r2, c2, pose)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        pose.copy_(torch.as_tensor(start, dtype=torch.float64))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, st, status = lib.align_p2p(ap, r1, r2, c2, pose)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    got = pose.cpu().numpy()
+    rot_err = lambda a, b: [np.degrees((Rotation.from_rotvec(g[:3]) * Rotation.from_rotvec(x[:3]).inv()).magnitude())
+                            for g, x in zip(a, b)]
+    ms_w = float(np.median(win_ms))
+    out = {"windows": 2 * n_pairs, "H": H, "W": W, "N": N, "iters": I, "P": 1,
+           "window_ms_p50": round(ms_w, 3), "window_ms_p90": round(float(np.percentile(win_ms, 90)), 3),
+           "window_updates_per_s": round(H * W * N * I / (ms_w / 1e3), 1),
+           "median_window_rel_error": round(float(np.median(errs)), 4),
+           "align_ms_per_call": round(float(np.median(ts)), 3), "align_pairs": n_pairs,
+           "align_median_rot_err_deg": round(float(np.median(rot_err(got, truth))), 4),
+           "align_median_trans_err": round(float(np.median(np.linalg.norm(got[:, 3:] - truth[:, 3:], axis=1))), 5),
+           "start_median_rot_err_deg": round(float(np.median(rot_err(start, truth))), 4),
+           "start_median_trans_err": round(float(np.median(np.linalg.norm(start[:, 3:] - truth[:, 3:], axis=1))), 5),
+           "align_converged": int((status.cpu().numpy() == 0).sum()),
+           "workload": "indoor room windows 640x480 N=8 with a 5%-noise depth prior (10% holes), GEM from "
+                       "the prior, then keyframe alignment of the GEM outputs and confidence (Huber 0.02, "
+                       "10 Gauss-Newton steps, from a visual-odometry start within 1 deg / 3 cm)"}
+    log("keyframe: " + json.dumps(out))
+    return out
 def batch_workload(lib, np, torch, args, pool=True):
     from paper_2104_06800_amd import synth
     t0 = time.time()
@@ -348,7 +469,74 @@ def batch_workload(lib, np, torch, args, pool=True):
     px = sum(p["H"] * p["W"] * p["N"] for p, _, _ in items) * iters
     log(f"batch: sequential {seq_ms:.2f} ms ({len(items) / seq_ms * 1e3:.0f} windows/s), batched graph "
         f"{bat_ms:.2f} ms ({len(items) / bat_ms * 1e3:.0f} windows/s)")
+    from paper_2104_06800_amd.proposal import median_rel_error
+    keys = ("idepth", "rigid", "pose", "conf", "stats")
+    fixed_out = [{k: b[k].clone() for k in keys} for _, b, _ in items]
+    err_plain = [median_rel_error(b["idepth"].cpu().numpy(), w["idepth_gt"], ~w["dynamic"])
+                 for (_, b, _), w in zip(items, wins)]
+
+    def timed_batch(fn, reps=5):
+        out = []
+        for _ in range(reps):
+            reset()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            out.append((time.perf_counter() - t1) * 1e3)
+        return float(np.median(out))
+
+    # autotuned knobs per window shape (coordinate descent; results must not change)
+    from paper_2104_06800_amd import autotune
+    t0 = time.time()
+    space = dict(local_chains=(2, 4, 8), local_spec=(1, 2, 3), coarse_spec=(4, 6, 8))
+    table = {}
+    for w in wins:
+        table[autotune.bucket(w["params"])] = autotune.tune(lib, w, reps=2, space=space)
+    tune_s = time.time() - t0
+    lib.batch_run(batch, iters)                  # recapture with the tuned knobs
+    tuned_ms = timed_batch(lambda: lib.batch_run(batch, iters))
+    same = all(torch.equal(b[k], f[k]) for (_, b, _), f in zip(items, fixed_out) for k in keys)
+    ev2 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in items]
+    reset()
+    for (p, b, _), (e0, e1) in zip(items, ev2):
+        e0.record()
+        lib.run(p, b, iters=iters)
+        e1.record()
+    torch.cuda.synchronize()
+    per_tuned = np.array([e0.elapsed_time(e1) for e0, e1 in ev2])
+    for w in wins:
+        lib.set_knobs(w["params"], None)
+    log(f"batch: autotuned ({tune_s:.0f} s of tuning) batched graph {tuned_ms:.2f} ms against {bat_ms:.2f} ms "
+        f"fixed; sequential per-window sum {per_tuned.sum():.2f} against {per.sum():.2f} ms; results identical: {same}")
+    # learned start in the batch: the proposal network's start of every window, captured in
+    # the same graph, and fewer iterations
+    from paper_2104_06800_amd import proposal as pr
+    params, _ = pr.load(os.path.join(ROOT, "paper_2104_06800_amd", "weights", "proposal_n6.npz"))
+    net = lib.net_alloc(params)
+    learned = {}
+    for k_it in (iters, 8):
+        reset()
+        fbs = torch.zeros(len(items), dtype=torch.int32, device="cuda")
+        lib.batch_run_learned(net, batch, k_it, fallback=fbs)
+        l_ms = timed_batch(lambda: lib.batch_run_learned(net, batch, k_it, fallback=fbs))
+        errs = [median_rel_error(b["idepth"].cpu().numpy(), w["idepth_gt"], ~w["dynamic"])
+                for (_, b, _), w in zip(items, wins)]
+        learned[k_it] = {"batched_graph_ms": round(l_ms, 3), "windows_per_s": round(len(items) / l_ms * 1e3, 1),
+                         "median_window_error": round(float(np.median(errs)), 4),
+                         "fallbacks": int(fbs.sum().cpu())}
+        log(f"batch: learned start, {k_it} iterations: {l_ms:.2f} ms, median window error "
+            f"{np.median(errs):.4f} (plain {np.median(err_plain):.4f}), fallbacks {int(fbs.sum().cpu())}")
     return {"windows": len(items), "iters": iters, "pixel_frame_updates": px,
+            "autotuned": {"batched_graph_ms": round(tuned_ms, 3), "fixed_batched_graph_ms": round(bat_ms, 3),
+                          "sequential_sum_ms": round(float(per_tuned.sum()), 3),
+                          "fixed_sequential_sum_ms": round(float(per.sum()), 3),
+                          "results_identical": bool(same), "tuning_s": round(tune_s, 1),
+                          "buckets": len(table), "space": {k: list(v) for k, v in space.items()},
+                          "per_window_ms_sequential": {q: round(float(np.percentile(per_tuned, int(q[1:]))), 3)
+                                                       for q in ("p50", "p90", "p99")}},
+            "learned_start": {"median_window_error_plain": round(float(np.median(err_plain)), 4),
+                              **{f"iters_{k}": v for k, v in learned.items()}},
             "sequential_ms": round(seq_ms, 3), "batched_graph_ms": round(bat_ms, 3),
             "windows_per_s_sequential": round(len(items) / seq_ms * 1e3, 1),
             "windows_per_s_batched": round(len(items) / bat_ms * 1e3, 1),
@@ -356,8 +544,98 @@ def batch_workload(lib, np, torch, args, pool=True):
             "per_window_ms_sequential": {"p50": round(float(np.percentile(per, 50)), 3),
                                          "p90": round(float(np.percentile(per, 90)), 3),
                                          "p99": round(float(np.percentile(per, 99)), 3)},
-            "per_window_ms_batched": round(bat_ms, 3),
+            "per_window_ms_batched": {"p50": round(bat_ms, 3), "p90": round(bat_ms, 3), "p99": round(bat_ms, 3),
+                                      "note": "every window of a replay completes with its last launch"},
             "shapes": "W 320..1216, H 240..352 (steps of 16), N 3..8, odd windows with a depth prior"}
+
+
+def _psnr(rho, gt, static):
+    """Depth-map quality as in the paper's runtime / quality plot: PSNR of the inverse depth
+    against the ground truth over static pixels, after median scaling (monocular gauge).  The
+    peak is the ground truth's 99th-percentile inverse depth, and each pixel's error is
+    clipped at a tenth of it, so that the few gross outliers of moving-object boundaries do
+    not decide the figure."""
+    import numpy as np
+    ok = static & np.isfinite(rho) & (rho > 0)
+    s = np.median(gt[ok] / rho[ok])
+    peak = np.percentile(gt[ok], 99)
+    err = np.minimum(np.abs(rho[ok] * s - gt[ok]), 0.1 * peak)
+    return float(10 * np.log10(peak ** 2 / np.mean(err ** 2)))
+
+
+def hierarchy_sweep(lib, np, torch, w, reps=3):
+    """Runtime against depth quality over the hierarchy's settings on the benchmark window:
+    coarse stride s (s = 1: full-resolution lattice rows / columns, the global propagation
+    of the method the paper builds on) and local tile T.  Each setting runs the full
+    10-iteration window; its coarse passes and local passes are timed separately by the
+    library's timers in extra windows."""
+    from paper_2104_06800_amd.binding import TIMER_COARSE, TIMER_LOCAL
+    from paper_2104_06800_amd.proposal import median_rel_error
+    static = ~w["dynamic"]
+    out = []
+    for s, T in ((1, 256), (1, 32), (2, 32), (4, 16), (4, 32), (4, 64), (8, 32), (8, 64), (16, 64)):
+        p = dict(w["params"], coarse_stride=s, tile=T)
+        b = lib.alloc(p, w["flow"], w["pose_init"])
+        pose0 = b["pose"].clone()
+
+        def run():
+            b["pose"].copy_(pose0)
+            lib.run(p, b, iters=p["iters"])
+
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(reps):
+            e0.record()
+            run()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        lib.timing(True, timers=(TIMER_LOCAL, TIMER_COARSE))
+        run()
+        torch.cuda.synchronize()
+        coarse_ms, _ = lib.timing_read(TIMER_COARSE)
+        local_ms, _ = lib.timing_read(TIMER_LOCAL)
+        lib.timing(False)
+        rho = b["idepth"].cpu().numpy()
+        row = {"s": s, "T": T, "ms": round(float(np.median(ts)), 3), "coarse_ms": round(coarse_ms, 3),
+               "local_ms": round(local_ms, 3), "psnr_db": round(_psnr(rho, w["idepth_gt"], static), 2),
+               "median_static_rel_error": round(median_rel_error(rho, w["idepth_gt"], static), 4)}
+        log("hierarchy: " + json.dumps(row))
+        out.append(row)
+        del b
+    return out
+
+
+def vc_workload(lib, np, torch, w, b, reps=20):
+    """Visibility-coverage scores of the window's estimated inverse depth (confidence >= 0.5)
+    against its N frames' estimated poses and a keyframe pose, in one call, with the first
+    frame whose VC falls below tau_stride = 0.7."""
+    from paper_2104_06800_amd.binding import VC_OUT_LEN  # noqa: F401  (ABI constant present)
+    p = w["params"]
+    vp = dict(H=p["H"], W=p["W"], fx=p["fx"], fy=p["fy"], cx=p["cx"], cy=p["cy"], cell=8, conf_min=0.5)
+    poses = torch.cat([b["pose"], torch.tensor([[0.0, 0.03, 0.0, 0.2, 0.0, -12.0]], dtype=torch.float64,
+                                               device=b["pose"].device)]).contiguous()
+    out, first = lib.vc_scores(vp, b["idepth"], b["conf"], poses, 0.7)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lib.vc_scores(vp, b["idepth"], b["conf"], poses, 0.7)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    o = out.cpu().numpy()
+    n = poses.shape[0]
+    alg = p["H"] * p["W"] * 8          # inverse depth + confidence, read once for all poses
+    res = {"us_per_call": round(us, 2), "poses": n, "vc": [round(float(x), 4) for x in o[:, 2]],
+           "visibility": [round(float(x), 4) for x in o[:, 0]], "coverage": [round(float(x), 4) for x in o[:, 1]],
+           "first_below_tau_0.7": int(first.cpu()[0]), "cell": 8,
+           "algorithmic_GB_per_s": round(alg / (us * 1e-6) / 1e9, 1),
+           "workload": f"{p['W']}x{p['H']} GEM output against its {n - 1} frames and one keyframe"}
+    log("vc: " + json.dumps(res))
+    return res
 
 
 def learned_init(lib, np, torch):

@@ -63,18 +63,31 @@ typedef struct {
     float hmm_gamma;           /* rigidness-chain stay probability, in (0.5, 1]           */
     float idepth_min, idepth_max;  /* candidate inverse-depth range                       */
     float perturb_sigma0;      /* relative width of perturbation candidates at it 0,1     */
-    float prior_sigma_rel;     /* Eq. 3: sigma(rho^) = prior_sigma_rel * rho^             */
-    float prior_uniform_rel;   /* Eq. 3: U(rho^) = 1 / (prior_uniform_rel * rho^)         */
+    float prior_sigma_rel;     /* Eq. 3: sigma(rho^) = prior_sigma_rel * rho^ (model 1:   */
+                               /*   scale of the disparity residual law, px)              */
+    float prior_uniform_rel;   /* Eq. 3: U(rho^) = 1 / (prior_uniform_rel * rho^) (model  */
+                               /*   1: width of the outlier disparity range, px)          */
     float prior_inlier_default;/* prior weight where prior_weight is NULL                 */
     int32_t n_candidates;      /* K slots per pixel per pass, 3..64                       */
     int32_t coarse_stride;     /* s of the coarse lattice, >= 1                           */
     int32_t tile;              /* T of the local tiles: 8, 16, 32, 64, 128 or 256         */
     int32_t pose_gn_steps;     /* Gauss-Newton steps per frame in the pose step, >= 0     */
     int32_t chain_axis;        /* rigidness chains: 0 spatial (paper), 1 frame window     */
-    int32_t reserved0;
+    int32_t prior_model;       /* 0: Eq. 3's Gaussian-uniform mixture on inverse depth;   */
+                               /* 1: empirical residual model of external (stereo) priors */
+                               /*    (sec. III-A, after Eq. 5): the disparity residual    */
+                               /*    r = prior_disp_scale (rho^ - 1/phi_z) has inlier     */
+                               /*    density f_Fisk(|r|; prior_sigma_rel,                 */
+                               /*    prior_fisk_beta) / 2 and outlier density             */
+                               /*    1 / prior_uniform_rel                                */
     uint64_t seed;             /* Philox key                                              */
     uint32_t window_id;        /* Philox counter word 3                                   */
-    uint32_t reserved1;
+    float prior_disp_scale;    /* model 1: focal length times baseline (disparity / rho)  */
+    float prior_fisk_beta;     /* model 1: shape of the disparity residual law, in (0, 1] */
+    uint32_t init_random;      /* 0: the initial inverse depth starts from depth prior 0  */
+                               /*    wherever its transfer resolves (sec. III-A, priors   */
+                               /*    bootstrap the estimate), random elsewhere; 1: random */
+                               /*    everywhere.  Without priors the start is random.     */
 } voldor_window;
 
 /* Device buffers of one window.  Sizes: Hc x Wc from voldor_lattice_shape. */
@@ -402,6 +415,22 @@ typedef struct {
 int voldor_vc_scores(voldor_ctx ctx, const voldor_vc_params* vp, const float* idepth, const float* conf,
                      int n_poses, const double* poses, double tau, double* out, int32_t* first_below,
                      void* stream);
+
+/* 7-DoF keyframe alignment (sec. III-B: "we estimate both their relative motion T and scale
+ * factor s", optimised by Levenberg-Marquardt, Eq. 12): as voldor_align_p2p with the
+ * relative depth scale unknown too.  Map 1's geometry is scaled by s, so the plane of pixel
+ * l passes through s P1(l): r = rho1(l) <n(l), s P1(l) - Q_j> / (s Q_j,z), which is Eq. 9's
+ * 1/(s theta1) - 1/phi_z for a fronto-parallel plane.  Unknowns (left pose update,
+ * log s); ap->gn_steps evaluations, each of the trial step solving
+ * (H + lambda diag(H)) d = -g at the accepted state (lambda from 1e-4): a trial with a lower
+ * cost is accepted (lambda / 10), otherwise lambda * 10.  scale_inout [n] FP64 (start and
+ * result, > 0); cov_out [n][49] = H^-1 of (w, v, log s) at the accepted state; stats_out
+ * [n][4] = initial cost, final cost, final valid count, accepted steps; status_out as for
+ * voldor_align_p2p (ESINGULAR: the accepted state is kept, cov is NaN).  ap->scale_s is
+ * not used.  All device memory. */
+int voldor_align_sim3(voldor_ctx ctx, const voldor_align_params* ap, int n_pairs, const float* idepth1,
+                      const float* idepth2, const float* conf2, double* pose_inout, double* scale_inout,
+                      double* cov_out, double* stats_out, int32_t* status_out, void* stream);
 
 #ifdef __cplusplus
 }

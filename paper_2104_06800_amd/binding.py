@@ -36,8 +36,9 @@ class Window(ctypes.Structure):
                 ("prior_sigma_rel", ctypes.c_float), ("prior_uniform_rel", ctypes.c_float),
                 ("prior_inlier_default", ctypes.c_float),
                 ("n_candidates", ctypes.c_int32), ("coarse_stride", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("pose_gn_steps", ctypes.c_int32), ("chain_axis", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("window_id", ctypes.c_uint32), ("reserved1", ctypes.c_uint32)]
+                ("pose_gn_steps", ctypes.c_int32), ("chain_axis", ctypes.c_int32), ("prior_model", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("window_id", ctypes.c_uint32), ("prior_disp_scale", ctypes.c_float),
+                ("prior_fisk_beta", ctypes.c_float), ("init_random", ctypes.c_uint32)]
 
 
 class Buffers(ctypes.Structure):
@@ -65,7 +66,7 @@ EXPORTS = sorted(["voldor_ctx_create", "voldor_ctx_destroy", "voldor_last_error"
                   "voldor_net_refresh", "voldor_proposal_forward", "voldor_proposal_train_step",
                   "voldor_conv3x3_bf16", "voldor_conv3x3_bf16_backward",
                   "voldor_align_p2p", "voldor_vc_scores", "voldor_set_knobs", "voldor_get_knobs",
-                  "voldor_pose_sample"])
+                  "voldor_pose_sample", "voldor_align_sim3"])
 
 
 class Knobs(ctypes.Structure):
@@ -122,6 +123,7 @@ def load_library(path=LIB):
     lib.voldor_conv3x3_bf16.argtypes = [V, I, I, I, I, I, I, I, V, V, V, V, V, V, V]
     lib.voldor_conv3x3_bf16_backward.argtypes = [V, I, I, I, I, I, I, V, V, V, V, V, V, V]
     lib.voldor_align_p2p.argtypes = [V, P(AlignParams), I, V, V, V, V, V, V, V, V]
+    lib.voldor_align_sim3.argtypes = [V, P(AlignParams), I, V, V, V, V, V, V, V, V, V]
     lib.voldor_vc_scores.argtypes = [V, P(VcParams), V, V, I, V, ctypes.c_double, V, V, V]
     for n in EXPORTS:
         if n not in ("voldor_ctx_destroy", "voldor_last_error"):
@@ -140,11 +142,18 @@ def lattice_shape(H, W, stride):
     return hc.value, wc.value
 
 
+# window fields a parameter dict may leave out (the Gaussian-uniform prior model)
+OPTIONAL_WINDOW_FIELDS = dict(prior_model=0, prior_disp_scale=0.0, prior_fisk_beta=1.0, init_random=0)
+
+
 def make_window(p):
     """Window struct from a parameter dict (keys as in the struct)."""
     w = Window()
     for name, _ in Window._fields_:
         if name.startswith("reserved"):
+            continue
+        if name in OPTIONAL_WINDOW_FIELDS and name not in p:
+            setattr(w, name, OPTIONAL_WINDOW_FIELDS[name])
             continue
         setattr(w, name, p[name] if name != "seed" else int(p[name]) & 0xFFFFFFFFFFFFFFFF)
     return w
@@ -414,6 +423,27 @@ class Voldor:
         self._check(_LIB.voldor_align_p2p(self._h, ctypes.byref(a), n, _ptr(idepth1), _ptr(idepth2), _ptr(conf2),
                                           _ptr(pose_inout), _ptr(cov), _ptr(stats), _ptr(status),
                                           _stream(stream)), "voldor_align_p2p")
+        return cov, stats, status
+
+    def align_sim3(self, ap, idepth1, idepth2, conf2, pose_inout, scale_inout, stream=None):
+        """7-DoF alignment: pose_inout [n][6] and scale_inout [n] (FP64 device tensors) are
+        updated in place; returns (cov [n][49], stats [n][4], status [n])."""
+        n = idepth1.shape[0]
+        dev = idepth1.device
+        for t, dt in ((idepth1, torch.float32), (idepth2, torch.float32), (conf2, torch.float32),
+                      (pose_inout, torch.float64), (scale_inout, torch.float64)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise VoldorError("align inputs must be contiguous device tensors of the documented dtypes")
+        if tuple(idepth1.shape) != (n, ap["H"], ap["W"]) or idepth2.shape != idepth1.shape \
+                or conf2.shape != idepth1.shape or tuple(pose_inout.shape) != (n, 6) or tuple(scale_inout.shape) != (n,):
+            raise VoldorError("align input shapes disagree")
+        a = AlignParams(**{k: ap[k] for k, _ in AlignParams._fields_})
+        cov = torch.zeros((n, 49), dtype=torch.float64, device=dev)
+        stats = torch.zeros((n, 4), dtype=torch.float64, device=dev)
+        status = torch.zeros(n, dtype=torch.int32, device=dev)
+        self._check(_LIB.voldor_align_sim3(self._h, ctypes.byref(a), n, _ptr(idepth1), _ptr(idepth2), _ptr(conf2),
+                                           _ptr(pose_inout), _ptr(scale_inout), _ptr(cov), _ptr(stats), _ptr(status),
+                                           _stream(stream)), "voldor_align_sim3")
         return cov, stats, status
 
     def vc_scores(self, vp, idepth, conf, poses, tau, stream=None):

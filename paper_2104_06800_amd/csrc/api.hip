@@ -141,6 +141,11 @@ int check_window(voldor_ctx ctx, const voldor_window* w, const voldor_buffers* b
     if (w->P > 0 && (!(w->prior_sigma_rel > 0) || !(w->prior_uniform_rel > 0) ||
                      !(w->prior_inlier_default >= 0 && w->prior_inlier_default <= 1)))
         return fail(ctx, VOLDOR_EINVAL, "bad prior constants");
+    if (w->prior_model != 0 && w->prior_model != 1) return fail(ctx, VOLDOR_EINVAL, "prior_model must be 0 or 1");
+    if (w->init_random > 1) return fail(ctx, VOLDOR_EINVAL, "init_random must be 0 or 1");
+    if (w->P > 0 && w->prior_model == 1 &&
+        (!(w->prior_disp_scale > 0) || !(w->prior_fisk_beta > 0 && w->prior_fisk_beta <= 1)))
+        return fail(ctx, VOLDOR_EINVAL, "disparity prior model: need prior_disp_scale > 0 and prior_fisk_beta in (0, 1]");
     if (w->n_candidates < 3 || w->n_candidates > 64) return fail(ctx, VOLDOR_EINVAL, "n_candidates outside 3..64");
     int hc, wc;
     if (!lattice(w->H, w->W, w->coarse_stride, &hc, &wc)) return fail(ctx, VOLDOR_EINVAL, "bad coarse_stride");
@@ -154,6 +159,16 @@ int check_window(voldor_ctx ctx, const voldor_window* w, const voldor_buffers* b
         return fail(ctx, VOLDOR_EINVAL, "null buffer pointer");
     if (w->P > 0 && (!b->prior_idepth || !b->prior_pose)) return fail(ctx, VOLDOR_EINVAL, "null prior pointer");
     return VOLDOR_OK;
+}
+
+// the first depth prior, which the initial inverse depth starts from, or none
+vd::InitSrc boot_src(const voldor_window* v, const voldor_buffers* b) {
+    vd::InitSrc s{nullptr, nullptr};
+    if (v->P > 0 && !v->init_random) {
+        s.prior = b->prior_idepth;
+        s.pose = b->prior_pose;
+    }
+    return s;
 }
 
 vd::Win make_win(const voldor_window* v, int it, int level, const voldor_buffers* b = nullptr) {
@@ -185,6 +200,16 @@ vd::Win make_win(const voldor_window* v, int it, int level, const voldor_buffers
     w.key1 = (uint32_t)(v->seed >> 32);
     w.window_id = v->window_id;
     w.has_prior_weight = (b && v->P > 0 && b->prior_weight) ? 1 : 0;
+    w.prior_disp = (v->P > 0 && v->prior_model == 1) ? 1 : 0;
+    if (w.prior_disp) {
+        const double al = v->prior_sigma_rel, be = v->prior_fisk_beta, D = v->prior_uniform_rel;
+        w.disp_fb = v->prior_disp_scale;
+        w.disp_inv_alpha = (float)(1.0 / al);
+        w.disp_beta = (float)be;
+        w.disp_beta1 = be == 1.0;
+        w.disp_zfloor = be < 1.0 ? 1e-3f : 0.0f;
+        w.disp_c = (float)std::log2(2.0 * al / (be * D));
+    }
     return w;
 }
 
@@ -217,11 +242,17 @@ vd::LevelGeom make_geom(const voldor_window* v, const vd::Win& w, int level, int
     const int lines = g.horizontal ? g.h : g.w;
     g.nseg = (axis + g.seg - 1) / g.seg;
     g.nblocks = g.nseg * ((lines + g.C - 1) / g.C);
+    g.nchains = g.nseg * lines;
     // speculation depth of the chain scan: the coarse level's long chains carry a value over
     // many nodes, so it speculates deeper (phase A2 cost grows with the depth, misses shrink)
     g.spec = level == VOLDOR_LEVEL_COARSE ? (kn.coarse_spec > 0 ? kn.coarse_spec : VD_SPEC)
                                           : (kn.local_spec > 0 ? kn.local_spec : 2);
     g.pa_lanes = kn.coarse_lanes > 0 ? kn.coarse_lanes : VD_PA_LANES;
+    g.nf = std::max(v->N, 3);
+    g.ncost = 0;
+    // a long chain (coarse stride 1 on a wide image) speculates less deep if its block would
+    // not fit the LDS; the speculation depth never changes a result
+    while (g.spec > 1 && vd::level_lds_bytes(g) > kLevelLdsMax) --g.spec;
     // a fused local pass keeps its E-step frame costs when there are no priors and the
     // block still fits 5 per CU (32 KB of the 160 KB LDS)
     g.ncost = 0;
@@ -240,10 +271,10 @@ struct GemLaunch {
     Scratch s;
     double* ll_partial;
     double* pose_partials;
-    float* pa_E;          // coarse-level phase-A results [Hc*Wc]
+    double* pa_E;         // coarse-level phase-A results [Hc*Wc]
     float* pa_V;
     int* pa_S;
-    float* pa_spec;       // [VD_SPEC][Hc*Wc]
+    double* pa_spec;      // [VD_SPEC][Hc*Wc]
     float4* flow2;        // [N][H][W] row-pair layout of the flows
     vd::PoseD* hist;      // pose history of a pose step
     float2* obs;          // [H][W] observed displacements
@@ -261,7 +292,10 @@ size_t gem_layout(const voldor_window* v, int n_cand, GemLaunch& L) {
     vd::Win w0 = make_win(v, 0, 1);
     int mx = 0;
     for (int lvl = 0; lvl < 2; ++lvl)
-        for (int d = 0; d < 2; ++d) mx = std::max(mx, make_geom(v, w0, lvl, d, L.kn).nblocks);
+        for (int d = 0; d < 2; ++d) {
+            const vd::LevelGeom g = make_geom(v, w0, lvl, d, L.kn);
+            mx = std::max(mx, std::max(g.nblocks, g.nchains));
+        }
     L.max_level_blocks = mx;
     const int64_t npix = (int64_t)v->H * v->W;
     // ~4 pixels per thread: enough blocks to fill the chip, few partial records
@@ -276,7 +310,7 @@ size_t gem_layout(const voldor_window* v, int n_cand, GemLaunch& L) {
     const size_t fin_bytes = align_up(sizeof(double) * 5 * (size_t)fin_blocks);
     const size_t gnp_bytes = align_up(sizeof(double) * 29 * 2 * (size_t)L.gn_blocks);
     L.sz.red = std::max(std::max(pp_bytes, fin_bytes), gnp_bytes);
-    L.sz.pa = align_up(sizeof(float) * (size_t)w0.hc * w0.wc);
+    L.sz.pa = align_up(sizeof(double) * (size_t)w0.hc * w0.wc);
     L.sz.f2 = align_up(sizeof(float4) * (size_t)npix * v->N);
     L.sz.hist = align_up(sizeof(vd::PoseD) * (size_t)v->N * std::max(1, v->pose_gn_steps));
     L.sz.obs = align_up(sizeof(float2) * (size_t)npix);
@@ -299,10 +333,10 @@ void gem_carve(char* base, GemLaunch& L) {
     p += L.sz.ll;
     L.pose_partials = (double*)p;
     p += L.sz.red;
-    L.pa_E = (float*)p;
+    L.pa_E = (double*)p;
     L.pa_V = (float*)(p + L.sz.pa);
     L.pa_S = (int*)(p + 2 * L.sz.pa);
-    L.pa_spec = (float*)(p + 3 * L.sz.pa);
+    L.pa_spec = (double*)(p + 3 * L.sz.pa);
 }
 
 int gem_prepare(voldor_ctx ctx, const voldor_window* v, const voldor_buffers* b, hipStream_t st, GemLaunch& L,
@@ -428,7 +462,7 @@ int run_finalize(GemLaunch& L, int iter) {
     const vd::Win w = make_win(L.v, iter, 1, L.b);
     const vd::LevelGeom g = make_geom(L.v, w, 1, iter, L.kn);
     const vd::FinalBufs B = final_bufs(L);
-    VD_CHECK(vd::launch_finalize(w, B, g.nblocks, L.st), "finalize launch");
+    VD_CHECK(vd::launch_finalize(w, B, g.nchains, L.st), "finalize launch");
     return VOLDOR_OK;
 }
 
@@ -448,7 +482,8 @@ int run_iteration(GemLaunch& L, int it, bool first) {
 int run_window(GemLaunch& L, int first, int n_iters, int flags) {
     voldor_ctx ctx = L.ctx;
     int rc;
-    if (flags & VOLDOR_RUN_INIT) VD_CHECK(vd::launch_init(make_win(L.v, 0, 1), L.b->idepth, L.st), "init launch");
+    if (flags & VOLDOR_RUN_INIT)
+        VD_CHECK(vd::launch_init(make_win(L.v, 0, 1), L.b->idepth, boot_src(L.v, L.b), L.st), "init launch");
     for (int it = first; it < first + n_iters; ++it)
         if ((rc = run_iteration(L, it, it == first))) return rc;
     return run_finalize(L, first + n_iters - 1);
@@ -543,6 +578,7 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
             it.flow2 = L.flow2;
             it.N = L.v->N;
             it.init = (flags & VOLDOR_RUN_INIT) ? 1 : 0;
+            it.boot = boot_src(L.v, L.b);
             const int64_t npix = (int64_t)L.v->H * L.v->W;
             const int64_t pairs = (int64_t)(L.v->H - 1) * L.v->W * (L.v->N - 1);
             it.nblocks = (int)((std::max(npix, pairs) + VD_BLOCK - 1) / VD_BLOCK);
@@ -645,7 +681,7 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
         std::memset(&x, 0, sizeof(x));
         x.w = make_win(L.v, last, VOLDOR_LEVEL_LOCAL, L.b);
         x.b = final_bufs(L);
-        x.n_ll = make_geom(L.v, x.w, VOLDOR_LEVEL_LOCAL, last, L.kn).nblocks;
+        x.n_ll = make_geom(L.v, x.w, VOLDOR_LEVEL_LOCAL, last, L.kn).nchains;
         x.nblocks = (int)(((int64_t)L.v->H * L.v->W + VD_BLOCK - 1) / VD_BLOCK);
         fin_all.push_back(x);
     }
@@ -804,7 +840,7 @@ int voldor_init_idepth(voldor_ctx ctx, const voldor_window* v, const voldor_buff
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
-    VD_CHECK(vd::launch_init(make_win(v, 0, 1), b->idepth, st), "init launch");
+    VD_CHECK(vd::launch_init(make_win(v, 0, 1), b->idepth, boot_src(v, b), st), "init launch");
     return VOLDOR_OK;
 }
 
@@ -1035,7 +1071,7 @@ int batch_run_impl(voldor_ctx ctx, const voldor_net* net, int n_windows, const v
                                                 b.idepth, b.rigid, &flag, s);
                     if (r) return r;
                 }
-                VD_CHECK(vd::launch_init_if(make_win(&v, 0, 1), b.idepth, flag, fo, s), "start launch");
+                VD_CHECK(vd::launch_init_if(make_win(&v, 0, 1), b.idepth, boot_src(&v, &b), flag, fo, s), "start launch");
             }
         }
         return enqueue_plan(ctx, plan, tables, s);
@@ -1083,7 +1119,7 @@ int voldor_proposal_start(voldor_ctx ctx, const voldor_net* net, const voldor_wi
     if ((rc = vdc::proposal_start(ctx, net, v->H, v->W, v->N, b->flow, b->pose, v->idepth_min, v->idepth_max,
                                   b->idepth, b->rigid, &flag, st)))
         return rc;
-    VD_CHECK(vd::launch_init_if(make_win(v, 0, 1), b->idepth, flag, fallback_out, st), "fallback launch");
+    VD_CHECK(vd::launch_init_if(make_win(v, 0, 1), b->idepth, boot_src(v, b), flag, fallback_out, st), "fallback launch");
     return VOLDOR_OK;
 }
 
@@ -1210,6 +1246,7 @@ int voldor_vc_scores(voldor_ctx ctx, const voldor_vc_params* vp, const float* id
     a.fx = vp->fx; a.fy = vp->fy; a.cx = vp->cx; a.cy = vp->cy;
     a.conf_min = vp->conf_min;
     a.tau = tau;
+    a.lds_bits = (size_t)a.words * n_poses <= 8192;   // up to 32 KB of LDS bitmaps per block
     const size_t rt_bytes = align_up(sizeof(double) * 12 * (size_t)n_poses);
     const size_t cnt_bytes = align_up(sizeof(uint32_t) * (size_t)(n_poses + 1));
     const size_t bit_bytes = align_up(sizeof(uint32_t) * (size_t)a.words * n_poses);
@@ -1223,6 +1260,49 @@ int voldor_vc_scores(voldor_ctx ctx, const voldor_vc_params* vp, const float* id
     B.bits = (uint32_t*)(base + rt_bytes + cnt_bytes);
     B.out = out; B.first_below = first_below;
     VD_CHECK(vd::launch_vc(a, B, st), "visibility-coverage launch");
+    return VOLDOR_OK;
+}
+
+int voldor_align_sim3(voldor_ctx ctx, const voldor_align_params* ap, int n_pairs, const float* idepth1,
+                      const float* idepth2, const float* conf2, double* pose_inout, double* scale_inout,
+                      double* cov_out, double* stats_out, int32_t* status_out, void* stream) {
+    if (!ctx) return VOLDOR_EINVAL;
+    if (!ap) return fail(ctx, VOLDOR_EINVAL, "null params");
+    if (n_pairs < 0 || n_pairs > (int)kMaxBatch) return fail(ctx, VOLDOR_EINVAL, "n_pairs outside 0..%zu", kMaxBatch);
+    if (n_pairs == 0) return VOLDOR_OK;
+    if (ap->H < 3 || ap->W < 3 || (int64_t)ap->H * ap->W > (1 << 28)) return fail(ctx, VOLDOR_EINVAL, "bad image size");
+    if (!(ap->fx > 0) || !(ap->fy > 0)) return fail(ctx, VOLDOR_EINVAL, "bad intrinsics");
+    if (ap->robust != 0 && ap->robust != 1) return fail(ctx, VOLDOR_EINVAL, "robust must be 0 or 1");
+    if (!(ap->robust_scale > 0) || !(ap->normal_disc_rel > 0))
+        return fail(ctx, VOLDOR_EINVAL, "robust_scale and normal_disc_rel must be > 0");
+    if (ap->gn_steps < 0 || ap->gn_steps > 1000) return fail(ctx, VOLDOR_EINVAL, "gn_steps outside 0..1000");
+    if (!idepth1 || !idepth2 || !conf2 || !pose_inout || !scale_inout || !cov_out || !stats_out || !status_out)
+        return fail(ctx, VOLDOR_EINVAL, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t plane = (size_t)ap->H * ap->W;
+    const int nblk = (int)std::min<size_t>(std::max<size_t>(1, (plane + VD_BLOCK * 4 - 1) / (VD_BLOCK * 4)), 512);
+    const size_t nrm_bytes = align_up(sizeof(float4) * plane * n_pairs);
+    const size_t part_bytes = align_up(sizeof(double) * 37 * nblk * (size_t)n_pairs);
+    const size_t state_bytes = align_up(sizeof(double) * vd::sim3_state_doubles(n_pairs));
+    int rc = vdc::ensure_buffer(ctx, &ctx->scratch, &ctx->scratch_bytes, nrm_bytes + part_bytes + state_bytes, st);
+    if (rc) return rc;
+    char* base = (char*)ctx->scratch;
+    vd::AlignArgs a;
+    a.H = ap->H; a.W = ap->W;
+    a.fx = ap->fx; a.fy = ap->fy; a.cx = ap->cx; a.cy = ap->cy;
+    a.ifx = (float)(1.0 / (double)ap->fx);
+    a.ify = (float)(1.0 / (double)ap->fy);
+    a.robust = ap->robust; a.scale = ap->robust_scale; a.disc = ap->normal_disc_rel; a.s = 1.0f;
+    a.n_pairs = n_pairs;
+    vd::AlignBufs B;
+    B.idepth1 = idepth1; B.idepth2 = idepth2; B.conf2 = conf2;
+    B.normals = (float4*)base;
+    B.partials = (double*)(base + nrm_bytes);
+    B.pose = pose_inout; B.cov = cov_out; B.stats = stats_out; B.status = status_out;
+    double* state = (double*)(base + nrm_bytes + part_bytes);
+    VD_CHECK(vd::launch_align_prepare(a, B, st), "align prepare launch");
+    VD_CHECK(vd::launch_align_sim3(a, B, scale_inout, state, ap->gn_steps, nblk, st), "sim(3) alignment launch");
     return VOLDOR_OK;
 }
 

@@ -70,6 +70,14 @@ struct Win {
     int chain_axis;
     uint32_t key0, key1, window_id;
     int has_prior_weight;
+    // empirical disparity model of the priors (prior_model 1): residual r = fb (rho^ - 1/phi_z)
+    int prior_disp;
+    float disp_fb;        // focal length times baseline
+    float disp_inv_alpha; // 1 / log-logistic scale (px)
+    float disp_beta;      // log-logistic shape, in (0, 1]
+    int disp_beta1;       // shape 1 (fast path)
+    float disp_zfloor;    // floor of |r| / alpha (shape < 1: the density diverges at 0)
+    float disp_c;         // log2(2 alpha / (beta D)), D the outlier disparity range
 };
 
 // ----------------------------------------------------------------------------------
@@ -446,8 +454,19 @@ __device__ __forceinline__ bool prior_z(const Win& w, const PoseF* __restrict__ 
         inv_phi = rho * iz;
     }
     if (!(rh > 0.f) || !isfinite(rh)) return false;
-    z = (rh - inv_phi) * rcp(w.csig * rh);
+    z = w.prior_disp ? w.disp_fb * (rh - inv_phi) : (rh - inv_phi) * rcp(w.csig * rh);
     return true;
+}
+
+// log2(p0 / p1) of a prior term with a valid transfer: Eq. 3's Gaussian-uniform mixture (z the
+// inverse-depth difference in units of sigma), or the empirical log-logistic law of the
+// disparity residual (z = fb (rho^ - 1/phi_z) px): p1 = f_Fisk(|z|) / 2, p0 = 1 / D
+__device__ __forceinline__ float prior_log2_ratio(const Win& w, float z) {
+    if (!w.prior_disp) return fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa);
+    const float a = fmaxf(fabsf(z) * w.disp_inv_alpha, w.disp_zfloor);
+    if (w.disp_beta1) return fmaf(2.f, log2f_fast(1.f + a), w.disp_c);
+    const float la = log2f_fast(a);
+    return fmaf(2.f, log2f_fast(1.f + exp2f_fast(w.disp_beta * la)), fmaf(1.f - w.disp_beta, la, w.disp_c));
 }
 
 // Per-frame flow residuals of candidate rho, frames in order: f(t, r^2, valid).
@@ -488,13 +507,24 @@ __device__ __forceinline__ void frame_residuals(const Win& w, const PoseF* __res
     }
 }
 
+// Energies are sums of FP32 terms (weight times cost factor) accumulated in FP64: with an
+// FP32 sum, candidates whose energies differ by less than the sum's rounding tie, and ties go
+// to the lowest slot (the current value), which holds values in place that an exact sum
+// would move.  The product of two FP32 numbers is exact in FP64, so each step is one FP64
+// FMA, the same in every phase (phase A, the speculative energies, the scan), bit for bit.
+typedef double energy_t;
+
+__device__ __forceinline__ energy_t eacc(float q, float cost, energy_t E) {
+    return fma((double)q, (double)cost, E);
+}
+
 // E_j(rho) in log2 units: sum_t q_t cost_t + sum_k q^_k cost^_k.  PR: window has priors.
 template <bool B2, bool PR>
-__device__ __forceinline__ float energy2(const Win& w, const PoseF* __restrict__ P, const float4* __restrict__ flow2,
-                                         const float* __restrict__ prior, const Pix& c, float rho) {
-    float E = 0.f;
+__device__ __forceinline__ energy_t energy2(const Win& w, const PoseF* __restrict__ P, const float4* __restrict__ flow2,
+                                            const float* __restrict__ prior, const Pix& c, float rho) {
+    energy_t E = 0.0;
     frame_residuals(w, P, flow2, c, rho, [&](int t, float r2, bool ok) {
-        E = fmaf(c.q[t], ok ? flow_cost2<B2>(w, r2) : 1.0f, E);
+        E = eacc(c.q[t], ok ? flow_cost2<B2>(w, r2) : 1.0f, E);
     });
     if (!PR) return E;
 #pragma unroll
@@ -502,8 +532,8 @@ __device__ __forceinline__ float energy2(const Win& w, const PoseF* __restrict__
         if (k < w.P && c.qh[k] > 0.f) {
             float z;
             const float cost = prior_z(w, P, prior, c, k, rho, z)
-                             ? softplus2(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)) : 1.0f;
-            E = fmaf(c.qh[k], cost, E);
+                             ? softplus2(prior_log2_ratio(w, z)) : 1.0f;
+            E = eacc(c.qh[k], cost, E);
         }
     }
     return E;
@@ -512,20 +542,21 @@ __device__ __forceinline__ float energy2(const Win& w, const PoseF* __restrict__
 // E_j(rho) from frame cost factors already evaluated at rho (cost[t * step], as energy2
 // forms them): the same FMAs in the same order as energy2, so the same value bit for bit.
 template <bool PR>
-__device__ __forceinline__ float energy2_costs(const Win& w, const PoseF* __restrict__ P, const float* __restrict__ prior,
-                                               const Pix& c, float rho, const float* cost, int step) {
-    float E = 0.f;
+__device__ __forceinline__ energy_t energy2_costs(const Win& w, const PoseF* __restrict__ P,
+                                                  const float* __restrict__ prior, const Pix& c, float rho,
+                                                  const float* cost, int step) {
+    energy_t E = 0.0;
 #pragma unroll
     for (int t = 0; t < VD_NMAX; ++t)
-        if (t < w.N) E = fmaf(c.q[t], cost[t * step], E);
+        if (t < w.N) E = eacc(c.q[t], cost[t * step], E);
     if (!PR) return E;
 #pragma unroll
     for (int k = 0; k < VD_PMAX; ++k) {
         if (k < w.P && c.qh[k] > 0.f) {
             float z;
             const float cost_k = prior_z(w, P, prior, c, k, rho, z)
-                               ? softplus2(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)) : 1.0f;
-            E = fmaf(c.qh[k], cost_k, E);
+                               ? softplus2(prior_log2_ratio(w, z)) : 1.0f;
+            E = eacc(c.qh[k], cost_k, E);
         }
     }
     return E;
@@ -571,43 +602,43 @@ __device__ __forceinline__ float frame_cost(const Win& w, const PoseF* __restric
 
 // E plus the prior terms of E_j(rho) in prior order (the tail of energy2 / energy2_lanes)
 template <bool PR>
-__device__ __forceinline__ float prior_terms(const Win& w, const PoseF* __restrict__ P, const float* __restrict__ prior,
-                                             const Pix& c, float rho, float E) {
+__device__ __forceinline__ energy_t prior_terms(const Win& w, const PoseF* __restrict__ P,
+                                                const float* __restrict__ prior, const Pix& c, float rho, energy_t E) {
     if (!PR) return E;
 #pragma unroll
     for (int k = 0; k < VD_PMAX; ++k) {
         if (k < w.P && c.qh[k] > 0.f) {
             float z;
             const float cost = prior_z(w, P, prior, c, k, rho, z)
-                             ? softplus2(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)) : 1.0f;
-            E = fmaf(c.qh[k], cost, E);
+                             ? softplus2(prior_log2_ratio(w, z)) : 1.0f;
+            E = eacc(c.qh[k], cost, E);
         }
     }
     return E;
 }
 
 template <bool B2, bool PR>
-__device__ __forceinline__ float energy2_lanes(const Win& w, const PoseF* __restrict__ P,
-                                               const float4* __restrict__ flow2, const float* __restrict__ prior,
-                                               const Pix& c, float rho, int hl, int hbase) {
+__device__ __forceinline__ energy_t energy2_lanes(const Win& w, const PoseF* __restrict__ P,
+                                                  const float4* __restrict__ flow2, const float* __restrict__ prior,
+                                                  const Pix& c, float rho, int hl, int hbase) {
     const float mine = hl < w.N ? frame_cost<B2>(w, P, flow2, c, rho, hl) : 0.f;
-    float E = 0.f;
+    energy_t E = 0.0;
 #pragma unroll
     for (int t = 0; t < VD_NMAX; ++t)
-        if (t < w.N) E = fmaf(c.q[t], __shfl(mine, hbase + t), E);
+        if (t < w.N) E = eacc(c.q[t], __shfl(mine, hbase + t), E);
     return prior_terms<PR>(w, P, prior, c, rho, E);
 }
 
-// E_j(rho) with pruning: all terms are non-negative and the FP32 running sum only grows, so
+// E_j(rho) with pruning: all terms are non-negative and the FP64 running sum only grows, so
 // once it passes `bound` the candidate cannot win and the remaining frames (and their flow
 // gathers) are skipped.  STRICT: stop when E > bound (callers that keep ties), otherwise
 // when E >= bound.  A pruned result is a partial sum on the losing side of the bound, so
 // every comparison against the bound is decided exactly as with the full sum.
 template <bool B2, bool PR, bool STRICT>
-__device__ __forceinline__ float energy2_bounded(const Win& w, const PoseF* __restrict__ P,
-                                                 const float4* __restrict__ flow2, const float* __restrict__ prior,
-                                                 const Pix& c, float rho, float bound) {
-    float E = 0.f;
+__device__ __forceinline__ energy_t energy2_bounded(const Win& w, const PoseF* __restrict__ P,
+                                                    const float4* __restrict__ flow2, const float* __restrict__ prior,
+                                                    const Pix& c, float rho, energy_t bound) {
+    energy_t E = 0.0;
     float dpx = 0.f, dpy = 0.f;
     bool zprev = true;
     const size_t plane = (size_t)w.H * w.W;
@@ -632,7 +663,7 @@ __device__ __forceinline__ float energy2_bounded(const Win& w, const PoseF* __re
         }
         const bool ok = zprev && zok && fok;
         const float ex = (dx - dpx) - fx, ey = (dy - dpy) - fy;
-        E = fmaf(c.q[t], ok ? flow_cost2<B2>(w, fmaf(ex, ex, ey * ey)) : 1.0f, E);
+        E = eacc(c.q[t], ok ? flow_cost2<B2>(w, fmaf(ex, ex, ey * ey)) : 1.0f, E);
         if (STRICT ? (E > bound) : (E >= bound)) return E;
         dpx = dx; dpy = dy; zprev = zok;
     }
@@ -642,8 +673,8 @@ __device__ __forceinline__ float energy2_bounded(const Win& w, const PoseF* __re
         if (k < w.P && c.qh[k] > 0.f) {
             float z;
             const float cost = prior_z(w, P, prior, c, k, rho, z)
-                             ? softplus2(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)) : 1.0f;
-            E = fmaf(c.qh[k], cost, E);
+                             ? softplus2(prior_log2_ratio(w, z)) : 1.0f;
+            E = eacc(c.qh[k], cost, E);
         }
     }
     return E;
@@ -657,12 +688,12 @@ __device__ __forceinline__ float energy2_bounded(const Win& w, const PoseF* __re
 template <bool B2, bool PR, int M>
 __device__ __forceinline__ void energy2_bounded_m(const Win& w, const PoseF* __restrict__ P,
                                                   const float4* __restrict__ flow2, const float* __restrict__ prior,
-                                                  const Pix& c, const float* rho, unsigned live, float bound,
-                                                  float* E) {
+                                                  const Pix& c, const float* rho, unsigned live, energy_t bound,
+                                                  energy_t* E) {
     float dpx[M], dpy[M];
     bool zprev[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) { E[m] = 0.f; dpx[m] = 0.f; dpy[m] = 0.f; zprev[m] = true; }
+    for (int m = 0; m < M; ++m) { E[m] = 0.0; dpx[m] = 0.f; dpy[m] = 0.f; zprev[m] = true; }
     const size_t plane = (size_t)w.H * w.W;
 #pragma unroll
     for (int t = 0; t < VD_NMAX; ++t) {
@@ -693,7 +724,7 @@ __device__ __forceinline__ void energy2_bounded_m(const Win& w, const PoseF* __r
             if ((live >> m) & 1u) {
                 const bool ok = zprev[m] && zok[m] && fok[m];
                 const float ex = (dx[m] - dpx[m]) - fx[m], ey = (dy[m] - dpy[m]) - fy[m];
-                E[m] = fmaf(c.q[t], ok ? flow_cost2<B2>(w, fmaf(ex, ex, ey * ey)) : 1.0f, E[m]);
+                E[m] = eacc(c.q[t], ok ? flow_cost2<B2>(w, fmaf(ex, ex, ey * ey)) : 1.0f, E[m]);
                 if (E[m] >= bound) live &= ~(1u << m);
             }
             dpx[m] = dx[m]; dpy[m] = dy[m]; zprev[m] = zok[m];
@@ -709,8 +740,8 @@ __device__ __forceinline__ void energy2_bounded_m(const Win& w, const PoseF* __r
             if (k < w.P && c.qh[k] > 0.f) {
                 float z;
                 const float cost = prior_z(w, P, prior, c, k, rho[m], z)
-                                 ? softplus2(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)) : 1.0f;
-                E[m] = fmaf(c.qh[k], cost, E[m]);
+                                 ? softplus2(prior_log2_ratio(w, z)) : 1.0f;
+                E[m] = eacc(c.qh[k], cost, E[m]);
             }
         }
     }
@@ -736,7 +767,7 @@ __device__ __forceinline__ int prior_posteriors(const Win& w, const PoseF* __res
                 const float pw = w.has_prior_weight ? pweight[k * plane + pix] : w.pi_default;
                 if (pw > 0.f) {
                     const float odds = (1.f - pw) / pw;
-                    c.qh[k] = rcp(fmaf(odds, exp2f_fast(fmaf(0.5f * VD_LOG2E * z, z, w.log2kappa)), 1.f));
+                    c.qh[k] = rcp(fmaf(odds, exp2f_fast(prior_log2_ratio(w, z)), 1.f));
                 }
             }
         }

@@ -25,27 +25,65 @@ __global__ void k_pose_prep(const double* __restrict__ pose, int N, const double
 }
 
 // ----------------------------------------------------------------------------------
-// random initial inverse depth
+// initial inverse depth: random, or read off the first depth prior
 // ----------------------------------------------------------------------------------
-__device__ __forceinline__ void init_body(const Win& w, float* __restrict__ idepth, int blk) {
+// The inverse depth of pixel j whose transfer into prior 0's camera meets the prior at the
+// pixel l it lands on (sec. III-A, priors bootstrap the estimate): R x~ / rho + t has depth
+// a / rho + t_z with a = r_3 . x~, so 1 / phi_z = rho^(l) gives rho = rho^(l) a / (1 - rho^(l) t_z).
+// l depends on rho: two fixed-point rounds from the prior's value at j (the first is exact
+// for an identity pose).  FP64 throughout so that the nearest-pixel choices are the exact
+// arithmetic's.  False where a round leaves the image, lands behind the camera, or meets a
+// hole or a non-positive solution.
+__device__ inline bool prior_boot(const Win& w, InitSrc s, int j, double& out) {
+    double R[9];
+    exp_so3(s.pose, R);
+    const int x = j % w.W, y = j / w.W;
+    const double fx = w.fx, fy = w.fy, cx = w.cx, cy = w.cy;
+    const double rx = ((double)x - cx) / fx, ry = ((double)y - cy) / fy;
+    const double a = R[6] * rx + R[7] * ry + R[8];
+    double rho = s.prior[j];
+    if (!(rho > 0.0) || !isfinite(rho)) return false;
+    for (int r = 0; r < 2; ++r) {
+        const double ir = 1.0 / rho;
+        const double qx = (R[0] * rx + R[1] * ry + R[2]) * ir + s.pose[3];
+        const double qy = (R[3] * rx + R[4] * ry + R[5]) * ir + s.pose[4];
+        const double qz = a * ir + s.pose[5];
+        if (!(qz > 0.0)) return false;
+        const double lx = floor(fx * qx / qz + cx + 0.5), ly = floor(fy * qy / qz + cy + 0.5);
+        if (!(lx >= 0.0 && lx <= (double)(w.W - 1) && ly >= 0.0 && ly <= (double)(w.H - 1))) return false;
+        const double rh = s.prior[(int)ly * w.W + (int)lx];
+        const double den = 1.0 - rh * s.pose[5];
+        if (!(rh > 0.0) || !isfinite(rh) || !(den > 0.0) || !(a > 0.0)) return false;
+        rho = rh * a / den;
+    }
+    out = rho;
+    return true;
+}
+
+__device__ __forceinline__ void init_body(const Win& w, float* __restrict__ idepth, InitSrc s, int blk) {
     const int j = blk * VD_BLOCK + threadIdx.x;
     if (j >= w.H * w.W) return;
+    double b;
+    if (s.prior && prior_boot(w, s, j, b)) {
+        idepth[j] = (float)fmin(fmax(b, (double)w.rmin), (double)w.rmax);
+        return;
+    }
     const uint4 r = philox10(make_uint4((uint32_t)j, 0u, philox_word2(0, 1, PURPOSE_INIT), w.window_id),
                              w.key0, w.key1);
     idepth[j] = fmaf(unit24(r.x), w.rmax - w.rmin, w.rmin);
 }
 
-__global__ void __launch_bounds__(VD_BLOCK) k_init_idepth(Win w, float* __restrict__ idepth) {
-    init_body(w, idepth, blockIdx.x);
+__global__ void __launch_bounds__(VD_BLOCK) k_init_idepth(Win w, float* __restrict__ idepth, InitSrc s) {
+    init_body(w, idepth, s, blockIdx.x);
 }
 
-// the random start where a learned start raised its fallback flag (always without a flag);
-// the flag is copied out
+// the start where a learned start raised its fallback flag (always without a flag); the flag
+// is copied out
 __global__ void __launch_bounds__(VD_BLOCK)
-k_init_idepth_if(Win w, float* __restrict__ idepth, const int* __restrict__ flag, int32_t* __restrict__ out) {
+k_init_idepth_if(Win w, float* __restrict__ idepth, InitSrc s, const int* __restrict__ flag, int32_t* __restrict__ out) {
     const int f = flag ? *flag : 1;
     if (out && blockIdx.x == 0 && threadIdx.x == 0) *out = f;
-    if (f) init_body(w, idepth, blockIdx.x);
+    if (f) init_body(w, idepth, s, blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------------
@@ -236,12 +274,13 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                                            int blk, float* lds) {
     const int stride = g.seg + 1;
     const int nodes = g.C * stride;
-    float* q_s = lds;                       // [N][C][stride] emission ratios -> alpha -> q
-    float* r_s = q_s + VD_NMAX * nodes;     // [N][C][stride] emission ratios (E-step)
-    float* bestE = r_s + VD_NMAX * nodes;   // [C][stride]
-    float* bestV = bestE + nodes;
-    float* specE = bestV + nodes;           // [spec][C][stride]
-    float* rcur = specE + g.spec * nodes;
+    const int nf = g.nf;
+    energy_t* bestE = (energy_t*)lds;       // [C][stride]
+    energy_t* specE = bestE + nodes;        // [spec][C][stride]
+    float* q_s = (float*)(specE + g.spec * nodes);   // [N][C][stride] emission ratios -> alpha -> q
+    float* r_s = q_s + nf * nodes;          // [N][C][stride] emission ratios (E-step)
+    float* bestV = r_s + nf * nodes;
+    float* rcur = bestV + nodes;
     float* newV = rcur + nodes;
     int* bestS = (int*)(newV + nodes);
     float* cost_s = (float*)(bestS + nodes);  // [ncost][C][stride] E-step frame costs at rho
@@ -249,6 +288,8 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
     // a fused pass keeps the E-step's frame costs at the current value: the M-step's slot-0
     // energy is then their q-weighted sum, with no flow gathers
     const bool keep_cost = do_e && do_m == 1 && g.ncost > 0;
+    // per-chain log-likelihood terms of an E-only pass, over the M-step arrays (unused there)
+    double* llc = bestE;
 
     const int tid = threadIdx.x;
     const int npix = g.C * g.seg;
@@ -304,7 +345,9 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                         q_s[t * nodes + o] = num * rcp(fmaf(1.f - al[t], 1.f - b1, num));
                     }
                 }
-                ll += (double)(logc * VD_LN2) + (double)w.N * (double)w.ln_L0;
+                const double llv = (double)(logc * VD_LN2) + (double)w.N * (double)w.ln_L0;
+                if constexpr (LC) ll += llv;
+                else if (B.ll_partial) llc[o] = llv;
             }
         }
         __syncthreads();
@@ -339,7 +382,7 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                     const float num = ai * b1;
                     a[i] = num * rcp(fmaf(1.f - ai, 1.f - b1, num));
                 }
-                ll += (double)(logc * VD_LN2) + (double)L * (double)w.ln_L0;
+                if (B.ll_partial) llc[c * VD_NMAX + t] = (double)(logc * VD_LN2) + (double)L * (double)w.ln_L0;
             }
         }
         __syncthreads();
@@ -351,14 +394,31 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             for (int t = 0; t < w.N; ++t) B.q_out[t * lplane + p.li] = q_s[t * nodes + o];
         }
         if (B.ll_partial) {
-            // block sum of chain log-likelihoods, fixed order
-            for (int off = 32; off > 0; off >>= 1) ll += __shfl_xor(ll, off);
-            if ((tid & 63) == 0) ll_red[tid >> 6] = ll;
-            __syncthreads();
-            if (tid == 0) {
-                double s = 0.0;
-                for (int i = 0; i < VD_BLOCK / 64; ++i) s += ll_red[i];
-                B.ll_partial[blk] = s;
+            if constexpr (LC) {
+                // block sum of chain log-likelihoods, fixed order
+                for (int off = 32; off > 0; off >>= 1) ll += __shfl_xor(ll, off);
+                if ((tid & 63) == 0) ll_red[tid >> 6] = ll;
+                __syncthreads();
+                if (tid == 0) {
+                    double s = 0.0;
+                    for (int i = 0; i < VD_BLOCK / 64; ++i) s += ll_red[i];
+                    B.ll_partial[blk] = s;
+                }
+            } else if (tid < g.C) {
+                // one entry per chain, at the chain's place on the level grid: the frames (or the
+                // nodes of a temporal-axis chain) summed in order, so the sums do not depend on
+                // how many chains a block holds
+                const int c = tid, L = chain_len(g, blk, c);
+                if (L > 0) {
+                    double sum = 0.0;
+                    if (w.chain_axis == 0) {
+                        for (int t = 0; t < w.N; ++t) sum += llc[c * VD_NMAX + t];
+                    } else {
+                        for (int i = 0; i < L; ++i) sum += llc[c * stride + i];
+                    }
+                    const int sidx = blk % g.nseg, lb = blk / g.nseg;
+                    B.ll_partial[(size_t)(lb * g.C + c) * g.nseg + sidx] = sum;
+                }
             }
         }
     }
@@ -402,14 +462,14 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
         const int fpix = p.v * w.W + p.u;
         const float r0 = rho_full[fpix];
         prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, fpix, c, r0);
-        float bE = keep_cost ? energy2_costs<PR>(w, B.P, B.prior, c, r0, cost_s + o, nodes)
-                             : energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, r0);
+        energy_t bE = keep_cost ? energy2_costs<PR>(w, B.P, B.prior, c, r0, cost_s + o, nodes)
+                                : energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, r0);
         float bV = r0;
         int bS = 0;
         if (local) {
             const int U = min(p.u / w.s, w.wc - 1), V = min(p.v / w.s, w.hc - 1);
             const float rc = B.idepth_coarse[V * w.wc + U];
-            const float e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, rc, bE);
+            const energy_t e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, rc, bE);
             if (e < bE) { bE = e; bV = rc; bS = 2; }
         }
         // the candidates of a draw are evaluated in groups of PG against the best before the
@@ -420,7 +480,8 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
         for (int gi = 0; gi < G; ++gi) {
             const uint4 r = philox10(make_uint4((uint32_t)p.li, (uint32_t)gi, word2, w.window_id), w.key0, w.key1);
             const uint32_t words[4] = {r.x, r.y, r.z, r.w};
-            float cand[4], e[4];
+            float cand[4];
+            energy_t e[4];
             unsigned live = 0u;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -496,7 +557,7 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                 for (int d = 1; d <= g.spec; ++d) {
                     if (pos + d >= L) { nx = -2; break; }
                     const int j = p.i + d * di;
-                    const float e1 = specE[(d - 1) * nodes + base + j], eA = bestE[base + j];
+                    const energy_t e1 = specE[(d - 1) * nodes + base + j], eA = bestE[base + j];
                     if (!((e1 < eA) || (e1 == eA && bestS[base + j] > 1))) { nx = j; break; }
                 }
                 hop[base + p.i] = make_int2(nx, __float_as_int(bestV[base + p.i]));
@@ -536,19 +597,19 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                                 }
                                 const int mm = min(wl, LW - 1), jmm = j0 + mm * di;
                                 const bool mine_node = wl < LW && jmm >= 0 && jmm < L;
-                                float la_e = 0.f;
+                                energy_t la_e = 0.0;
 #pragma unroll
                                 for (int tt = 0; tt < VD_NMAX; ++tt) {
                                     if (tt < w.N) {
                                         const float ct = __shfl(mine, mm * w.N + tt);
-                                        if (mine_node) la_e = fmaf(q_s[tt * nodes + base + jmm], ct, la_e);
+                                        if (mine_node) la_e = eacc(q_s[tt * nodes + base + jmm], ct, la_e);
                                     }
                                 }
                                 // lane m < LW decides node j0 + m di; the first replacing
                                 // node in sweep order is the lowest such lane
                                 bool rep = false;
                                 if (mine_node) {
-                                    const float eA = bestE[base + jmm];
+                                    const energy_t eA = bestE[base + jmm];
                                     rep = !((la_e < eA) || (la_e == eA && bestS[base + jmm] > 1));
                                 }
                                 const unsigned long long rm = __ballot(rep);
@@ -615,18 +676,18 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                                     for (int tt = 0; tt < VD_NMAX; ++tt) if (tt < w.N) cn.q[tt] = q_s[tt * nodes + on];
                                     prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cn, rcur[on]);
                                 }
-                                float e1 = 0.f;
+                                energy_t e1 = 0.0;
 #pragma unroll
                                 for (int tt = 0; tt < VD_NMAX; ++tt) {
                                     if (tt < w.N) {
                                         const float ct = __shfl(mine, hbase + mm * w.N + tt);
-                                        if (mine_node) e1 = fmaf(cn.q[tt], ct, e1);
+                                        if (mine_node) e1 = eacc(cn.q[tt], ct, e1);
                                     }
                                 }
                                 bool rep = false;
                                 if (mine_node) {
                                     e1 = prior_terms<PR>(w, B.P, B.prior, cn, carried, e1);
-                                    const float eA = bestE[on];
+                                    const energy_t eA = bestE[on];
                                     rep = !((e1 < eA) || (e1 == eA && bestS[on] > 1));
                                 }
                                 // the first replacing node in sweep order: this group's lowest lane
@@ -660,11 +721,11 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                 float carried = bestV[base + i0];
                 int src = i0;
                 int la_src = -1, la_i = 0;                      // lookahead: source node, first node
-                float la_e = 0.f;                               // lane m < LA: energy at node la_i + m*di
+                energy_t la_e = 0.0;                            // lane m < LA: energy at node la_i + m*di
                 if (hl == 0) newV[base + i0] = carried;
                 for (int n = 1, i = i0 + di; n < L; ++n, i += di) {
                     const int o = base + i;
-                    float e1;
+                    energy_t e1;
                     const int dist = (i - src) * di;            // steps back to the carried value's node
                     if (dist <= g.spec) {
                         e1 = specE[(dist - 1) * nodes + o];
@@ -684,12 +745,12 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                             }
                             const int mm = min(hl, LA - 1), imm = i + mm * di;
                             const bool mine_node = hl < LA && imm >= 0 && imm < L;
-                            la_e = 0.f;
+                            la_e = 0.0;
 #pragma unroll
                             for (int tt = 0; tt < VD_NMAX; ++tt) {
                                 if (tt < w.N) {
                                     const float ct = __shfl(mine, hbase + mm * w.N + tt);
-                                    if (mine_node) la_e = fmaf(q_s[tt * nodes + base + imm], ct, la_e);
+                                    if (mine_node) la_e = eacc(q_s[tt * nodes + base + imm], ct, la_e);
                                 }
                             }
                         }
@@ -705,7 +766,7 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                         prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, cx, rcur[o]);
                         e1 = energy2_lanes<B2, PR>(w, B.P, B.flow2, B.prior, cx, carried, hl, hbase);
                     }
-                    const float eA = bestE[o];
+                    const energy_t eA = bestE[o];
                     const bool keep = (e1 < eA) || (e1 == eA && bestS[o] > 1);
                     if (!keep) { carried = bestV[o]; src = i; }
                     if (hl == 0) newV[o] = carried;
@@ -726,7 +787,7 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
 template <bool B2, bool PR, bool LC>
 __global__ void __launch_bounds__(VD_BLOCK)
 k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     level_body<B2, PR, LC>(w, g, B, do_e, do_m, xcd_block(blockIdx.x, gridDim.x), lds);
 }
 
@@ -749,7 +810,8 @@ __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, c
     const int gl = lane / SUB, part = lane - gl * SUB;
     const size_t lplane = (size_t)g.h * g.w;
     const bool valid = li < (int)lplane;
-    float bE = __builtin_huge_valf(), bV = 0.f, r0 = 0.f;
+    energy_t bE = __builtin_huge_val();
+    float bV = 0.f, r0 = 0.f;
     int bS = 1 << 30;
     if (valid) {
         const int ly = li / g.w, lx = li - ly * g.w;
@@ -767,7 +829,7 @@ __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, c
         if (lane == 1 && w.level == 1) {
             const int U = min(u / w.s, w.wc - 1), V = min(v / w.s, w.hc - 1);
             const float rc = B.idepth_coarse[V * w.wc + U];
-            const float e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, rc, bE);
+            const energy_t e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, rc, bE);
             if (e < bE) { bE = e; bV = rc; bS = 2; }
         }
         const int G = (w.K - 3 + 3) / 4;
@@ -783,7 +845,7 @@ __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, c
                     const float cand = (slot & 1)
                         ? fminf(fmaxf(r0 * fmaf(w.sigma_it, fmaf(2.f, uu, -1.f), 1.f), w.rmin), w.rmax)
                         : fmaf(uu, w.rmax - w.rmin, w.rmin);
-                    const float e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, cand, bE);
+                    const energy_t e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, cand, bE);
                     if (e < bE) { bE = e; bV = cand; bS = slot; }
                 }
             }
@@ -791,7 +853,8 @@ __device__ __forceinline__ void phase_a_body(const Win& w, const LevelGeom& g, c
     }
 #pragma unroll
     for (int off = 1; off < LANES; off <<= 1) {
-        const float oE = __shfl_xor(bE, off), oV = __shfl_xor(bV, off);
+        const energy_t oE = __shfl_xor(bE, off);
+        const float oV = __shfl_xor(bV, off);
         const int oS = __shfl_xor(bS, off);
         if (oE < bE || (oE == bE && oS < bS)) { bE = oE; bV = oV; bS = oS; }
     }
@@ -1211,7 +1274,7 @@ __device__ __forceinline__ void finalize_body(const Win& w, const FinalBufs& B, 
         B.conf[j] = C;
         int nv = 0;
         emissions<B2>(w, B.P, B.flow2, c, rho, [&](int, float, bool ok, float) { nv += ok; });
-        acc[0] = (double)energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, rho) * (double)VD_LN2;
+        acc[0] = energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, rho) * (double)VD_LN2;
         acc[1] = nv;
         acc[2] = w.N - nv;
         acc[3] = npr;
@@ -1262,7 +1325,7 @@ __global__ void __launch_bounds__(VD_BLOCK) k_setup_batch(const PrepItem* __rest
     const int gb = xcd_block(blockIdx.x, gridDim.x);
     const PrepItem& it = items[blk2item[gb]];
     const int blk = gb - it.begin;
-    if (it.init) init_body(it.w, it.idepth, blk);
+    if (it.init) init_body(it.w, it.idepth, it.boot, blk);
     flow_pairs_body(it.flow, it.flow2, it.N, it.w.H, it.w.W, blk);
 }
 
@@ -1271,7 +1334,7 @@ __global__ void __launch_bounds__(VD_BLOCK) k_setup_batch(const PrepItem* __rest
 template <bool B2, bool PR, int MODE>
 __global__ void __launch_bounds__(VD_BLOCK) k_level_batch(const LevelItem* __restrict__ items,
                                                           const int* __restrict__ blk2item) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     const int gb = xcd_block(blockIdx.x, gridDim.x);
     const LevelItem& it = items[blk2item[gb]];
     const int blk = gb - it.begin;
@@ -1319,7 +1382,8 @@ namespace vd {
 
 size_t level_lds_bytes(const LevelGeom& g) {
     const size_t nodes = (size_t)g.C * (g.seg + 1);
-    return (2 * VD_NMAX * nodes + (4 + (size_t)g.spec) * nodes + (size_t)g.ncost * nodes) * sizeof(float) +
+    return (1 + (size_t)g.spec) * nodes * sizeof(energy_t) +
+           (2 * (size_t)g.nf * nodes + 3 * nodes + (size_t)g.ncost * nodes) * sizeof(float) +
            nodes * sizeof(int);
 }
 
@@ -1352,16 +1416,16 @@ hipError_t launch_flow_pairs(const float2* flow, float4* f2, int N, int H, int W
     return hipGetLastError();
 }
 
-hipError_t launch_init(const Win& w, float* idepth, hipStream_t st) {
+hipError_t launch_init(const Win& w, float* idepth, InitSrc boot, hipStream_t st) {
     const int n = w.H * w.W;
-    hipLaunchKernelGGL(k_init_idepth, dim3((n + VD_BLOCK - 1) / VD_BLOCK), dim3(VD_BLOCK), 0, st, w, idepth);
+    hipLaunchKernelGGL(k_init_idepth, dim3((n + VD_BLOCK - 1) / VD_BLOCK), dim3(VD_BLOCK), 0, st, w, idepth, boot);
     return hipGetLastError();
 }
 
-hipError_t launch_init_if(const Win& w, float* idepth, const int* flag, int32_t* out, hipStream_t st) {
+hipError_t launch_init_if(const Win& w, float* idepth, InitSrc boot, const int* flag, int32_t* out, hipStream_t st) {
     const int n = w.H * w.W;
-    hipLaunchKernelGGL(k_init_idepth_if, dim3((n + VD_BLOCK - 1) / VD_BLOCK), dim3(VD_BLOCK), 0, st, w, idepth, flag,
-                       out);
+    hipLaunchKernelGGL(k_init_idepth_if, dim3((n + VD_BLOCK - 1) / VD_BLOCK), dim3(VD_BLOCK), 0, st, w, idepth, boot,
+                       flag, out);
     return hipGetLastError();
 }
 

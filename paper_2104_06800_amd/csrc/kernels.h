@@ -21,6 +21,8 @@ struct LevelGeom {
     int spec;          // speculation depth of the chain scan
     int ncost;         // frames of E-step costs kept for a fused pass's M-step (0: none)
     int pa_lanes;      // lanes per lattice node of the separate phase-A grid (4, 8 or 16)
+    int nchains;       // chain segments of the level (one log-likelihood entry each)
+    int nf;            // frames of the per-frame LDS arrays: max(N, 3) (the scan reuses them)
 };
 
 struct LevelBufs {
@@ -35,10 +37,10 @@ struct LevelBufs {
     const float* q_in;           // M-step input when the E-step is not fused
     float* rho_out;              // M-step output (coarse lattice or full image)
     double* ll_partial;          // per-block log-likelihood, or null
-    float* pa_E;                 // phase-A results per level pixel (split M-step)
+    double* pa_E;                // phase-A results per level pixel (split M-step)
     float* pa_V;
     int* pa_S;
-    float* pa_spec;              // [spec][level plane] speculative predecessor energies
+    double* pa_spec;             // [spec][level plane] speculative predecessor energies
 };
 
 struct PoseBufs {
@@ -100,6 +102,7 @@ struct VcArgs {
     double fx, fy, cx, cy;
     float conf_min;
     double tau;
+    int lds_bits;              // the block gathers its coverage bits in LDS first
 };
 
 struct VcBufs {
@@ -157,6 +160,13 @@ struct FinalItem {
     int begin, nblocks;
 };
 
+// first depth prior of a window, which the initial inverse depth starts from (null prior:
+// random start everywhere)
+struct InitSrc {
+    const float* prior;          // prior 0's inverse depth [H][W]
+    const double* pose;          // prior 0's pose 6-vector
+};
+
 struct PrepItem {
     const double* pose;
     const double* prior_pose;
@@ -168,6 +178,7 @@ struct PrepItem {
     float* idepth;
     const float2* flow;
     float4* flow2;
+    InitSrc boot;
     int init;
     int begin, nblocks;
 };
@@ -175,8 +186,8 @@ struct PrepItem {
 size_t level_lds_bytes(const LevelGeom& g);
 hipError_t launch_pose_prep(const double* pose, int N, const double* prior_pose, int P, PoseF* out, PoseD* outd,
                             hipStream_t st);
-hipError_t launch_init(const Win& w, float* idepth, hipStream_t st);
-hipError_t launch_init_if(const Win& w, float* idepth, const int* flag, int32_t* out, hipStream_t st);
+hipError_t launch_init(const Win& w, float* idepth, InitSrc boot, hipStream_t st);
+hipError_t launch_init_if(const Win& w, float* idepth, InitSrc boot, const int* flag, int32_t* out, hipStream_t st);
 hipError_t launch_flow_pairs(const float2* flow, float4* f2, int N, int H, int W, hipStream_t st);
 hipError_t launch_level(const Win& w, const LevelGeom& g, const LevelBufs& b, int do_e, int do_m, hipStream_t st);
 hipError_t launch_phase_a(const Win& w, const LevelGeom& g, const LevelBufs& b, hipStream_t st);
@@ -205,5 +216,8 @@ hipError_t launch_vc(const VcArgs& a, const VcBufs& b, hipStream_t st);
 hipError_t launch_pose_sample(const PoseSampleArgs& a, const PoseSampleBufs& b, hipStream_t st);
 hipError_t launch_align_prepare(const AlignArgs& a, const AlignBufs& b, hipStream_t st);
 hipError_t launch_align_step(const AlignArgs& a, const AlignBufs& b, int final_pass, int nblocks, hipStream_t st);
+size_t sim3_state_doubles(int n_pairs);
+hipError_t launch_align_sim3(const AlignArgs& a, const AlignBufs& b, double* scale, double* state, int steps, int nblocks,
+                             hipStream_t st);
 
 }  // namespace vd

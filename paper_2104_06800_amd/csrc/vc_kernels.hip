@@ -40,7 +40,14 @@ k_vc_prep(VcArgs a, VcBufs B) {
 __global__ void __launch_bounds__(VD_BLOCK)
 k_vc_pass(VcArgs a, VcBufs B) {
     extern __shared__ uint32_t cnt[];          // [n] visible counts, [n] depth pixels
+    // with lds_bits, the block's coverage bits go to an LDS copy of the n bitmaps first and
+    // only its nonzero words reach the global bitmaps: one atomic per word per block instead
+    // of one per pixel and pose that lands in a not yet covered cell
+    uint32_t* lbits = cnt + ((a.n + 2) & ~1);
+    const int nwords = a.n * a.words;
     for (int k = threadIdx.x; k <= a.n; k += VD_BLOCK) cnt[k] = 0u;
+    if (a.lds_bits)
+        for (int k = threadIdx.x; k < nwords; k += VD_BLOCK) lbits[k] = 0u;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -73,9 +80,13 @@ k_vc_pass(VcArgs a, VcBufs B) {
                 in = xn >= 0.0 && xn <= (double)(a.W - 1) && yn >= 0.0 && yn <= (double)(a.H - 1);
                 if (in) {
                     const int c = ((int)yn / a.cell) * a.wc + (int)xn / a.cell;
-                    uint32_t* word = B.bits + (size_t)k * a.words + (c >> 5);
                     const uint32_t bit = 1u << (c & 31);
-                    if (!(*word & bit)) atomicOr(word, bit);
+                    if (a.lds_bits) {
+                        atomicOr(lbits + k * a.words + (c >> 5), bit);
+                    } else {
+                        uint32_t* word = B.bits + (size_t)k * a.words + (c >> 5);
+                        if (!(*word & bit)) atomicOr(word, bit);
+                    }
                 }
             }
         }
@@ -87,6 +98,11 @@ k_vc_pass(VcArgs a, VcBufs B) {
         const uint32_t c = cnt[k];
         if (c) atomicAdd(&B.count[k == a.n ? 0 : k + 1], c);
     }
+    if (a.lds_bits)
+        for (int k = threadIdx.x; k < nwords; k += VD_BLOCK) {
+            const uint32_t v = lbits[k];
+            if (v) atomicOr(B.bits + k, v);
+        }
 }
 
 __global__ void __launch_bounds__(VD_BLOCK)
@@ -127,7 +143,9 @@ hipError_t launch_vc(const VcArgs& a, const VcBufs& b, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nb = (a.H * a.W + VD_BLOCK - 1) / VD_BLOCK;
-    hipLaunchKernelGGL(k_vc_pass, dim3(nb), dim3(VD_BLOCK), sizeof(uint32_t) * (a.n + 1), st, a, b);
+    const size_t lds = sizeof(uint32_t) * (((size_t)a.n + 2) & ~(size_t)1) +
+                       (a.lds_bits ? sizeof(uint32_t) * (size_t)a.n * a.words : 0);
+    hipLaunchKernelGGL(k_vc_pass, dim3(nb), dim3(VD_BLOCK), lds, st, a, b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_vc_finish, dim3(1), dim3(VD_BLOCK), 0, st, a, b);
     return hipGetLastError();

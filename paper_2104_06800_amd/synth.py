@@ -167,6 +167,25 @@ def disc_outliers(rng, shape, radius=OUTLIER_RADIUS):
     return np.stack([r * np.cos(phi), r * np.sin(phi)], axis=-1)
 
 
+def stereo_prior(rng, rho_gt, fb, alpha_px=0.6, beta=1.0, outlier_frac=0.08, hole_frac=0.05):
+    """An external stereo depth prior of a window's reference frame: disparity fb * rho_gt plus a
+    signed log-logistic(alpha_px, beta) error (inverse CDF, random sign), a fraction replaced by
+    disparities uniform over [0, fb * max(rho_gt)] (matching failures), a fraction of holes (NaN);
+    returned as inverse depth [1][H][W] with the window fields of the empirical disparity model."""
+    shape = rho_gt.shape
+    u = rng.uniform(1e-12, 1 - 1e-12, size=shape)
+    mag = alpha_px * (u / (1.0 - u)) ** (1.0 / beta)
+    d = fb * rho_gt + np.where(rng.uniform(size=shape) < 0.5, -mag, mag)
+    D = float(fb * np.nanmax(rho_gt))
+    out = rng.uniform(size=shape) < outlier_frac
+    d = np.where(out, rng.uniform(0.0, D, size=shape), d)
+    pr = np.maximum(d, 1e-3) / fb
+    pr[rng.uniform(size=shape) < hole_frac] = np.nan
+    fields = dict(prior_model=1, prior_disp_scale=float(fb), prior_sigma_rel=float(alpha_px),
+                  prior_fisk_beta=float(beta), prior_uniform_rel=D)
+    return pr[None].astype(np.float32), fields
+
+
 # --------------------------------------------------------------------------- #
 # scene recipes
 # --------------------------------------------------------------------------- #
@@ -502,3 +521,53 @@ def make_pairs(n_pairs: int, H=480, W=640, seed=3_000_000, max_deg=2.0, max_t=0.
                   robust_scale=0.02, gn_steps=10, normal_disc_rel=0.05, scale_s=1.0)
     return dict(params=params, idepth1=rho1, idepth2=rho2, conf2=c2, pose_gt=pose, object1=obj1,
                 object2=obj2)
+
+
+def _rel(Ts):
+    """Poses of frames 1.. relative to frame 0 (world -> camera each)."""
+    R0, t0 = Ts[0]
+    inv0 = (R0.T, -R0.T @ t0)
+    return [_compose(T, inv0) for T in Ts]
+
+
+def vo_start(rng, pose6, max_deg=1.0, max_t=0.03):
+    """A chained visual-odometry estimate of a relative pose: the 6-vector moved by a random
+    left motion of up to max_deg per rotation axis and max_t per translation axis."""
+    dT = (_rot(np.deg2rad(rng.uniform(-max_deg, max_deg, 3))), rng.uniform(-max_t, max_t, 3))
+    return _as6(_compose(dT, _from6(pose6)))
+
+
+def keyframe_pair(k, H=480, W=640, N=8, seed=3_500_000):
+    """Two indoor windows of one room whose reference cameras are related by a random motion
+    (<= 5 deg, <= 0.3 m), each with its flows, depth prior (as workload 3) and perturbed
+    initial poses, for keyframe alignment of GEM outputs.  Returns (window a, window b, pose
+    of camera b relative to camera a as a 6-vector mapping camera-b points to camera a)."""
+    rng = np.random.default_rng(seed + k)
+    f0 = 500.0 * W / 640
+    intr = (f0, f0, W / 2, H / 2)
+    scene = scene_room(rng, intr=intr, HW=(H, W))
+    alpha, beta = 0.5, 2.0
+    TA = traj_6dof(rng, N)
+    ax = rng.normal(size=3)
+    ax /= np.linalg.norm(ax)
+    d = rng.normal(size=3)
+    dT = (_rot(ax * np.deg2rad(rng.uniform(0.5, 1.0) * 5.0)), d / np.linalg.norm(d) * rng.uniform(0.5, 1.0) * 0.3)
+    TB = [_compose(T, dT) for T in traj_6dof(rng, N)]
+    out = []
+    for Ts in (TA, TB):
+        flow, rho_gt, dyn = render_window(scene, Ts, H, W, intr, rng, alpha, beta, True)
+        rel = _rel(Ts)
+        params = default_params(H, W, N, intr, fisk_alpha=alpha, fisk_beta=beta, idepth_min=0.1, idepth_max=1.0,
+                                n_candidates=32, iters=10, P=1)
+        params["seed"] = int(rng.integers(0, 2 ** 63))
+        depth = 1.0 / rho_gt
+        pr = 1.0 / np.maximum(depth * (1.0 + 0.05 * rng.normal(size=depth.shape)), 1e-3)
+        pr[rng.uniform(size=pr.shape) < 0.10] = np.nan
+        out.append(dict(params=params, flow=flow.astype(np.float32),
+                        pose_gt=np.stack([_as6(T) for T in rel[1:]]),
+                        pose_init=np.stack([_as6(perturb(rng, T)) for T in rel[1:]]),
+                        idepth_gt=rho_gt, dynamic=dyn, intr=intr, prior_idepth=pr[None].astype(np.float32),
+                        prior_pose=np.zeros((1, 6))))
+    # camera b -> camera a:  X_a = R_a0 R_b0^T (X_b - t_b0) + t_a0, with camera a = world
+    Rb, tb = TB[0]
+    return out[0], out[1], _as6((Rb.T, -Rb.T @ tb))

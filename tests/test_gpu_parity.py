@@ -65,6 +65,28 @@ def test_init_idepth(lib):
     np.testing.assert_allclose(np_(b["idepth"]), ob["idepth"], rtol=1e-6)
 
 
+@pytest.mark.parametrize("pose_kind", ["identity", "moved"])
+def test_init_idepth_from_prior(lib, pose_kind):
+    """The start read off depth prior 0 (two fixed-point rounds of its transfer, FP64 on both
+    sides) and the random start at holes and at pixels whose transfer leaves the image."""
+    w = window(3, 1, H=40, W=56, N=3)
+    p = w["params"]
+    if pose_kind == "moved":
+        w["prior_pose"] = np.array([[0.02, -0.015, 0.01, 0.08, -0.03, 0.12]])
+    b = lib.alloc(p, w["flow"], w["pose_init"], w["prior_idepth"], w["prior_pose"])
+    lib.init_idepth(p, b)
+    ob = oracle_bufs(p, w)
+    ogem.init_idepth(p, ob)
+    boot, ok = ogem.prior_bootstrap(p, ob)
+    print("init from prior:", pose_kind, "resolved", ok.mean())
+    assert 0.5 < ok.mean() < 1.0
+    np.testing.assert_allclose(np_(b["idepth"]), ob["idepth"], rtol=1e-6)
+    p2 = dict(p, init_random=1)
+    lib.init_idepth(p2, b)
+    ogem.init_idepth(p2, ob)
+    np.testing.assert_allclose(np_(b["idepth"]), ob["idepth"], rtol=1e-6)
+
+
 # ----------------------------------------------------------------------------- E-step
 CASES_E = [dict(level=1, it=0), dict(level=1, it=1), dict(level=1, it=2), dict(level=1, it=3),
            dict(level=0, it=0), dict(level=0, it=1), dict(level=0, it=3)]
