@@ -85,7 +85,10 @@ class VcParams(ctypes.Structure):
                 ("cell", ctypes.c_int32), ("conf_min", ctypes.c_float)]
 
 
-def load_library(path=LIB):
+def load_library(path=None):
+    """Loads the C-ABI library: the in-tree build, or another build of the same sources
+    (same ABI) named by the environment variable VOLDOR_LIBRARY."""
+    path = path or os.environ.get("VOLDOR_LIBRARY") or LIB
     if not os.path.exists(path):
         raise VoldorError(f"{path} is missing: build it first (python -m paper_2104_06800_amd.build)")
     lib = ctypes.CDLL(path)

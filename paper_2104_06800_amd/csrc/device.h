@@ -312,12 +312,14 @@ __device__ __forceinline__ float log2_ratio(const Win& w, float r2) {
     return w.fl_c + 2.f * log2f_fast(1.f + y) + (2.f - w.beta) * lz;
 }
 
-// MIE cost of a valid flow term, log2(1 + L0/L1), in log2 units
+// MIE cost of a valid flow term, log2(1 + L0/L1), in log2 units.  Shape 2: L0/L1 = c s^2 >= c,
+// and 1 + c s^2 is rounded once before the log: the absolute error stays at the log's FP32
+// resolution, which is what a sum of such terms needs
 template <bool B2>
 __device__ __forceinline__ float flow_cost2(const Win& w, float r2) {
     if (B2) {
         const float s = fmaf(r2, w.inv_a2, 1.f);
-        return log2_1p(w.fl_c * s * s);
+        return log2f_fast(fmaf(w.fl_c * s, s, 1.f));
     }
     return softplus2(log2_ratio<false>(w, r2));
 }
@@ -377,8 +379,9 @@ __device__ __forceinline__ bool sample_flow2(const float4* __restrict__ F2, int 
     x0 = min(x0, W - 2);
     y0 = min(y0, H - 2);
     const float ax = xs - (float)x0, ay = ys - (float)y0;
-    const unsigned o = (unsigned)y0 * (unsigned)W + (unsigned)x0;
-    const float4 l = F2[o], r = F2[o + 1];
+    const unsigned o = __umul24((unsigned)y0, (unsigned)W) + (unsigned)x0;
+    const float4* q = (const float4*)((const char*)F2 + (o << 4));
+    const float4 l = q[0], r = q[1];
     const float tx = fmaf(ax, r.x - l.x, l.x), ty = fmaf(ax, r.y - l.y, l.y);
     const float bx = fmaf(ax, r.z - l.z, l.z), by = fmaf(ax, r.w - l.w, l.w);
     fx = fmaf(ay, bx - tx, tx);
@@ -864,7 +867,7 @@ __device__ __forceinline__ void reduce_partials(const double* part, unsigned nb,
     if (k < NR) {
         const double* pk = part + (size_t)k * nb;
 #pragma unroll 8
-        for (unsigned b = l; b < nb; b += SL) acc += __builtin_nontemporal_load(pk + b);
+        for (unsigned b = l; b < nb; b += SL) acc += pk[b];
     }
 #pragma unroll
     for (int off = SL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
