@@ -39,15 +39,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 work of one local-level pass, per (pixel, frame) (flops; a transcendental
-# counts as one): K candidate evaluations of ~50 flops each (reprojection in displacement
-# form 16, bilinear flow sample 16 for frames t >= 2, residual 7, log-logistic MIE cost 12)
-# plus the E-step's emission (42) and forward-backward (23).
-FLOPS_PER_CAND_FRAME = 50.0
-FLOPS_ESTEP_PER_PIXEL_FRAME = 65.0
-# Non-packed FP32 vector peak: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz.  Packed FP32
-# instructions are disabled when the library is compiled, which halves the 157.3 TFLOP/s published peak.
-PEAK_FP32_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# Algorithmic VALU work of one local-level pass per (pixel, frame), counted as the survey of
+# the method does: K candidate evaluations of ~48 lane-op slots each (reprojection,
+# bilinear flow sample, residual, log-logistic MIE cost; a transcendental counts 4) plus
+# ~55 slots for the E-step's emission and forward-backward at the current value.
+SLOTS_PER_CAND_FRAME = 48.0
+SLOTS_ESTEP_PER_PIXEL_FRAME = 55.0
+# Unpacked FP32 vector issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-op slots/s
+# (packed FP32, which doubles it to the published 157.3 TFLOP/s, is not emitted).
+PEAK_VALU_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 PEAK_BF16_TFLOPS = 2500.0           # dense BF16 matrix-core peak
 # stored (computed) channel counts of the proposal network's layers: (c_in, c_out, scale)
 PROPOSAL_LAYERS = [(16, 64, 1), (64, 128, 0.25), (128, 128, 0.25), (128, 128, 0.25), (128, 64, 1), (64, 32, 1)]
@@ -59,10 +59,14 @@ BYTES_PER_PIXEL = 8.0 + 4.0 / 16
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_level_local_1216x352_n6_k32_hbm_bytes.txt")
 
 
+# the sources the local-level kernel is compiled from
+LEVEL_SOURCES = ("device.h", "kernels.h", "gem_kernels.hip")
+
+
 def source_hash():
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2104_06800_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for f in LEVEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2104_06800_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -92,6 +96,8 @@ def main():
     ap.add_argument("--only-window", action="store_true", help="skip the batch / learned-init / proposal parts")
     ap.add_argument("--only-batch", action="store_true",
                     help="only the 64-window batch, its windows generated in this process (for profilers)")
+    ap.add_argument("--only-proposal", action="store_true",
+                    help="only the proposal network's forward pass at 640x480 (for profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -115,6 +121,16 @@ def main():
 
     from paper_2104_06800_amd import synth
     from paper_2104_06800_amd.binding import TIMER_COARSE, TIMER_LOCAL, TIMER_POSE, Voldor
+
+    if args.only_proposal:
+        from paper_2104_06800_amd import proposal as pr
+        lib = Voldor(0)
+        params, _ = pr.load(os.path.join(ROOT, "paper_2104_06800_amd", "weights", "proposal_n6.npz"))
+        net = lib.net_alloc(params)
+        print(json.dumps({"proposal": proposal_forward_workload(lib, torch, net, synth.make_window(4, 10 ** 6))}),
+              flush=True)
+        lib.close()
+        return
 
     if args.only_batch:
         lib = Voldor(0)
@@ -174,16 +190,16 @@ def main():
     # dominant kernel: the fused local-level pass, every launch of it in the timed steps
     k_ms_total, k_n = local_timer
     k_ms = k_ms_total / k_n
-    flops = H * W * N * (K * FLOPS_PER_CAND_FRAME + FLOPS_ESTEP_PER_PIXEL_FRAME)
+    slots = H * W * N * (K * SLOTS_PER_CAND_FRAME + SLOTS_ESTEP_PER_PIXEL_FRAME)
     alg_bytes = H * W * (N * BYTES_PER_PIXEL_FRAME + BYTES_PER_PIXEL)
-    achieved = flops / (k_ms / 1e3) / 1e12
+    achieved = slots / (k_ms / 1e3) / 1e12
     traffic = measured_traffic()
-    log(f"local level pass: {k_ms * 1e3:.1f} us/launch over {k_n} launches, {flops / 1e9:.2f} GFLOP "
-        f"algorithmic, {achieved:.2f} TFLOP/s; algorithmic bytes {alg_bytes / 1e6:.1f} MB "
+    log(f"local level pass: {k_ms * 1e3:.1f} us/launch over {k_n} launches, {slots / 1e9:.2f} G VALU slots "
+        f"algorithmic, {achieved:.2f} T slots/s; algorithmic bytes {alg_bytes / 1e6:.1f} MB "
         f"({alg_bytes / (k_ms / 1e3) / 1e9:.0f} GB/s); counted traffic "
         f"{'n/a' if traffic is None else f'{traffic / 1e6:.1f} MB'}")
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TSLOTS, 2),
+                "unit": "T VALU lane-op slots/s", "frac": round(achieved / PEAK_VALU_TSLOTS, 4),
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_unit": "bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE)",
                 "algorithmic_bytes": round(alg_bytes), "kernel": "k_level (local level, fused E+M)",
@@ -638,6 +654,39 @@ def vc_workload(lib, np, torch, w, b, reps=20):
     return res
 
 
+def proposal_forward_workload(lib, torch, net, w, reps=20):
+    """MFMA throughput of the whole proposal network on one window's flows (inference)."""
+    from paper_2104_06800_amd import proposal as pr
+    p = w["params"]
+    H, W, N = p["H"], p["W"], p["N"]
+    flow = lib.alloc(p, w["flow"], w["pose_init"])["flow"]
+    tn = pr.tnorm_of(w["pose_init"])
+    for _ in range(3):
+        lib.proposal_forward(net, flow, tn, p["idepth_min"], p["idepth_max"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lib.proposal_forward(net, flow, tn, p["idepth_min"], p["idepth_max"])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    # real channels: 2N flow components in, 1 + N heads out; the stored layers pad them to
+    # 16 and 32 (the matrix-core tiles compute the padding too)
+    real = [(2 * N if i == 0 else ci, 1 + N if i == len(PROPOSAL_LAYERS) - 1 else co, sc)
+            for i, (ci, co, sc) in enumerate(PROPOSAL_LAYERS)]
+    flops = sum(2.0 * H * W * sc * co * 9 * ci for ci, co, sc in real)
+    flops_stored = sum(2.0 * H * W * sc * co * 9 * ci for ci, co, sc in PROPOSAL_LAYERS)
+    achieved = flops / (ms / 1e3) / 1e12
+    log(f"proposal forward at {W}x{H}: {ms:.3f} ms, {flops / 1e9:.1f} GFLOP on real channels "
+        f"({flops_stored / 1e9:.1f} stored), {achieved:.1f} TFLOP/s")
+    return {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "ms": round(ms, 4), "gflop": round(flops / 1e9, 2),
+            "gflop_stored": round(flops_stored / 1e9, 2),
+            "frac_stored": round(flops_stored / (ms / 1e3) / 1e12 / PEAK_BF16_TFLOPS, 4),
+            "workload": f"proposal forward {W}x{H}, N={N}, BF16 weights/activations, FP32 accumulation"}
+
+
 def learned_init(lib, np, torch):
     from paper_2104_06800_amd import proposal as pr
     path = os.path.join(ROOT, "paper_2104_06800_amd", "weights", "proposal_n6.npz")
@@ -649,28 +698,7 @@ def learned_init(lib, np, torch):
     res = pr.compare(lib, net, test, warm=False)
     summ = pr.summarize(res)
     log("learned init: " + json.dumps(summ))
-    # proposal forward: MFMA throughput of the whole network at 640x480
-    p = test[0]["params"]
-    H, W = p["H"], p["W"]
-    flow = lib.alloc(p, test[0]["flow"], test[0]["pose_init"])["flow"]
-    tn = pr.tnorm_of(test[0]["pose_init"])
-    for _ in range(3):
-        lib.proposal_forward(net, flow, tn, p["idepth_min"], p["idepth_max"])
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 20
-    e0.record()
-    for _ in range(reps):
-        lib.proposal_forward(net, flow, tn, p["idepth_min"], p["idepth_max"])
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    flops = sum(2.0 * H * W * sc * co * 9 * ci for ci, co, sc in PROPOSAL_LAYERS)
-    achieved = flops / (ms / 1e3) / 1e12
-    log(f"proposal forward at {W}x{H}: {ms:.3f} ms, {flops / 1e9:.1f} GFLOP, {achieved:.1f} TFLOP/s")
-    prop = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "ms": round(ms, 4), "gflop": round(flops / 1e9, 2),
-            "workload": f"proposal forward {W}x{H}, N={p['N']}, BF16 weights/activations, FP32 accumulation"}
+    prop = proposal_forward_workload(lib, torch, net, test[0])
     summ["held_out_windows"] = "seeds 10^6..10^6+15 of the 640x480 street recipe, N=6"
     summ["training"] = (f"{int(meta.get('train', 0))} windows, {int(meta.get('steps', 0))} Adam steps on plain-GEM "
                         "outputs")
