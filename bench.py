@@ -213,10 +213,12 @@ def main():
     extra = {}
     if not args.only_window:
         extra["vc"] = vc_workload(lib, np, torch, w, b)
+        extra["pose_sample"] = pose_sample_workload(lib, np, torch, w, b)
         extra["hierarchy"] = hierarchy_sweep(lib, np, torch, w)
         extra["batch"] = batch_workload(lib, np, torch, args)
         extra["learned_init"], extra["proposal"] = learned_init(lib, np, torch)
         extra["align"] = align_workload(lib, np, torch)
+        extra["sim3"] = sim3_workload(lib, np, torch)
         extra["keyframe"] = keyframe_workload(lib, np, torch)
 
     out = {
@@ -345,6 +347,76 @@ def align_workload(lib, np, torch, n_pairs=32, reps=5):
            "converged": int((status.cpu().numpy() == 0).sum()),
            "workload": "synthetic room pairs, motion <= 2 deg / 0.1, 1% inverse-depth noise, random confidence"}
     log("align: " + json.dumps(out))
+    return out
+
+
+def pose_sample_workload(lib, np, torch, w, b, reps=10):
+    """The paper's sampled pose M-step on the street window's GEM output: 256 q-weighted P3P
+    samples per frame, meanshift mode and 3-sigma covariance fit for frames 1..N, one call;
+    time per call and the poses' distance to the truth before and after."""
+    from scipy.spatial.transform import Rotation
+    p = w["params"]
+    sp = dict(samples=256, tries=16, sigma_w=0.01, sigma_t_rel=0.02, eps=1e-12)
+    pose0 = b["pose"].clone()
+    lib.rigidness_fb(p, b, p["iters"], 1)
+    lib.pose_sample(p, b, p["iters"], sp)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        b["pose"].copy_(pose0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, info = lib.pose_sample(p, b, p["iters"], sp)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    got, gt, start = b["pose"].cpu().numpy(), w["pose_gt"], pose0.cpu().numpy()
+    b["pose"].copy_(pose0)
+    rot = lambda a: float(np.median([np.degrees((Rotation.from_rotvec(x[:3]) * Rotation.from_rotvec(y[:3]).inv()).magnitude())
+                                     for x, y in zip(a, gt)]))
+    out = {"ms_per_call": round(float(np.median(ts)), 3), "frames": p["N"], "samples_per_frame": sp["samples"],
+           "median_rot_err_deg_before": round(rot(start), 4), "median_rot_err_deg_after": round(rot(got), 4),
+           "valid_samples_frame1": int(info.cpu().numpy()[0, 0]),
+           "workload": "street window 1216x352 N=6 after 10 GEM iterations (GEM's Gauss-Newton poses as the start)"}
+    log("pose sample: " + json.dumps(out))
+    return out
+
+
+def sim3_workload(lib, np, torch, n_pairs=32, reps=5):
+    """7-DoF keyframe alignment (motion and relative depth scale, Levenberg-Marquardt, 15
+    evaluations) of the synthetic 640x480 pairs with map 1 scaled by a known factor."""
+    prs = _pool_generate(_align_pairs, [3_400_000 + i for i in range(n_pairs)])
+    ap = dict(prs[0]["params"], gn_steps=15)
+    cat = lambda k: np.concatenate([p[k] for p in prs])
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(3)
+    s_true = rng.uniform(0.7, 1.4, n_pairs)
+    t = lambda a, dt=torch.float32: torch.as_tensor(a, dtype=dt, device=dev).contiguous()
+    r1 = t(cat("idepth1") * s_true[:, None, None].astype(np.float32))
+    r2, c2 = t(cat("idepth2")), t(cat("conf2"))
+    gt = cat("pose_gt")
+    from paper_2104_06800_amd import synth
+    start = np.stack([synth.vo_start(rng, x, 1.0, 0.02) for x in gt])
+    pose = torch.as_tensor(start, dtype=torch.float64, device=dev)
+    scale = torch.ones(n_pairs, dtype=torch.float64, device=dev)
+    ts = []
+    for _ in range(reps + 1):
+        pose.copy_(torch.as_tensor(start, dtype=torch.float64))
+        scale.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, _, status = lib.align_sim3(ap, r1, r2, c2, pose, scale)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    got_s = scale.cpu().numpy()
+    out = {"pairs": n_pairs, "H": ap["H"], "W": ap["W"], "evaluations": ap["gn_steps"],
+           "ms_per_call": round(float(np.median(ts[1:])), 3),
+           "median_scale_rel_err": round(float(np.median(np.abs(got_s / s_true - 1))), 6),
+           "median_pose_err": round(float(np.median(np.abs(pose.cpu().numpy() - gt).max(1))), 6),
+           "converged": int((status.cpu().numpy() == 0).sum()),
+           "workload": "synthetic room pairs as in align, map 1 scaled by U[0.7, 1.4], start within 1 deg / 2 cm, s = 1"}
+    log("sim3: " + json.dumps(out))
     return out
 
 
