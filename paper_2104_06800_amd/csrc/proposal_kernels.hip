@@ -206,6 +206,208 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Stride-1 convolution from an LDS halo tile (the fast path of stride-1 layers).  A block
+// owns TH output rows x 32 output columns x BN output channels; a wave owns WM of those rows
+// (each an MFMA M tile of 32 pixels: lane % 32 is the column) and WN tiles of 32 channels.
+// Per chunk of KC input channels the block stages the (TH + 2) x 34 input halo and the
+// weights of all 9 taps in LDS once, and every tap's A operand is read from the halo
+// shifted by the tap: 9 x KC/16 MFMA steps per wave per chunk instead of KC/16, and each
+// input pixel is fetched about 1.3 times instead of 9.  MODE 0: forward; with UP the source
+// is read through a 2x nearest upsampling, and the halo holds the (TH/2 + 2) x 18 source
+// pixels under the tile, each tap reading the pixel its upsampled position falls on;
+// MODE 1: data gradient (taps flipped, transposed weights).  The next chunk's global
+// loads are in flight while the matrix cores work.
+// ---------------------------------------------------------------------------------------
+template <int WAVES_M, int WM, int WN, int KC, int MODE, bool UP>
+__global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
+    constexpr int WAVES_N = 4 / WAVES_M;
+    constexpr int TW = 32, TH = WAVES_M * WM, BN = WAVES_N * 32 * WN;
+    static_assert(!UP || (MODE == 0 && TH % 2 == 0), "upsampling: forward, even tile rows");
+    constexpr int HX = UP ? TW / 2 + 2 : TW + 2, HY = UP ? TH / 2 + 2 : TH + 2;   // halo columns, rows
+    constexpr int LD = KC + 8;                         // padded LDS pixel / weight row (bf16)
+    constexpr int QA = KC / 8;                         // 16-byte units per pixel / weight row
+    constexpr int NA = HY * HX * QA, NB = 9 * BN * QA; // 16-byte units of one chunk
+    constexpr int UA = (NA + 255) / 256, UB = (NB + 255) / 256;
+    constexpr unsigned kOut = 0x7ffffff0u;             // beyond any buffer: the load returns zeros
+    // the halo and the weights of a chunk; after the last chunk the same LDS holds the tile's
+    // skip input, staged with 16-byte loads
+    constexpr int NHS = HY * HX * LD, NBS = 9 * BN * LD, NSK = TH * TW * BN;
+    __shared__ __attribute__((aligned(16))) uint16_t lds_u16[(NHS + NBS) > NSK ? (NHS + NBS) : NSK];
+    uint16_t* const Hs = lds_u16;
+    uint16_t* const Bs = lds_u16 + NHS;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr0 = (wave % WAVES_M) * WM, wn0 = (wave / WAVES_M) * 32 * WN;
+    const int ntx = (a.Wo + TW - 1) / TW;
+    const int ox0 = (int)(blockIdx.x % (unsigned)ntx) * TW, oy0 = (int)(blockIdx.x / (unsigned)ntx) * TH;
+    const int n0 = blockIdx.y * BN;
+    const int nchunks = a.Cin / KC;
+
+    // The units a thread stages do not depend on the chunk: byte offsets into the source and
+    // weight arrays (kOut where the halo leaves the source grid or the channel tile leaves
+    // Cout: buffer loads out of range return zeros) and LDS positions, computed once.  A
+    // chunk moves the two buffer bases by KC channels.
+    unsigned offA[UA], offB[UB];
+    int ldsA[UA], ldsB[UB];
+#pragma unroll
+    for (int i = 0; i < UA; ++i) {
+        const int u = tid + 256 * i;
+        const int pix = u / QA, q = u - pix * QA;
+        const int hy = pix / HX, hx = pix - hy * HX;
+        // halo origin: the source pixel left of and above the tile's first tap (with UP, on
+        // the stored grid, whose pixel covers upsampled positions 2s and 2s + 1)
+        const int sy = UP ? oy0 / 2 + hy - 1 : oy0 + hy - 1, sx = UP ? ox0 / 2 + hx - 1 : ox0 + hx - 1;
+        const bool ok = u < NA && sy >= 0 && sy < (UP ? a.Hx : a.Hs) && sx >= 0 && sx < (UP ? a.Wx : a.Ws);
+        offA[i] = ok ? (unsigned)((((size_t)sy * a.Wx + sx) * a.Cin + 8 * q) * 2) : kOut;
+        ldsA[i] = u < NA ? pix * LD + 8 * q : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < UB; ++i) {
+        const int u = tid + 256 * i;
+        const int row = u / QA, q = u - row * QA;       // row = tap * BN + local channel
+        const int tap = row / BN, n = n0 + (row - tap * BN);
+        const bool ok = u < NB && n < a.Cout;
+        offB[i] = ok ? (unsigned)((((size_t)n * 9 + tap) * a.Cin + 8 * q) * 2) : kOut;
+        ldsB[i] = u < NB ? row * LD + 8 * q : -1;
+    }
+    const int bytesX = (int)min((size_t)0x7fffffff, (size_t)a.Hx * a.Wx * a.Cin * 2);
+    const int bytesW = (int)min((size_t)0x7fffffff, (size_t)a.Cout * 9 * a.Cin * 2);
+
+    u32x4 ra[UA], rb[UB];
+    auto load_chunk = [&](int c) {
+        const int cb = c * KC * 2;                      // chunk's byte shift within a pixel / row
+        const __amdgpu_buffer_rsrc_t rx =
+            __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)a.x + cb), (short)0, bytesX - cb, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rw =
+            __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)a.w + cb), (short)0, bytesW - cb, 0x00020000);
+#pragma unroll
+        for (int i = 0; i < UA; ++i) ra[i] = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)offA[i], 0, 0);
+#pragma unroll
+        for (int i = 0; i < UB; ++i) rb[i] = __builtin_amdgcn_raw_buffer_load_b128(rw, (int)offB[i], 0, 0);
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int i = 0; i < UA; ++i)
+            if (ldsA[i] >= 0) *reinterpret_cast<u32x4*>(&Hs[ldsA[i]]) = ra[i];
+#pragma unroll
+        for (int i = 0; i < UB; ++i)
+            if (ldsB[i] >= 0) *reinterpret_cast<u32x4*>(&Bs[ldsB[i]]) = rb[i];
+    };
+
+    f32x16 acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+    const int col_lane = lane & 31, khalf = 8 * (lane >> 5);
+    load_chunk(0);
+    for (int c = 0; c < nchunks; ++c) {
+        __syncthreads();                                // the previous chunk's reads are done
+        store_chunk();
+        __syncthreads();
+        if (c + 1 < nchunks) load_chunk(c + 1);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+            // forward: output (y, x) reads source (y + ky - 1, x + kx - 1) = halo (r + ky, col + kx);
+            // data gradient: source (y + 1 - ky, x + 1 - kx) = halo (r + 2 - ky, col + 2 - kx);
+            // UP: upsampled position (y + ky - 1) lies on stored row floor((y + ky - 1) / 2), halo
+            // row floor((r + ky - 1) / 2) + 1 = (r + ky + 1) >> 1 (tile origin even), likewise columns
+            const int dy = MODE == 0 ? ky : 2 - ky, dx = MODE == 0 ? kx : 2 - kx;
+            const int hcol = UP ? (col_lane + dx + 1) >> 1 : col_lane + dx;
+#pragma unroll
+            for (int kk = 0; kk < KC / 16; ++kk) {
+                const int col = 16 * kk + khalf;
+                bf16x8 A[WM], B[WN];
+#pragma unroll
+                for (int i = 0; i < WM; ++i) {
+                    const int hrow = UP ? (wr0 + i + dy + 1) >> 1 : wr0 + i + dy;
+                    A[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&Hs[(hrow * HX + hcol) * LD + col]));
+                }
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+                    B[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(
+                                                          &Bs[(tap * BN + wn0 + 32 * j + col_lane) * LD + col]));
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[i], B[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+
+    // epilogue: lane holds D[i][j = lane % 32] of M tile (row) wr0 + t for columns
+    // i = 8(e/4) + 4(lane/32) + e%4; the element offsets of the 16 columns are multiples of
+    // Cout shared by every row and channel tile
+    const bool full = ox0 + TW <= a.Wo;
+    const bool plain = !a.addf && !a.mask && !a.yf && a.y;
+    const int xb = ox0 + 4 * (lane >> 5);
+    // skip input of the tile into LDS as [row][column][BN channels]: rows of BN channels are
+    // contiguous in the source, so one 16-byte load per 8 channels (out of range: zeros)
+    const bool skip_lds = MODE == 0 && a.skip;
+    if (skip_lds) {
+        __syncthreads();                                // every wave is done with the last chunk
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)a.skip, (short)0, (int)min((size_t)0x7fffffff, (size_t)a.Ho * a.Wo * a.Cout * 2), 0x00020000);
+        constexpr int QS = BN / 8, NSU = TH * TW * QS;
+#pragma unroll
+        for (int i = 0; i < (NSU + 255) / 256; ++i) {
+            const int u = tid + 256 * i;
+            if (u >= NSU) break;
+            const int px = u / QS, q = u - px * QS;
+            const int r = px / TW, x = px - r * TW;
+            const int oy = oy0 + r, ox = ox0 + x;
+            const unsigned off = (oy < a.Ho && ox < a.Wo && n0 + 8 * q < a.Cout)
+                                     ? (unsigned)((((size_t)oy * a.Wo + ox) * a.Cout + n0 + 8 * q) * 2) : kOut;
+            *reinterpret_cast<u32x4*>(&lds_u16[px * BN + 8 * q]) = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+        const int nl = wn0 + 32 * j + col_lane, n = n0 + nl;
+        if (n >= a.Cout) continue;
+        const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+        for (int t = 0; t < WM; ++t) {
+            const int oy = oy0 + wr0 + t;
+            if (oy >= a.Ho) continue;
+            const size_t o0 = ((size_t)oy * a.Wo + xb) * a.Cout + n;
+            if (plain && full) {
+                uint16_t* yp = a.y + o0;
+                const int sk0 = ((wr0 + t) * TW + 4 * (lane >> 5)) * BN + nl;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    float v = acc[t][j][e] + bias;
+                    if (skip_lds) v += bf2f(lds_u16[sk0 + (8 * (e >> 2) + (e & 3)) * BN]);
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    yp[(size_t)(8 * (e >> 2) + (e & 3)) * a.Cout] = __builtin_bit_cast(uint16_t, (__bf16)v);
+                }
+                continue;
+            }
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int dxe = 8 * (e >> 2) + (e & 3);
+                if (xb + dxe >= a.Wo) continue;
+                const size_t o = o0 + (size_t)dxe * a.Cout;
+                float v = acc[t][j][e] + bias;
+                if (skip_lds) v += bf2f(lds_u16[((wr0 + t) * TW + 4 * (lane >> 5) + dxe) * BN + nl]);
+                else if (a.skip) v += bf2f(a.skip[o]);
+                if (a.addf) v += a.addf[o];
+                if (a.relu) v = fmaxf(v, 0.f);
+                if (a.mask && !(bf2f(a.mask[o]) > 0.f)) v = 0.f;
+                if (a.y) a.y[o] = __builtin_bit_cast(uint16_t, (__bf16)v);
+                if (a.yf) a.yf[o] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // 2x2 sum pooling of an FP32 gradient on the upsampled grid, times the ReLU mask of the
 // pooled grid's activation, stored as BF16 (and FP32 when asked)
 // ---------------------------------------------------------------------------------------
@@ -469,6 +671,27 @@ static void conv2_launch(const ConvArgs& a, int mode, hipStream_t st) {
     else hipLaunchKernelGGL((k_conv2<WAVES_M, WM, WN, KC, 1>), grid, dim3(256), 0, st, a);
 }
 
+template <int WAVES_M, int WM, int WN, int KC>
+static void halo_launch(const ConvArgs& a, int mode, hipStream_t st) {
+    constexpr int TH = WAVES_M * WM, BN = (4 / WAVES_M) * 32 * WN;
+    const dim3 grid((unsigned)(((a.Wo + 31) / 32) * ((a.Ho + TH - 1) / TH)), (unsigned)((a.Cout + BN - 1) / BN));
+    if (mode == 1) hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 1, false>), grid, dim3(256), 0, st, a);
+    else if (a.up) hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 0, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 0, false>), grid, dim3(256), 0, st, a);
+}
+
+// Stride-1 layers (forward with or without upsampling; data gradient without): the halo
+// kernel, blocks of 8 rows x 32 columns x 64 channels (chunks of 16 input channels; 128
+// output channels take two such blocks per tile, which keeps 3 blocks per CU) or x 32
+// channels (chunks of 32).
+static bool launch_halo(const ConvArgs& a, int mode, hipStream_t st) {
+    if (a.stride != 1 || (mode == 1 && a.up) || (a.up && (a.Hs != 2 * a.Hx || a.Ws != 2 * a.Wx))) return false;
+    if (a.Cout % 64 == 0) halo_launch<4, 2, 2, 16>(a, mode, st);
+    else if (a.Cin % 32 == 0) halo_launch<4, 2, 1, 32>(a, mode, st);
+    else halo_launch<4, 2, 1, 16>(a, mode, st);
+    return true;
+}
+
 // LDS-staged kernel: block 128 x 128 (Cout multiple of 128), 256 x 64 (Cout multiple of 64)
 // or 256 x 32; chunks of 32 channels (16 when Cin is not a multiple of 32)
 static void launch_conv2(const ConvArgs& a, int mode, hipStream_t st) {
@@ -483,7 +706,7 @@ static void launch_conv2(const ConvArgs& a, int mode, hipStream_t st) {
 }
 
 hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t st) {
-    launch_conv2(a, mode, st);
+    if (!launch_halo(a, mode, st)) launch_conv2(a, mode, st);
     return hipGetLastError();
 }
 

@@ -53,6 +53,10 @@ CASES = [
     dict(H=7, W=10, Cin=128, Cout=64, stride=1, up=1, relu=1, skip=True),
     dict(H=33, W=40, Cin=64, Cout=128, stride=1, up=0, relu=1, skip=False),
     dict(H=16, W=20, Cin=128, Cout=128, stride=2, up=0, relu=0, skip=False),
+    # stride-1 halo tiles with ragged edges in both directions (4- and 8-row tiles of 32 columns)
+    dict(H=37, W=70, Cin=128, Cout=128, stride=1, up=0, relu=1, skip=False),
+    dict(H=21, W=45, Cin=64, Cout=32, stride=1, up=0, relu=0, skip=True),
+    dict(H=13, W=34, Cin=128, Cout=64, stride=1, up=1, relu=1, skip=False),
 ]
 
 
