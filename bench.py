@@ -127,8 +127,8 @@ def main():
         lib = Voldor(0)
         params, _ = pr.load(os.path.join(ROOT, "paper_2104_06800_amd", "weights", "proposal_n6.npz"))
         net = lib.net_alloc(params)
-        print(json.dumps({"proposal": proposal_forward_workload(lib, torch, net, synth.make_window(4, 10 ** 6))}),
-              flush=True)
+        print(json.dumps({"proposal": proposal_forward_workload(lib, torch, net, synth.make_window(4, 10 ** 6),
+                                                                params=params)}), flush=True)
         lib.close()
         return
 
@@ -726,8 +726,9 @@ def vc_workload(lib, np, torch, w, b, reps=20):
     return res
 
 
-def proposal_forward_workload(lib, torch, net, w, reps=20):
-    """MFMA throughput of the whole proposal network on one window's flows (inference)."""
+def proposal_forward_workload(lib, torch, net, w, reps=20, params=None):
+    """MFMA throughput of the whole proposal network on one window's flows (inference), and
+    with params the time of one training step (forward, loss, backward, Adam) on it."""
     from paper_2104_06800_amd import proposal as pr
     p = w["params"]
     H, W, N = p["H"], p["W"], p["N"]
@@ -752,10 +753,29 @@ def proposal_forward_workload(lib, torch, net, w, reps=20):
     achieved = flops / (ms / 1e3) / 1e12
     log(f"proposal forward at {W}x{H}: {ms:.3f} ms, {flops / 1e9:.1f} GFLOP on real channels "
         f"({flops_stored / 1e9:.1f} stored), {achieved:.1f} TFLOP/s")
+    train_ms = None
+    if params is not None:
+        tnet = lib.net_alloc(params, train=True)
+        rho_t = torch.full((H, W), 0.1, dtype=torch.float32, device=flow.device)
+        q_t = torch.full((N, H, W), 0.9, dtype=torch.float32, device=flow.device)
+        mask = torch.ones((H, W), dtype=torch.uint8, device=flow.device)
+        loss = torch.zeros(3, dtype=torch.float64, device=flow.device)
+        step = lambda k: lib.proposal_train_step(tnet, flow, tn, rho_t, q_t, mask, 0.5, 1e-5, k, loss)
+        for k in range(3):
+            step(k + 1)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(reps):
+            step(k + 4)
+        e1.record()
+        torch.cuda.synchronize()
+        train_ms = e0.elapsed_time(e1) / reps
+        log(f"proposal training step at {W}x{H}: {train_ms:.3f} ms")
     return {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "ms": round(ms, 4), "gflop": round(flops / 1e9, 2),
             "gflop_stored": round(flops_stored / 1e9, 2),
             "frac_stored": round(flops_stored / (ms / 1e3) / 1e12 / PEAK_BF16_TFLOPS, 4),
+            "train_step_ms": None if train_ms is None else round(train_ms, 3),
             "workload": f"proposal forward {W}x{H}, N={N}, BF16 weights/activations, FP32 accumulation"}
 
 
@@ -770,7 +790,7 @@ def learned_init(lib, np, torch):
     res = pr.compare(lib, net, test, warm=False)
     summ = pr.summarize(res)
     log("learned init: " + json.dumps(summ))
-    prop = proposal_forward_workload(lib, torch, net, test[0])
+    prop = proposal_forward_workload(lib, torch, net, test[0], params=params)
     summ["held_out_windows"] = "seeds 10^6..10^6+15 of the 640x480 street recipe, N=6"
     summ["training"] = (f"{int(meta.get('train', 0))} windows, {int(meta.get('steps', 0))} Adam steps on plain-GEM "
                         "outputs")

@@ -43,6 +43,16 @@ struct ConvArgs {
     const uint16_t* mask;    // [Ho][Wo][Cout] BF16: output zeroed where mask <= 0, or null
     uint16_t* y;             // BF16 output or null
     float* yf;               // FP32 output or null
+    // heads fused into the last layer (stride-1 forward, hN > 0): rho [Ho][Wo] from channel 0,
+    // q [hN][Ho][Wo] from channels 1 .. hN (either may be null); the depth scale is |t| of
+    // hpose (FP64 pose; a non-finite scale or logit sets *hflag, when given, and gives hrmin)
+    // or htnorm when hpose is null
+    int hN;
+    float htnorm, hrmin, hrmax;
+    float* hrho;
+    float* hq;
+    const double* hpose;
+    int* hflag;
 };
 
 struct WgradArgs {
@@ -74,10 +84,13 @@ hipError_t launch_bgrad(const uint16_t* dy, int Mpix, int C, int nchunks, float*
 hipError_t launch_sum_chunks(const float* part, int n, int nchunks, float* out, hipStream_t st);
 hipError_t launch_heads(const float* o, int HW, int N, float tnorm, float rmin, float rmax, float* rho, float* q,
                         hipStream_t st);
+hipError_t launch_flag_clear(int* flag, hipStream_t st);
 hipError_t launch_start_heads(const float* o, int HW, int N, const double* pose, float rmin, float rmax, float* rho,
                               float* q, int* flag, hipStream_t st);
+// blocks of the mask count (4096 mask bytes each): the loss's count buffer holds that many ints
+inline int mask_count_blocks(int HW) { return (HW + 4095) / 4096; }
 hipError_t launch_loss(const float* o, int HW, int N, float tnorm, const float* rho_t, const float* q_t,
-                       const uint8_t* mask, float lam, float* inv_cnt, uint16_t* dout, double* part, double* loss,
+                       const uint8_t* mask, float lam, int* cnt, uint16_t* dout, double* part, double* loss,
                        hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
 

@@ -17,6 +17,10 @@ namespace {
 inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kMaxWgradChunks = 64;
+constexpr int kMaxBgradChunks = 256;
+
+// blocks of the bias-gradient sum: about 1024 pixels each, at most kMaxBgradChunks
+int bgrad_chunks(int Mpix) { return std::max(1, std::min(kMaxBgradChunks, (Mpix + 1023) / 1024)); }
 constexpr int kMaxLayerWeights = 128 * 9 * 128;
 
 int wgrad_chunks(int Cout, int Cin, int Mpix) {
@@ -36,7 +40,7 @@ struct Acts {
     float* wpart;
     float* bpart;
     double* lpart;
-    float* inv_cnt;
+    int* mask_cnt;
 };
 
 int check_net_shape(voldor_ctx ctx, int H, int W, int N) {
@@ -68,9 +72,9 @@ int layout(voldor_ctx ctx, int H, int W, bool train, hipStream_t st, Acts& A) {
     sz[k++] = al(HW * 64 * b16);     // g1
     sz[k++] = al(HW * 128 * sizeof(float));  // dup (also the single-layer backward's up grid)
     sz[k++] = al((size_t)kMaxWgradChunks * kMaxLayerWeights * sizeof(float));
-    sz[k++] = al((size_t)kMaxWgradChunks * 128 * sizeof(float));
+    sz[k++] = al((size_t)kMaxBgradChunks * 128 * sizeof(float));
     sz[k++] = al((size_t)3 * ((HW + 255) / 256) * sizeof(double));
-    sz[k++] = al(sizeof(float));     // 1 / mask count
+    sz[k++] = al(sizeof(int) * (size_t)vp::mask_count_blocks(HW));   // masked-pixel counts per span
     const int n = train ? k : nfwd;
     size_t total = 0;
     for (int i = 0; i < n; ++i) total += sz[i];
@@ -80,7 +84,7 @@ int layout(voldor_ctx ctx, int H, int W, bool train, hipStream_t st, Acts& A) {
     void** slots[19] = {(void**)&A.x, (void**)&A.a1, (void**)&A.a2, (void**)&A.a3, (void**)&A.a4, (void**)&A.a5,
                         (void**)&A.o, (void**)&A.flag, (void**)&A.go, (void**)&A.g5, (void**)&A.g4, (void**)&A.g3, (void**)&A.g2,
                         (void**)&A.g1, (void**)&A.dup, (void**)&A.wpart, (void**)&A.bpart, (void**)&A.lpart,
-                        (void**)&A.inv_cnt};
+                        (void**)&A.mask_cnt};
     std::memset(&A, 0, sizeof(A));
     for (int i = 0; i < n; ++i) {
         *slots[i] = p;
@@ -117,10 +121,36 @@ vp::ConvArgs layer_args(int L, int H, int W, const voldor_net* net, const Acts& 
     return a;
 }
 
+// heads of a forward pass, fused into the last layer's epilogue; logits (FP32 [H][W][32]) are
+// written only where asked for
+struct Heads {
+    float* rho;
+    float* q;
+    float tnorm, rmin, rmax;
+    const double* pose;
+    int* flag;
+    float* logits;
+};
+
+// the forward pass; without heads the last layer writes its FP32 output to A.o (training)
 int run_forward(voldor_ctx ctx, const voldor_net* net, int H, int W, int N, const float* flow, const Acts& A,
-                hipStream_t st) {
+                hipStream_t st, const Heads* h = nullptr) {
     VD_CHECK(vp::launch_features(flow, N, H * W, A.x, st), "feature launch");
-    for (int L = 0; L < VP_NLAYERS; ++L) VD_CHECK(vp::launch_conv(layer_args(L, H, W, net, A), 0, st), "conv launch");
+    for (int L = 0; L < VP_NLAYERS; ++L) {
+        vp::ConvArgs a = layer_args(L, H, W, net, A);
+        if (h && L == VP_NLAYERS - 1) {
+            a.yf = h->logits;
+            a.hN = N;
+            a.htnorm = h->tnorm;
+            a.hrmin = h->rmin;
+            a.hrmax = h->rmax;
+            a.hrho = h->rho;
+            a.hq = h->q;
+            a.hpose = h->pose;
+            a.hflag = h->flag;
+        }
+        VD_CHECK(vp::launch_conv(a, 0, st), "conv launch");
+    }
     return VOLDOR_OK;
 }
 
@@ -139,7 +169,7 @@ int layer_param_grads(voldor_ctx ctx, const vp::ConvArgs& f, const uint16_t* dy,
     const int nch = wgrad_chunks(f.Cout, f.Cin, Mpix);
     VD_CHECK(vp::launch_wgrad(g, nch, st), "wgrad launch");
     if (grads) VD_CHECK(vp::launch_sum_chunks(A.wpart, g.nparam, nch, grads, st), "wgrad reduce launch");
-    const int nb = std::max(1, std::min(kMaxWgradChunks, Mpix / 1024));
+    const int nb = bgrad_chunks(Mpix);
     VD_CHECK(vp::launch_bgrad(dy, Mpix, f.Cout, nb, A.bpart, st), "bgrad launch");
     if (grads) VD_CHECK(vp::launch_sum_chunks(A.bpart, f.Cout, nb, grads + g.nparam, st), "bgrad reduce launch");
     return VOLDOR_OK;
@@ -185,8 +215,9 @@ int proposal_start(voldor_ctx ctx, const voldor_net* net, int H, int W, int N, c
     if (!net || !net->params || !net->wbf16) return fail(ctx, VOLDOR_EINVAL, "null network pointer");
     Acts A;
     if ((rc = layout(ctx, H, W, false, st, A))) return rc;
-    if ((rc = run_forward(ctx, net, H, W, N, flow, A, st))) return rc;
-    VD_CHECK(vp::launch_start_heads(A.o, H * W, N, pose, rmin, rmax, idepth, rigid, A.flag, st), "start heads launch");
+    VD_CHECK(vp::launch_flag_clear(A.flag, st), "flag clear launch");
+    const Heads h = {idepth, rigid, 0.f, rmin, rmax, pose, A.flag, nullptr};
+    if ((rc = run_forward(ctx, net, H, W, N, flow, A, st, &h))) return rc;
     *flag = A.flag;
     return VOLDOR_OK;
 }
@@ -221,11 +252,8 @@ int voldor_proposal_forward(voldor_ctx ctx, const voldor_net* net, int32_t H, in
     VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
     Acts A;
     if ((rc = layout(ctx, H, W, false, st, A))) return rc;
-    if ((rc = run_forward(ctx, net, H, W, N, flow, A, st))) return rc;
-    VD_CHECK(vp::launch_heads(A.o, H * W, N, tnorm, idepth_min, idepth_max, idepth_out, rigid_out, st), "heads launch");
-    if (logits_out)
-        VD_CHECK(hipMemcpyAsync(logits_out, A.o, sizeof(float) * H * W * VP_C_HEAD, hipMemcpyDeviceToDevice, st),
-                 "logits copy");
+    const Heads h = {idepth_out, rigid_out, tnorm, idepth_min, idepth_max, nullptr, nullptr, logits_out};
+    if ((rc = run_forward(ctx, net, H, W, N, flow, A, st, &h))) return rc;
     return VOLDOR_OK;
 }
 
@@ -248,7 +276,7 @@ int voldor_proposal_train_step(voldor_ctx ctx, const voldor_net* net, int32_t H,
     if ((rc = layout(ctx, H, W, true, st, A))) return rc;
     if ((rc = run_forward(ctx, net, H, W, N, flow, A, st))) return rc;
     const int HW = H * W;
-    VD_CHECK(vp::launch_loss(A.o, HW, N, tnorm, idepth_target, rigid_target, mask, lam, A.inv_cnt, A.go, A.lpart,
+    VD_CHECK(vp::launch_loss(A.o, HW, N, tnorm, idepth_target, rigid_target, mask, lam, A.mask_cnt, A.go, A.lpart,
                              loss_out, st), "loss launch");
 
     vp::ConvArgs f[VP_NLAYERS];
@@ -347,7 +375,7 @@ int voldor_conv3x3_bf16_backward(voldor_ctx ctx, int32_t H, int32_t W, int32_t C
     // workspace: weight-gradient partials, bias partials, the gradient on the upsampled grid
     const int Mpix0 = f.Ho * f.Wo;
     const int nch = wgrad_chunks(Cout, Cin, Mpix0);
-    const int nbb = std::max(1, std::min(kMaxWgradChunks, Mpix0 / 1024));
+    const int nbb = bgrad_chunks(Mpix0);
     const size_t wbytes = al(sizeof(float) * (size_t)nch * Cout * 9 * Cin);
     const size_t bbytes = al(sizeof(float) * (size_t)nbb * Cout);
     const size_t ubytes = up ? al(sizeof(float) * (size_t)f.Hs * f.Ws * Cin) : 0;

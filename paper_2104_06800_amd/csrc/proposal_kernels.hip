@@ -36,6 +36,10 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 
 
+// heads of the last layer: rho = clip(softplus(o_0) / |t_1|, rho_min, rho_max), q_t = sigmoid(o_t)
+__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+__device__ __forceinline__ float sigmoidf(float z) { return 0.5f * (1.f + tanhf(0.5f * z)); }
+
 // ---------------------------------------------------------------------------------------
 // input features: channel 2(t-1) + c = X_t[c] / FLOW_SCALE (non-finite -> 0), 16 channels
 // ---------------------------------------------------------------------------------------
@@ -218,21 +222,26 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a) {
 // MODE 1: data gradient (taps flipped, transposed weights).  The next chunk's global
 // loads are in flight while the matrix cores work.
 // ---------------------------------------------------------------------------------------
-template <int WAVES_M, int WM, int WN, int KC, int MODE, bool UP>
+template <int WAVES_M, int WM, int WN, int KC, int MODE, bool UP, int S>
 __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
     constexpr int WAVES_N = 4 / WAVES_M;
     constexpr int TW = 32, TH = WAVES_M * WM, BN = WAVES_N * 32 * WN;
-    static_assert(!UP || (MODE == 0 && TH % 2 == 0), "upsampling: forward, even tile rows");
-    constexpr int HX = UP ? TW / 2 + 2 : TW + 2, HY = UP ? TH / 2 + 2 : TH + 2;   // halo columns, rows
+    static_assert(!UP || (MODE == 0 && TH % 2 == 0 && S == 1), "upsampling: forward, even tile rows");
+    static_assert(S == 1 || (S == 2 && MODE == 0), "stride 2: forward");
+    // halo columns, rows: a tile of TW outputs at stride S reads S (TW - 1) + 3 source columns
+    constexpr int HX = UP ? TW / 2 + 2 : S * (TW - 1) + 3, HY = UP ? TH / 2 + 2 : S * (TH - 1) + 3;
     constexpr int LD = KC + 8;                         // padded LDS pixel / weight row (bf16)
     constexpr int QA = KC / 8;                         // 16-byte units per pixel / weight row
     constexpr int NA = HY * HX * QA, NB = 9 * BN * QA; // 16-byte units of one chunk
     constexpr int UA = (NA + 255) / 256, UB = (NB + 255) / 256;
     constexpr unsigned kOut = 0x7ffffff0u;             // beyond any buffer: the load returns zeros
     // the halo and the weights of a chunk; after the last chunk the same LDS holds the tile's
-    // skip input, staged with 16-byte loads
-    constexpr int NHS = HY * HX * LD, NBS = 9 * BN * LD, NSK = TH * TW * BN;
-    __shared__ __attribute__((aligned(16))) uint16_t lds_u16[(NHS + NBS) > NSK ? (NHS + NBS) : NSK];
+    // skip input, staged with 16-byte loads, or its FP32 outputs for the heads
+    // heads: stride-1 forward blocks of 32 output channels
+    constexpr bool HEADS = MODE == 0 && !UP && S == 1 && BN == 32;
+    constexpr int NHS = HY * HX * LD, NBS = 9 * BN * LD, NSK = TH * TW * BN, NHD = HEADS ? TH * TW * (BN + 1) * 2 : 0;
+    constexpr int NLDS = (NHS + NBS) > NSK ? ((NHS + NBS) > NHD ? NHS + NBS : NHD) : (NSK > NHD ? NSK : NHD);
+    __shared__ __attribute__((aligned(16))) uint16_t lds_u16[NLDS];
     uint16_t* const Hs = lds_u16;
     uint16_t* const Bs = lds_u16 + NHS;
 
@@ -256,7 +265,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
         const int hy = pix / HX, hx = pix - hy * HX;
         // halo origin: the source pixel left of and above the tile's first tap (with UP, on
         // the stored grid, whose pixel covers upsampled positions 2s and 2s + 1)
-        const int sy = UP ? oy0 / 2 + hy - 1 : oy0 + hy - 1, sx = UP ? ox0 / 2 + hx - 1 : ox0 + hx - 1;
+        const int sy = UP ? oy0 / 2 + hy - 1 : S * oy0 + hy - 1, sx = UP ? ox0 / 2 + hx - 1 : S * ox0 + hx - 1;
         const bool ok = u < NA && sy >= 0 && sy < (UP ? a.Hx : a.Hs) && sx >= 0 && sx < (UP ? a.Wx : a.Ws);
         offA[i] = ok ? (unsigned)((((size_t)sy * a.Wx + sx) * a.Cin + 8 * q) * 2) : kOut;
         ldsA[i] = u < NA ? pix * LD + 8 * q : -1;
@@ -317,14 +326,14 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
             // UP: upsampled position (y + ky - 1) lies on stored row floor((y + ky - 1) / 2), halo
             // row floor((r + ky - 1) / 2) + 1 = (r + ky + 1) >> 1 (tile origin even), likewise columns
             const int dy = MODE == 0 ? ky : 2 - ky, dx = MODE == 0 ? kx : 2 - kx;
-            const int hcol = UP ? (col_lane + dx + 1) >> 1 : col_lane + dx;
+            const int hcol = UP ? (col_lane + dx + 1) >> 1 : S * col_lane + dx;
 #pragma unroll
             for (int kk = 0; kk < KC / 16; ++kk) {
                 const int col = 16 * kk + khalf;
                 bf16x8 A[WM], B[WN];
 #pragma unroll
                 for (int i = 0; i < WM; ++i) {
-                    const int hrow = UP ? (wr0 + i + dy + 1) >> 1 : wr0 + i + dy;
+                    const int hrow = UP ? (wr0 + i + dy + 1) >> 1 : S * (wr0 + i) + dy;
                     A[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&Hs[(hrow * HX + hcol) * LD + col]));
                 }
 #pragma unroll
@@ -344,7 +353,12 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
     // i = 8(e/4) + 4(lane/32) + e%4; the element offsets of the 16 columns are multiples of
     // Cout shared by every row and channel tile
     const bool full = ox0 + TW <= a.Wo;
-    const bool plain = !a.addf && !a.mask && !a.yf && a.y;
+    // heads (first channel block, no skip input): the tile's FP32 outputs go to LDS as
+    // [pixel][BN + 1] (padded against bank conflicts on the pixel reads)
+    const bool heads = HEADS && a.hN > 0 && n0 == 0;
+    float* const hv = reinterpret_cast<float*>(lds_u16);
+    if (heads) __syncthreads();                         // every wave is done with the last chunk
+    const bool plain = !a.addf && !a.mask && !a.yf && a.y && !heads;
     const int xb = ox0 + 4 * (lane >> 5);
     // skip input of the tile into LDS as [row][column][BN channels]: rows of BN channels are
     // contiguous in the source, so one 16-byte load per 8 channels (out of range: zeros)
@@ -402,7 +416,33 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
                 if (a.mask && !(bf2f(a.mask[o]) > 0.f)) v = 0.f;
                 if (a.y) a.y[o] = __builtin_bit_cast(uint16_t, (__bf16)v);
                 if (a.yf) a.yf[o] = v;
+                if (heads) hv[((wr0 + t) * TW + 4 * (lane >> 5) + dxe) * (BN + 1) + nl] = v;
             }
+        }
+    }
+    if (heads) {
+        // one thread per pixel of the tile: rho from channel 0, q_t from channel 1 + t
+        __syncthreads();
+        float tn = a.htnorm;
+        if (a.hpose) {
+            const double t0 = a.hpose[3], t1 = a.hpose[4], t2 = a.hpose[5];
+            tn = (float)sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+        }
+        for (int p = tid; p < TH * TW; p += 256) {
+            const int oy = oy0 + p / TW, ox = ox0 + p % TW;
+            if (oy >= a.Ho || ox >= a.Wo) continue;
+            const size_t px = (size_t)oy * a.Wo + ox;
+            const float* hp = hv + p * (BN + 1);
+            if (a.hrho) {
+                // the learned start checks the scale and the logit; the plain forward clips
+                // whatever comes
+                const float v = hp[0];
+                const bool ok = !a.hpose || (isfinite(tn) && tn > 0.f && isfinite(v));
+                if (!ok && a.hflag) atomicOr(a.hflag, 1);
+                a.hrho[px] = ok ? fminf(fmaxf(softplusf(v) / tn, a.hrmin), a.hrmax) : a.hrmin;
+            }
+            if (a.hq)
+                for (int t = 0; t < a.hN; ++t) a.hq[(size_t)t * a.Ho * a.Wo + px] = sigmoidf(hp[1 + t]);
         }
     }
 }
@@ -480,15 +520,42 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     }
 }
 
-// bias gradient partials: per (channel, pixel chunk)
-__global__ void k_bgrad(const uint16_t* __restrict__ dy, int Mpix, int C, int nchunks, float* __restrict__ part) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+// bias gradient partials: block b sums the pixels [b chunk, (b + 1) chunk) of dy [Mpix][C].
+// Thread t takes the 8 channels of group g = t % G (G = C / 8; one 16-byte load per pixel
+// when dy is 16-byte aligned) on the pixels mbeg + p, mbeg + p + P, ... (p = t / G,
+// P = 256 / G); the P sums of a channel are added in LDS in a fixed order.
+__global__ void __launch_bounds__(256) k_bgrad(const uint16_t* __restrict__ dy, int Mpix, int C, int nchunks,
+                                               float* __restrict__ part) {
+    extern __shared__ float red_b[];                    // [P][C]
+    const int G = C / 8, P = 256 / G;
+    const int t = threadIdx.x, g = t % G, pl = t / G;
     const int chunk = (Mpix + nchunks - 1) / nchunks;
-    const int mbeg = blockIdx.y * chunk, mend = min(Mpix, mbeg + chunk);
-    float s = 0.f;
-    for (int m = mbeg; m < mend; ++m) s += bf2f(dy[(size_t)m * C + c]);
-    part[(size_t)blockIdx.y * C + c] = s;
+    const int mbeg = blockIdx.x * chunk, mend = min(Mpix, mbeg + chunk);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (pl < P) {
+        if ((reinterpret_cast<uintptr_t>(dy) & 15) == 0) {
+            for (int m = mbeg + pl; m < mend; m += P) {
+                const u32x4 v = *reinterpret_cast<const u32x4*>(dy + (size_t)m * C + 8 * g);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    acc[2 * e] += __uint_as_float(v[e] << 16);
+                    acc[2 * e + 1] += __uint_as_float(v[e] & 0xffff0000u);
+                }
+            }
+        } else {
+            for (int m = mbeg + pl; m < mend; m += P)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc[e] += bf2f(dy[(size_t)m * C + 8 * g + e]);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) red_b[pl * C + 8 * g + e] = acc[e];
+    }
+    __syncthreads();
+    for (int c = t; c < C; c += 256) {
+        float s = 0.f;
+        for (int q = 0; q < P; ++q) s += red_b[q * C + c];
+        part[(size_t)blockIdx.x * C + c] = s;
+    }
 }
 
 // out[i] = sum over chunks of part[chunk][i], fixed order
@@ -501,11 +568,8 @@ __global__ void k_sum_chunks(const float* __restrict__ part, int n, int nchunks,
 }
 
 // ---------------------------------------------------------------------------------------
-// heads: rho = clip(softplus(o_0) / |t_1|, rho_min, rho_max), q_t = sigmoid(o_t)
+// heads as a pass of their own over FP32 logits (the same arithmetic as the fused epilogue)
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
-__device__ __forceinline__ float sigmoidf(float z) { return 0.5f * (1.f + tanhf(0.5f * z)); }
-
 __global__ void k_heads(const float* __restrict__ o, int HW, int N, float tnorm, float rmin, float rmax,
                         float* __restrict__ rho, float* __restrict__ q) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -538,6 +602,11 @@ __global__ void k_start_heads(const float* __restrict__ o, int HW, int N, const 
     for (int t = 0; t < N; ++t) q[(size_t)t * HW + j] = sigmoidf(oj[1 + t]);
 }
 
+hipError_t launch_flag_clear(int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, st, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_start_heads(const float* o, int HW, int N, const double* pose, float rmin, float rmax, float* rho,
                               float* q, int* flag, hipStream_t st) {
     hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, st, flag);
@@ -551,26 +620,40 @@ hipError_t launch_start_heads(const float* o, int HW, int N, const double* pose,
 // gradient w.r.t. o (BF16, zero on unused channels) and per-block FP64 partial sums
 // [L1 sum, mask count, BCE sum]
 // ---------------------------------------------------------------------------------------
-// 1 / max(1, number of masked pixels), one block
-__global__ void __launch_bounds__(1024) k_mask_count(const uint8_t* __restrict__ mask, int HW, float* __restrict__ inv) {
-    __shared__ int red[16];
+// number of masked pixels in each 4096-byte span of the mask (one block per span, 16 bytes per
+// thread); integer partial counts, so their sum is exact in any order
+__global__ void __launch_bounds__(256) k_mask_count(const uint8_t* __restrict__ mask, int HW, int* __restrict__ cnt) {
+    __shared__ int red[4];
+    const int j0 = (blockIdx.x * 256 + threadIdx.x) * 16;
     int c = 0;
-    for (int j = threadIdx.x; j < HW; j += 1024) c += mask[j] != 0;
+    if (j0 + 16 <= HW && (reinterpret_cast<uintptr_t>(mask) & 15) == 0) {
+        const u32x4 v = *reinterpret_cast<const u32x4*>(mask + j0);
+        // a byte b is non-zero iff the top bit of ((b & 0x7f) + 0x7f) | b is set (no carry
+        // leaves the byte)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c += __popc((((v[e] & 0x7f7f7f7fu) + 0x7f7f7f7fu) | v[e]) & 0x80808080u);
+    } else {
+        for (int j = j0; j < min(HW, j0 + 16); ++j) c += mask[j] != 0;
+    }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int s = 0;
-        for (int i = 0; i < 16; ++i) s += red[i];
-        inv[0] = 1.0f / (float)max(s, 1);
-    }
+    if (threadIdx.x == 0) cnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 __global__ void k_loss(const float* __restrict__ o, int HW, int N, float tnorm, const float* __restrict__ rho_t,
                        const float* __restrict__ q_t, const uint8_t* __restrict__ mask, float lam,
-                       const float* __restrict__ inv_cnt_p, uint16_t* __restrict__ dout, double* __restrict__ part) {
+                       const int* __restrict__ mcnt, int ncnt, uint16_t* __restrict__ dout, double* __restrict__ part) {
     __shared__ double red[3][4];
-    const float inv_cnt = inv_cnt_p[0];
+    __shared__ float inv_s;
+    if (threadIdx.x < 64) {                             // 1 / max(1, masked pixels)
+        int c = 0;
+        for (int i = threadIdx.x; i < ncnt; i += 64) c += mcnt[i];
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+        if (threadIdx.x == 0) inv_s = 1.0f / (float)max(c, 1);
+    }
+    __syncthreads();
+    const float inv_cnt = inv_s;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     double l1 = 0.0, cnt = 0.0, bce = 0.0;
     if (j < HW) {
@@ -611,13 +694,25 @@ __global__ void k_loss(const float* __restrict__ o, int HW, int N, float tnorm, 
     }
 }
 
-// loss[0] = L, loss[1] = L1 part, loss[2] = BCE part (fixed-order sums of the partials)
-__global__ void k_loss_finish(const double* __restrict__ part, int nb, int N, int HW, float lam,
-                              double* __restrict__ loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < 3; ++k)
-        for (int b = 0; b < nb; ++b) s[k] += part[(size_t)k * nb + b];
+// loss[0] = L, loss[1] = L1 part, loss[2] = BCE part: one block of 256 threads, thread t sums
+// the partials t, t + 256, ... and the 256 sums are added pairwise in LDS (a fixed order)
+__global__ void __launch_bounds__(256) k_loss_finish(const double* __restrict__ part, int nb, int N, int HW,
+                                                     float lam, double* __restrict__ loss) {
+    __shared__ double red[3][256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < 3; ++k) {
+        double a = 0.0;
+        for (int b = t; b < nb; b += 256) a += part[(size_t)k * nb + b];
+        red[k][t] = a;
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+            for (int k = 0; k < 3; ++k) red[k][t] += red[k][t + h];
+        __syncthreads();
+    }
+    if (t != 0) return;
+    const double s[3] = {red[0][0], red[1][0], red[2][0]};
     const double l1 = s[0] / fmax(s[1], 1.0), bce = s[2] / ((double)N * HW);
     loss[0] = l1 + (double)lam * bce;
     loss[1] = l1;
@@ -671,13 +766,17 @@ static void conv2_launch(const ConvArgs& a, int mode, hipStream_t st) {
     else hipLaunchKernelGGL((k_conv2<WAVES_M, WM, WN, KC, 1>), grid, dim3(256), 0, st, a);
 }
 
-template <int WAVES_M, int WM, int WN, int KC>
+template <int WAVES_M, int WM, int WN, int KC, int S>
 static void halo_launch(const ConvArgs& a, int mode, hipStream_t st) {
     constexpr int TH = WAVES_M * WM, BN = (4 / WAVES_M) * 32 * WN;
     const dim3 grid((unsigned)(((a.Wo + 31) / 32) * ((a.Ho + TH - 1) / TH)), (unsigned)((a.Cout + BN - 1) / BN));
-    if (mode == 1) hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 1, false>), grid, dim3(256), 0, st, a);
-    else if (a.up) hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 0, true>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 0, false>), grid, dim3(256), 0, st, a);
+    if constexpr (S == 2) {
+        hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 0, false, 2>), grid, dim3(256), 0, st, a);
+    } else {
+        if (mode == 1) hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 1, false, 1>), grid, dim3(256), 0, st, a);
+        else if (a.up) hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 0, true, 1>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 0, false, 1>), grid, dim3(256), 0, st, a);
+    }
 }
 
 // Stride-1 layers (forward with or without upsampling; data gradient without): the halo
@@ -685,10 +784,18 @@ static void halo_launch(const ConvArgs& a, int mode, hipStream_t st) {
 // output channels take two such blocks per tile, which keeps 3 blocks per CU) or x 32
 // channels (chunks of 32).
 static bool launch_halo(const ConvArgs& a, int mode, hipStream_t st) {
-    if (a.stride != 1 || (mode == 1 && a.up) || (a.up && (a.Hs != 2 * a.Hx || a.Ws != 2 * a.Wx))) return false;
-    if (a.Cout % 64 == 0) halo_launch<4, 2, 2, 16>(a, mode, st);
-    else if (a.Cin % 32 == 0) halo_launch<4, 2, 1, 32>(a, mode, st);
-    else halo_launch<4, 2, 1, 16>(a, mode, st);
+    if ((mode == 1 && (a.up || a.stride != 1)) || (a.up && (a.stride != 1 || a.Hs != 2 * a.Hx || a.Ws != 2 * a.Wx)))
+        return false;
+    // heads: stride-1 forward, 32 output channels (one 32-channel block), no skip input
+    if (a.hN > 0 && (mode != 0 || a.up || a.stride != 1 || a.skip || a.Cout != 32 || a.hN >= a.Cout)) return false;
+    if (a.stride == 2) {                                // 4-row tiles: the halo spans 2 x 32 + 1 columns
+        if (a.Cout % 64 != 0) return false;
+        halo_launch<4, 1, 2, 16, 2>(a, mode, st);
+        return true;
+    }
+    if (a.Cout % 64 == 0) halo_launch<4, 2, 2, 16, 1>(a, mode, st);
+    else if (a.Cin % 32 == 0) halo_launch<4, 2, 1, 32, 1>(a, mode, st);
+    else halo_launch<4, 2, 1, 16, 1>(a, mode, st);
     return true;
 }
 
@@ -706,7 +813,9 @@ static void launch_conv2(const ConvArgs& a, int mode, hipStream_t st) {
 }
 
 hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t st) {
-    if (!launch_halo(a, mode, st)) launch_conv2(a, mode, st);
+    if (launch_halo(a, mode, st)) return hipGetLastError();
+    if (a.hN > 0) return hipErrorInvalidValue;            // fused heads: stride-1 forward only
+    launch_conv2(a, mode, st);
     return hipGetLastError();
 }
 
@@ -724,7 +833,9 @@ hipError_t launch_wgrad(const WgradArgs& a, int nchunks, hipStream_t st) {
 }
 
 hipError_t launch_bgrad(const uint16_t* dy, int Mpix, int C, int nchunks, float* part, hipStream_t st) {
-    hipLaunchKernelGGL(k_bgrad, dim3((unsigned)((C + 63) / 64), (unsigned)nchunks), dim3(64), 0, st, dy, Mpix, C,
+    if (C % 8 != 0 || C > 2048) return hipErrorInvalidValue;
+    const int P = 256 / (C / 8);
+    hipLaunchKernelGGL(k_bgrad, dim3((unsigned)nchunks), dim3(256), (size_t)P * C * sizeof(float), st, dy, Mpix, C,
                        nchunks, part);
     return hipGetLastError();
 }
@@ -741,13 +852,13 @@ hipError_t launch_heads(const float* o, int HW, int N, float tnorm, float rmin, 
 }
 
 hipError_t launch_loss(const float* o, int HW, int N, float tnorm, const float* rho_t, const float* q_t,
-                       const uint8_t* mask, float lam, float* inv_cnt, uint16_t* dout, double* part, double* loss,
+                       const uint8_t* mask, float lam, int* cnt, uint16_t* dout, double* part, double* loss,
                        hipStream_t st) {
-    const int nb = (HW + 255) / 256;
-    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(1024), 0, st, mask, HW, inv_cnt);
+    const int nb = (HW + 255) / 256, ncnt = mask_count_blocks(HW);
+    hipLaunchKernelGGL(k_mask_count, dim3(ncnt), dim3(256), 0, st, mask, HW, cnt);
     hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, st, o, HW, N, tnorm, rho_t, q_t, mask, lam,
-                       (const float*)inv_cnt, dout, part);
-    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(64), 0, st, part, nb, N, HW, lam, loss);
+                       (const int*)cnt, ncnt, dout, part);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, st, part, nb, N, HW, lam, loss);
     return hipGetLastError();
 }
 

@@ -57,6 +57,11 @@ CASES = [
     dict(H=37, W=70, Cin=128, Cout=128, stride=1, up=0, relu=1, skip=False),
     dict(H=21, W=45, Cin=64, Cout=32, stride=1, up=0, relu=0, skip=True),
     dict(H=13, W=34, Cin=128, Cout=64, stride=1, up=1, relu=1, skip=False),
+    # stride-2 halo tiles (4 rows of 32 outputs, 9 x 65 source pixels) with ragged edges; a
+    # 32-channel output takes the staged kernel
+    dict(H=37, W=131, Cin=64, Cout=128, stride=2, up=0, relu=1, skip=False),
+    dict(H=22, W=70, Cin=16, Cout=64, stride=2, up=0, relu=0, skip=True),
+    dict(H=21, W=45, Cin=16, Cout=32, stride=2, up=0, relu=1, skip=False),
 ]
 
 
@@ -148,6 +153,9 @@ def test_network_forward(lib):
     rr, qr = P.heads(got.astype(np.float64), N, 1.7, 0.005, 0.5)
     np.testing.assert_allclose(np_(rho), rr, rtol=1e-5, atol=1e-7)
     np.testing.assert_allclose(np_(q), qr, rtol=1e-5, atol=1e-6)
+    # the heads are fused into the last layer: without the logits they are the same bits
+    rho2, q2, _ = lib.proposal_forward(net, torch.from_numpy(flow).cuda(), 1.7, 0.005, 0.5)
+    assert np.array_equal(np_(rho2), np_(rho)) and np.array_equal(np_(q2), np_(q))
 
 
 def test_training_step(lib):
