@@ -49,6 +49,9 @@ struct ConvArgs {
     // or htnorm when hpose is null
     int hN;
     float htnorm, hrmin, hrmax;
+    // data gradient of an upsampling layer (MODE 1, stride 1, even Ho and Wo): the result
+    // summed over 2 x 2 blocks onto the (Ho / 2) x (Wo / 2) grid, where mask, y and yf live
+    int pool;
     float* hrho;
     float* hq;
     const double* hpose;
@@ -77,8 +80,8 @@ struct AdamArgs {
 
 hipError_t launch_features(const float* flow, int N, int HW, uint16_t* x, hipStream_t st);
 hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t st);
-hipError_t launch_pool2(const float* g, int H2, int W2, int C, const uint16_t* mask, uint16_t* out, float* outf,
-                        hipStream_t st);
+// output channels per block of the staged weight-gradient kernel (32 input channels, 9 taps)
+inline int wgrad_co_tile(int Cout) { return Cout % 128 == 0 ? 128 : (Cout % 64 == 0 ? 64 : 32); }
 hipError_t launch_wgrad(const WgradArgs& a, int nchunks, hipStream_t st);
 hipError_t launch_bgrad(const uint16_t* dy, int Mpix, int C, int nchunks, float* part, hipStream_t st);
 hipError_t launch_sum_chunks(const float* part, int n, int nchunks, float* out, hipStream_t st);

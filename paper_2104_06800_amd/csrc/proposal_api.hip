@@ -23,11 +23,13 @@ constexpr int kMaxBgradChunks = 256;
 int bgrad_chunks(int Mpix) { return std::max(1, std::min(kMaxBgradChunks, (Mpix + 1023) / 1024)); }
 constexpr int kMaxLayerWeights = 128 * 9 * 128;
 
+// pixel chunks of a weight-gradient launch: about 512 blocks, at least 256 pixels per chunk,
+// and at most kMaxWgradChunks x kMaxLayerWeights partial sums (chunks x parameters)
 int wgrad_chunks(int Cout, int Cin, int Mpix) {
-    const int tiles = (Cout / 32) * 9 * ((Cin + 31) / 32);
-    int n = (4096 + tiles - 1) / tiles;
-    n = std::max(1, std::min(n, std::min(kMaxWgradChunks, (Mpix + 63) / 64)));
-    return n;
+    const int tiles = (Cout / vp::wgrad_co_tile(Cout)) * ((Cin + 31) / 32);
+    const int nparam = Cout * 9 * Cin;
+    const int cap = std::min(kMaxWgradChunks * kMaxLayerWeights / nparam, (Mpix + 255) / 256);
+    return std::max(1, std::min((512 + tiles - 1) / tiles, cap));
 }
 
 struct Acts {
@@ -36,7 +38,6 @@ struct Acts {
     int* flag;          // learned start: fallback flag
     // training
     uint16_t *go, *g5, *g4, *g3, *g2, *g1;
-    float* dup;
     float* wpart;
     float* bpart;
     double* lpart;
@@ -70,7 +71,6 @@ int layout(voldor_ctx ctx, int H, int W, bool train, hipStream_t st, Acts& A) {
     sz[k++] = al(HW2 * 128 * b16);   // g3
     sz[k++] = al(HW2 * 128 * b16);   // g2
     sz[k++] = al(HW * 64 * b16);     // g1
-    sz[k++] = al(HW * 128 * sizeof(float));  // dup (also the single-layer backward's up grid)
     sz[k++] = al((size_t)kMaxWgradChunks * kMaxLayerWeights * sizeof(float));
     sz[k++] = al((size_t)kMaxBgradChunks * 128 * sizeof(float));
     sz[k++] = al((size_t)3 * ((HW + 255) / 256) * sizeof(double));
@@ -81,9 +81,9 @@ int layout(voldor_ctx ctx, int H, int W, bool train, hipStream_t st, Acts& A) {
     int rc = vdc::ensure_buffer(ctx, &ctx->net_ws, &ctx->net_ws_bytes, total, st);
     if (rc) return rc;
     char* p = (char*)ctx->net_ws;
-    void** slots[19] = {(void**)&A.x, (void**)&A.a1, (void**)&A.a2, (void**)&A.a3, (void**)&A.a4, (void**)&A.a5,
+    void** slots[18] = {(void**)&A.x, (void**)&A.a1, (void**)&A.a2, (void**)&A.a3, (void**)&A.a4, (void**)&A.a5,
                         (void**)&A.o, (void**)&A.flag, (void**)&A.go, (void**)&A.g5, (void**)&A.g4, (void**)&A.g3, (void**)&A.g2,
-                        (void**)&A.g1, (void**)&A.dup, (void**)&A.wpart, (void**)&A.bpart, (void**)&A.lpart,
+                        (void**)&A.g1, (void**)&A.wpart, (void**)&A.bpart, (void**)&A.lpart,
                         (void**)&A.mask_cnt};
     std::memset(&A, 0, sizeof(A));
     for (int i = 0; i < n; ++i) {
@@ -292,9 +292,10 @@ int voldor_proposal_train_step(voldor_ctx ctx, const voldor_net* net, int32_t H,
     // c5: dy = g5 (also the gradient reaching a1 through the skip)
     if ((rc = layer_param_grads(ctx, f[4], A.g5, grads + vp::layer_off(4), A, st))) return rc;
     d = dgrad_args(f[4], wt(4), A.g5);
-    d.yf = A.dup;                        // on the upsampled grid
+    d.pool = 1;                          // summed back onto the half grid, then c4's ReLU
+    d.mask = A.a4;
+    d.y = A.g4;
     VD_CHECK(vp::launch_conv(d, 1, st), "dgrad launch");
-    VD_CHECK(vp::launch_pool2(A.dup, H, W, 128, A.a4, A.g4, nullptr, st), "pool launch");
     // c4, c3
     if ((rc = layer_param_grads(ctx, f[3], A.g4, grads + vp::layer_off(3), A, st))) return rc;
     d = dgrad_args(f[3], wt(3), A.g4);
@@ -372,19 +373,17 @@ int voldor_conv3x3_bf16_backward(voldor_ctx ctx, int32_t H, int32_t W, int32_t C
     f.Wo = (f.Ws - 1) / stride + 1;
     f.stride = stride; f.up = up;
     f.x = x;
-    // workspace: weight-gradient partials, bias partials, the gradient on the upsampled grid
+    // workspace: weight-gradient partials, bias partials
     const int Mpix0 = f.Ho * f.Wo;
     const int nch = wgrad_chunks(Cout, Cin, Mpix0);
     const int nbb = bgrad_chunks(Mpix0);
     const size_t wbytes = al(sizeof(float) * (size_t)nch * Cout * 9 * Cin);
     const size_t bbytes = al(sizeof(float) * (size_t)nbb * Cout);
-    const size_t ubytes = up ? al(sizeof(float) * (size_t)f.Hs * f.Ws * Cin) : 0;
-    if ((rc = vdc::ensure_buffer(ctx, &ctx->net_ws, &ctx->net_ws_bytes, wbytes + bbytes + ubytes, st))) return rc;
+    if ((rc = vdc::ensure_buffer(ctx, &ctx->net_ws, &ctx->net_ws_bytes, wbytes + bbytes, st))) return rc;
     Acts A;
     std::memset(&A, 0, sizeof(A));
     A.wpart = (float*)ctx->net_ws;
     A.bpart = (float*)((char*)ctx->net_ws + wbytes);
-    A.dup = (float*)((char*)ctx->net_ws + wbytes + bbytes);
     if (dw || db) {
         vp::WgradArgs g;
         g.Hs = f.Hs; g.Ws = f.Ws; g.Hx = f.Hx; g.Wx = f.Wx; g.Cin = f.Cin;
@@ -401,14 +400,9 @@ int voldor_conv3x3_bf16_backward(voldor_ctx ctx, int32_t H, int32_t W, int32_t C
     }
     if (dx) {
         vp::ConvArgs d = dgrad_args(f, w_t, dy);
-        if (up) {
-            d.yf = A.dup;
-            VD_CHECK(vp::launch_conv(d, 1, st), "dgrad launch");
-            VD_CHECK(vp::launch_pool2(A.dup, f.Hs, f.Ws, Cin, nullptr, nullptr, dx, st), "pool launch");
-        } else {
-            d.yf = dx;
-            VD_CHECK(vp::launch_conv(d, 1, st), "dgrad launch");
-        }
+        d.pool = up ? 1 : 0;             // upsampling: summed back onto the stored grid
+        d.yf = dx;
+        VD_CHECK(vp::launch_conv(d, 1, st), "dgrad launch");
     }
     return VOLDOR_OK;
 }

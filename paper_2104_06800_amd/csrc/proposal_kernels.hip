@@ -1,16 +1,20 @@
 // Learned depth / rigidness proposal on gfx950: BF16 3x3 convolutions as implicit GEMMs on
 // the matrix cores (v_mfma_f32_32x32x16_bf16), FP32 accumulation, NHWC activations.
 //
-//   k_conv2           MODE 0: y = act(conv3x3(x) + b [+ skip])    (stride 1 or 2, optional 2x
-//                              nearest upsampling of the input)
+//   k_conv_halo       the fast path: a block stages the halo of its output tile and the
+//                     weights of a chunk of input channels in LDS with buffer loads.
+//                     MODE 0: y = act(conv3x3(x) + b [+ skip]), stride 1 (optional 2x
+//                     nearest upsampling of the input) or 2, optionally with the heads fused;
 //                     MODE 1: data gradient dx = conv3x3^T(dy) with the transposed weights
-//                              [Cin][3][3][Cout], optional "+ add" and "* (mask > 0)" epilogue
-//                     GEMM view: M = output pixels, N = output channels, K = 9 * input
-//                     channels, operand tiles staged through LDS (see the kernel).  Cin is a
-//                     multiple of 16, Cout of 16 (a partial channel tile reads zero weights).
-//   k_wgrad           dW[co][tap][ci] = sum_m dy[m][co] x_tap(m)[ci] per pixel chunk (FP32
-//                     partials), k_sum_chunks reduces them in a fixed order
-//   k_features, k_pool2, k_heads, k_loss (+ finish), k_adam: the element-wise rest.
+//                     [Cin][3][3][Cout], optional "+ add" and "* (mask > 0)" epilogue; stride-2
+//                     layers by sub-pixel classes, upsampling layers pooled 2x2 in registers
+//   k_conv2           the general LDS-staged kernel for every other shape (same arithmetic
+//                     roles; Cin a multiple of 16, Cout of 16)
+//   k_wgrad2          dW[co][tap][ci] = sum_m dy[m][co] x_tap(m)[ci] per pixel chunk (FP32
+//                     partials), dy and the 9 im2col slices staged pixel-contiguous in LDS;
+//                     k_wgrad the fallback for unaligned pointers; k_sum_chunks reduces the
+//                     partials in a fixed order; k_bgrad the bias gradient
+//   k_features, k_heads, k_loss (+ finish), k_adam: the element-wise rest.
 //
 // MFMA operand layout (32x32x16, wave64): lane l supplies A[i = l%32][k = 8(l/32) .. +7] and
 // B[k = 8(l/32) .. +7][j = l%32]; the 16 accumulators of lane l hold D[i][j = l%32] for
@@ -223,13 +227,20 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a) {
 // loads are in flight while the matrix cores work.
 // ---------------------------------------------------------------------------------------
 template <int WAVES_M, int WM, int WN, int KC, int MODE, bool UP, int S>
-__global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_conv_halo(ConvArgs a) {
     constexpr int WAVES_N = 4 / WAVES_M;
     constexpr int TW = 32, TH = WAVES_M * WM, BN = WAVES_N * 32 * WN;
     static_assert(!UP || (MODE == 0 && TH % 2 == 0 && S == 1), "upsampling: forward, even tile rows");
-    static_assert(S == 1 || (S == 2 && MODE == 0), "stride 2: forward");
-    // halo columns, rows: a tile of TW outputs at stride S reads S (TW - 1) + 3 source columns
-    constexpr int HX = UP ? TW / 2 + 2 : S * (TW - 1) + 3, HY = UP ? TH / 2 + 2 : S * (TH - 1) + 3;
+    static_assert(S == 1 || S == 2, "stride 1 or 2");
+    // SUB: data gradient of a stride-2 layer by sub-pixel classes.  Output (2y' + py, 2x' + px)
+    // takes tap (ky, kx) only where py + 1 - ky and px + 1 - kx are even, from gradient pixel
+    // (y' + (py + 1 - ky) / 2, x' + (px + 1 - kx) / 2): per class (blockIdx.z = 2 py + px) a
+    // stride-1 problem with 1, 2, 2 or 4 taps on tiles of the class's sub-grid.
+    constexpr bool SUB = MODE == 1 && S == 2;
+    // halo columns, rows: a tile of TW outputs at stride S reads S (TW - 1) + 3 source columns;
+    // a SUB tile reads TW + 1
+    constexpr int HX = SUB ? TW + 1 : (UP ? TW / 2 + 2 : S * (TW - 1) + 3);
+    constexpr int HY = SUB ? TH + 1 : (UP ? TH / 2 + 2 : S * (TH - 1) + 3);
     constexpr int LD = KC + 8;                         // padded LDS pixel / weight row (bf16)
     constexpr int QA = KC / 8;                         // 16-byte units per pixel / weight row
     constexpr int NA = HY * HX * QA, NB = 9 * BN * QA; // 16-byte units of one chunk
@@ -247,8 +258,9 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr0 = (wave % WAVES_M) * WM, wn0 = (wave / WAVES_M) * 32 * WN;
-    const int ntx = (a.Wo + TW - 1) / TW;
+    const int ntx = ((SUB ? (a.Wo + 1) / 2 : a.Wo) + TW - 1) / TW;
     const int ox0 = (int)(blockIdx.x % (unsigned)ntx) * TW, oy0 = (int)(blockIdx.x / (unsigned)ntx) * TH;
+    const int py = SUB ? (int)(blockIdx.z >> 1) : 0, px = SUB ? (int)(blockIdx.z & 1) : 0;
     const int n0 = blockIdx.y * BN;
     const int nchunks = a.Cin / KC;
 
@@ -265,7 +277,8 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
         const int hy = pix / HX, hx = pix - hy * HX;
         // halo origin: the source pixel left of and above the tile's first tap (with UP, on
         // the stored grid, whose pixel covers upsampled positions 2s and 2s + 1)
-        const int sy = UP ? oy0 / 2 + hy - 1 : S * oy0 + hy - 1, sx = UP ? ox0 / 2 + hx - 1 : S * ox0 + hx - 1;
+        const int sy = SUB ? oy0 + hy : (UP ? oy0 / 2 + hy - 1 : S * oy0 + hy - 1);
+        const int sx = SUB ? ox0 + hx : (UP ? ox0 / 2 + hx - 1 : S * ox0 + hx - 1);
         const bool ok = u < NA && sy >= 0 && sy < (UP ? a.Hx : a.Hs) && sx >= 0 && sx < (UP ? a.Wx : a.Ws);
         offA[i] = ok ? (unsigned)((((size_t)sy * a.Wx + sx) * a.Cin + 8 * q) * 2) : kOut;
         ldsA[i] = u < NA ? pix * LD + 8 * q : -1;
@@ -275,7 +288,9 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
         const int u = tid + 256 * i;
         const int row = u / QA, q = u - row * QA;       // row = tap * BN + local channel
         const int tap = row / BN, n = n0 + (row - tap * BN);
-        const bool ok = u < NB && n < a.Cout;
+        // SUB: only the class's taps are used
+        const bool in_class = !SUB || (!((py + 1 - tap / 3) & 1) && !((px + 1 - tap % 3) & 1));
+        const bool ok = u < NB && n < a.Cout && in_class;
         offB[i] = ok ? (unsigned)((((size_t)n * 9 + tap) * a.Cin + 8 * q) * 2) : kOut;
         ldsB[i] = u < NB ? row * LD + 8 * q : -1;
     }
@@ -325,15 +340,17 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
             // data gradient: source (y + 1 - ky, x + 1 - kx) = halo (r + 2 - ky, col + 2 - kx);
             // UP: upsampled position (y + ky - 1) lies on stored row floor((y + ky - 1) / 2), halo
             // row floor((r + ky - 1) / 2) + 1 = (r + ky + 1) >> 1 (tile origin even), likewise columns
-            const int dy = MODE == 0 ? ky : 2 - ky, dx = MODE == 0 ? kx : 2 - kx;
-            const int hcol = UP ? (col_lane + dx + 1) >> 1 : S * col_lane + dx;
+            if (SUB && (((py + 1 - ky) & 1) || ((px + 1 - kx) & 1))) continue;
+            const int dy = SUB ? (py + 1 - ky) >> 1 : (MODE == 0 ? ky : 2 - ky);
+            const int dx = SUB ? (px + 1 - kx) >> 1 : (MODE == 0 ? kx : 2 - kx);
+            const int hcol = SUB ? col_lane + dx : (UP ? (col_lane + dx + 1) >> 1 : S * col_lane + dx);
 #pragma unroll
             for (int kk = 0; kk < KC / 16; ++kk) {
                 const int col = 16 * kk + khalf;
                 bf16x8 A[WM], B[WN];
 #pragma unroll
                 for (int i = 0; i < WM; ++i) {
-                    const int hrow = UP ? (wr0 + i + dy + 1) >> 1 : S * (wr0 + i) + dy;
+                    const int hrow = SUB ? wr0 + i + dy : (UP ? (wr0 + i + dy + 1) >> 1 : S * (wr0 + i) + dy);
                     A[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&Hs[(hrow * HX + hcol) * LD + col]));
                 }
 #pragma unroll
@@ -352,7 +369,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
     // epilogue: lane holds D[i][j = lane % 32] of M tile (row) wr0 + t for columns
     // i = 8(e/4) + 4(lane/32) + e%4; the element offsets of the 16 columns are multiples of
     // Cout shared by every row and channel tile
-    const bool full = ox0 + TW <= a.Wo;
+    const bool full = !SUB && ox0 + TW <= a.Wo;
     // heads (first channel block, no skip input): the tile's FP32 outputs go to LDS as
     // [pixel][BN + 1] (padded against bank conflicts on the pixel reads)
     const bool heads = HEADS && a.hN > 0 && n0 == 0;
@@ -381,6 +398,92 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
         }
         __syncthreads();
     }
+    if constexpr (MODE == 1 && S == 1 && WM == 2) {
+        if (a.pool) {
+            // the data gradient of an upsampling layer: sums over 2 x 2 output blocks, which lie
+            // in one lane (rows t = 0, 1 of an even tile row; columns e, e + 1 for e % 4 = 0, 2),
+            // in the order (row 0 pair) + (row 1 pair); mask, y and yf on the half grid
+            const int Hp = a.Ho / 2, Wp = a.Wo / 2, Y = (oy0 + wr0) / 2;
+            // every mask value is read before the first store (the compiler cannot tell the
+            // output from the mask, so a store would hold back every later load)
+            uint32_t keep[WN];
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+                const int n = n0 + wn0 + 32 * j + col_lane;
+                keep[j] = 0xffffu;
+                if (!a.mask || n >= a.Cout || Y >= Hp) continue;
+#pragma unroll
+                for (int e = 0; e < 16; e += 2) {
+                    const int X = (xb + 8 * (e >> 2) + (e & 3)) / 2;
+                    if (X < Wp && !(bf2f(a.mask[((size_t)Y * Wp + X) * a.Cout + n]) > 0.f)) keep[j] &= ~(1u << e);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+                const int n = n0 + wn0 + 32 * j + col_lane;
+                if (n >= a.Cout || Y >= Hp) continue;
+                const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+                for (int e = 0; e < 16; e += 2) {
+                    const int X = (xb + 8 * (e >> 2) + (e & 3)) / 2;
+                    if (X >= Wp) continue;
+                    const size_t o = ((size_t)Y * Wp + X) * a.Cout + n;
+                    float v = ((acc[0][j][e] + bias) + (acc[0][j][e + 1] + bias)) +
+                              ((acc[1][j][e] + bias) + (acc[1][j][e + 1] + bias));
+                    if (!((keep[j] >> e) & 1u)) v = 0.f;
+                    if (a.y) a.y[o] = __builtin_bit_cast(uint16_t, (__bf16)v);
+                    if (a.yf) a.yf[o] = v;
+                }
+            }
+            return;
+        }
+    }
+    // data gradient: the mask and skip tiles go through LDS ([pixel][BN channels], 16-byte
+    // loads; a SUB tile's outputs are every other pixel), the mask kept as one bit per element
+    uint32_t keepbits[WM * WN];
+#pragma unroll
+    for (int i = 0; i < WM * WN; ++i) keepbits[i] = 0xffffu;
+    if constexpr (MODE == 1) {
+        const int bytesO = (int)min((size_t)0x7fffffff, (size_t)a.Ho * a.Wo * a.Cout * 2);
+        auto stage = [&](const uint16_t* src) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, bytesO, 0x00020000);
+            constexpr int QS = BN / 8, NSU = TH * TW * QS;
+#pragma unroll
+            for (int i = 0; i < (NSU + 255) / 256; ++i) {
+                const int u = tid + 256 * i;
+                if (u >= NSU) break;
+                const int pix = u / QS, q = u - pix * QS;
+                const int r = pix / TW, x = pix - r * TW;
+                const int oy = SUB ? 2 * (oy0 + r) + py : oy0 + r, ox = SUB ? 2 * (ox0 + x) + px : ox0 + x;
+                const unsigned off = (oy < a.Ho && ox < a.Wo && n0 + 8 * q < a.Cout)
+                                         ? (unsigned)((((size_t)oy * a.Wo + ox) * a.Cout + n0 + 8 * q) * 2) : kOut;
+                *reinterpret_cast<u32x4*>(&lds_u16[pix * BN + 8 * q]) = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+            }
+        };
+        if (a.mask) {
+            __syncthreads();                            // every wave is done with the last chunk
+            stage(a.mask);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                for (int t = 0; t < WM; ++t) {
+                    uint32_t b = 0;
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int dxe = 8 * (e >> 2) + (e & 3);
+                        const uint16_t m = lds_u16[((wr0 + t) * TW + 4 * (lane >> 5) + dxe) * BN + wn0 + 32 * j + col_lane];
+                        b |= (bf2f(m) > 0.f ? 1u : 0u) << e;
+                    }
+                    keepbits[j * WM + t] = b;
+                }
+        }
+        if (a.skip) {
+            __syncthreads();
+            stage(a.skip);
+            __syncthreads();
+        }
+    }
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
         const int nl = wn0 + 32 * j + col_lane, n = n0 + nl;
@@ -388,7 +491,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
         const float bias = a.bias ? a.bias[n] : 0.f;
 #pragma unroll
         for (int t = 0; t < WM; ++t) {
-            const int oy = oy0 + wr0 + t;
+            const int oy = SUB ? 2 * (oy0 + wr0 + t) + py : oy0 + wr0 + t;
             if (oy >= a.Ho) continue;
             const size_t o0 = ((size_t)oy * a.Wo + xb) * a.Cout + n;
             if (plain && full) {
@@ -403,14 +506,31 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
                 }
                 continue;
             }
+            if constexpr (MODE == 1) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int dxe = 8 * (e >> 2) + (e & 3);
+                    const int ox = SUB ? 2 * (xb + dxe) + px : xb + dxe;
+                    if (ox >= a.Wo) continue;
+                    const size_t o = ((size_t)oy * a.Wo + ox) * a.Cout + n;
+                    float v = acc[t][j][e] + bias;
+                    if (a.skip) v += bf2f(lds_u16[((wr0 + t) * TW + 4 * (lane >> 5) + dxe) * BN + nl]);
+                    if (a.addf) v += a.addf[o];
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    if (!((keepbits[j * WM + t] >> e) & 1u)) v = 0.f;
+                    if (a.y) a.y[o] = __builtin_bit_cast(uint16_t, (__bf16)v);
+                    if (a.yf) a.yf[o] = v;
+                }
+                continue;
+            }
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int dxe = 8 * (e >> 2) + (e & 3);
-                if (xb + dxe >= a.Wo) continue;
-                const size_t o = o0 + (size_t)dxe * a.Cout;
+                const int ox = xb + dxe;
+                if (ox >= a.Wo) continue;
+                const size_t o = ((size_t)oy * a.Wo + ox) * a.Cout + n;
                 float v = acc[t][j][e] + bias;
                 if (skip_lds) v += bf2f(lds_u16[((wr0 + t) * TW + 4 * (lane >> 5) + dxe) * BN + nl]);
-                else if (a.skip) v += bf2f(a.skip[o]);
                 if (a.addf) v += a.addf[o];
                 if (a.relu) v = fmaxf(v, 0.f);
                 if (a.mask && !(bf2f(a.mask[o]) > 0.f)) v = 0.f;
@@ -445,25 +565,6 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs a) {
                 for (int t = 0; t < a.hN; ++t) a.hq[(size_t)t * a.Ho * a.Wo + px] = sigmoidf(hp[1 + t]);
         }
     }
-}
-
-// ---------------------------------------------------------------------------------------
-// 2x2 sum pooling of an FP32 gradient on the upsampled grid, times the ReLU mask of the
-// pooled grid's activation, stored as BF16 (and FP32 when asked)
-// ---------------------------------------------------------------------------------------
-__global__ void k_pool2(const float* __restrict__ g, int H2, int W2, int C, const uint16_t* __restrict__ mask,
-                        uint16_t* __restrict__ out, float* __restrict__ outf) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int H = H2 / 2, W = W2 / 2;
-    if (i >= (size_t)H * W * C) return;
-    const int c = (int)(i % C);
-    const int p = (int)(i / C);
-    const int y = p / W, x = p - y * W;
-    const size_t b = ((size_t)(2 * y) * W2 + 2 * x) * C + c;
-    float v = (g[b] + g[b + C]) + (g[b + (size_t)W2 * C] + g[b + (size_t)W2 * C + C]);
-    if (mask && !(bf2f(mask[i]) > 0.f)) v = 0.f;
-    if (out) out[i] = f2bf(v);
-    if (outf) outf[i] = v;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -520,6 +621,126 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// weight gradient, LDS-staged: block = (CO_T output channels) x (32 input channels) x all 9
+// taps x a chunk of output pixels.  D[co][ci] (one 32 x 32 tile per tap and 32 output
+// channels) = sum over pixels m of dy[m][co] x_tap(m)[ci]: the contraction runs over pixels,
+// so both operands are staged pixel-contiguous.  Per step of KP = 32 pixels a thread loads
+// one unit, 8 pixels x 8 channels (eight 16-byte loads: dy rows, or the source pixels of one
+// tap), transposes it in registers and writes 8 channel rows of 8 pixels to LDS:
+// dy^T [CO_T][KP] and the im2col slices [9][32][KP].  The next step's loads are in flight
+// while the matrix cores work.  The 9 CO_T / 32 output tiles are split evenly over the 4 waves.
+// ---------------------------------------------------------------------------------------
+template <int CO_T>
+__global__ void __launch_bounds__(256) k_wgrad2(WgradArgs a) {
+    constexpr int CI_T = 32, KP = 32, LDP = KP + 8;     // padded LDS row (bf16): 80 bytes
+    constexpr int NT = 9 * (CO_T / 32), MAXT = (NT + 3) / 4;
+    constexpr int NA = (CO_T / 8) * (KP / 8), NB = 9 * (CI_T / 8) * (KP / 8);
+    static_assert(NA + NB <= 256, "one staging unit per thread");
+    __shared__ __attribute__((aligned(16))) uint16_t As[CO_T * LDP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[9 * CI_T * LDP];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int co0 = blockIdx.x * CO_T, ci0 = blockIdx.y * CI_T;
+    const int Wo = a.Wo, Hs = a.Hs, Ws = a.Ws, Wx = a.Wx, Cin = a.Cin, Cout = a.Cout;
+    const int stride = a.stride, up = a.up;
+    const int Mpix = a.Ho * Wo;
+    const int chunk = (Mpix + gridDim.z - 1) / gridDim.z;
+    const int mbeg = blockIdx.z * chunk, mend = min(Mpix, mbeg + chunk);
+
+    // this thread's staging unit: an A unit (8 output channels g, 8 pixels p8) or a B unit
+    // (tap, 8 input channels g, 8 pixels p8)
+    const bool isA = tid < NA, isB = !isA && tid < NA + NB;
+    const int ub = isA ? tid : tid - NA;
+    const int tap = isA ? 0 : ub / ((CI_T / 8) * (KP / 8));
+    const int ur = isA ? ub : ub - tap * ((CI_T / 8) * (KP / 8));
+    const int g = isA ? ur % (CO_T / 8) : ur % (CI_T / 8);
+    const int p8 = isA ? ur / (CO_T / 8) : ur / (CI_T / 8);
+    const int ky = tap / 3, kx = tap - 3 * ky;
+    const bool active = isA || (isB && ci0 + 8 * g < Cin);
+    const int dst = isA ? (8 * g) * LDP + 8 * p8 : (tap * CI_T + 8 * g) * LDP + 8 * p8;
+    uint16_t* const dstp = isA ? As + dst : Bs + dst;
+    const uint16_t* const dyb = a.dy + co0 + 8 * g;
+    const uint16_t* const xb = a.x + ci0 + 8 * g;
+
+    u32x4 r[8];
+    const int t0 = (wave * NT) / 4, t1 = ((wave + 1) * NT) / 4;
+    f32x16 acc[MAXT];
+#pragma unroll
+    for (int i = 0; i < MAXT; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[i][e] = 0.f;
+    const int col_lane = lane & 31, khalf = 8 * (lane >> 5);
+
+    for (int m0 = mbeg - KP; m0 < mend; m0 += KP) {
+        if (m0 >= mbeg) {
+            // r[e] holds channels 0..7 of pixel e; row c of the unit: pixels 0..7 of channel c
+            __syncthreads();                            // the previous step's reads are done
+            if (isA || isB) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    u32x4 w;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t lo = r[2 * q][c >> 1], hi = r[2 * q + 1][c >> 1];
+                        w[q] = (c & 1) ? ((lo >> 16) | (hi & 0xffff0000u)) : ((lo & 0xffffu) | (hi << 16));
+                    }
+                    *reinterpret_cast<u32x4*>(dstp + c * LDP) = w;
+                }
+            }
+            __syncthreads();
+        }
+        // the next step's unit: eight 16-byte loads (zeros off the chunk, the grid or Cin)
+        const int mn = m0 + KP;
+        if (mn < mend) {
+            const int mf = mn + 8 * p8;
+            int oy = mf / Wo, ox = mf - oy * Wo;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int m = mf + e;
+                int sy = oy * stride + ky - 1, sx = ox * stride + kx - 1;
+                const bool ok = active && m < mend && (isA || (sy >= 0 && sy < Hs && sx >= 0 && sx < Ws));
+                if (up) { sy >>= 1; sx >>= 1; }
+                const size_t off = isA ? (size_t)m * Cout : ((size_t)sy * Wx + sx) * Cin;
+                r[e] = ok ? *reinterpret_cast<const u32x4*>((isA ? dyb : xb) + off) : u32x4{0u, 0u, 0u, 0u};
+                if (++ox == Wo) { ox = 0; ++oy; }
+            }
+        }
+        if (m0 < mbeg) continue;
+#pragma unroll
+        for (int kk = 0; kk < KP / 16; ++kk) {
+            const int col = 16 * kk + khalf;
+#pragma unroll
+            for (int i = 0; i < MAXT; ++i) {
+                const int t = t0 + i;
+                if (t >= t1) break;
+                const int c = t / 9, tp = t - 9 * c;
+                const bf16x8 A = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(
+                                                            &As[(32 * c + col_lane) * LDP + col]));
+                const bf16x8 B = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(
+                                                            &Bs[(tp * CI_T + col_lane) * LDP + col]));
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[i], 0, 0, 0);
+            }
+        }
+    }
+
+    // lane holds D[co = 32 c + 8(e/4) + 4(lane/32) + e%4][ci = lane % 32]
+    float* const part = a.part + (size_t)blockIdx.z * a.nparam;
+#pragma unroll
+    for (int i = 0; i < MAXT; ++i) {
+        const int t = t0 + i;
+        if (t >= t1) break;
+        const int c = t / 9, tp = t - 9 * c;
+        const int ci = ci0 + col_lane;
+        if (ci >= Cin) continue;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int co = co0 + 32 * c + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            part[((size_t)co * 9 + tp) * Cin + ci] = acc[i][e];
+        }
+    }
+}
+
 // bias gradient partials: block b sums the pixels [b chunk, (b + 1) chunk) of dy [Mpix][C].
 // Thread t takes the 8 channels of group g = t % G (G = C / 8; one 16-byte load per pixel
 // when dy is 16-byte aligned) on the pixels mbeg + p, mbeg + p + P, ... (p = t / G,
@@ -558,13 +779,24 @@ __global__ void __launch_bounds__(256) k_bgrad(const uint16_t* __restrict__ dy, 
     }
 }
 
-// out[i] = sum over chunks of part[chunk][i], fixed order
-__global__ void k_sum_chunks(const float* __restrict__ part, int n, int nchunks, float* __restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// out[i] = sum over chunks of part[chunk][i] in a fixed order: block = 64 outputs x 16 rows,
+// row r sums the chunks r, r + 16, ..., then the 16 row sums are added in order
+__global__ void __launch_bounds__(1024) k_sum_chunks(const float* __restrict__ part, int n, int nchunks,
+                                                     float* __restrict__ out) {
+    __shared__ float red[16][64];
+    const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + x;
     float s = 0.f;
-    for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * n + i];
-    out[i] = s;
+    if (i < n)
+        for (int c = y; c < nchunks; c += 16) s += part[(size_t)c * n + i];
+    red[y][x] = s;
+    __syncthreads();
+    if (y == 0 && i < n) {
+        float t = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) t += red[r][x];
+        out[i] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -657,28 +889,36 @@ __global__ void k_loss(const float* __restrict__ o, int HW, int N, float tnorm, 
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     double l1 = 0.0, cnt = 0.0, bce = 0.0;
     if (j < HW) {
-        const float* oj = o + (size_t)j * VP_C_HEAD;
-        uint16_t* dj = dout + (size_t)j * VP_C_HEAD;
-        const float s = softplusf(oj[0]);
+        // logits 0 .. N (N <= 8) as three 16-byte loads; the gradient row (32 BF16, zero past
+        // channel N) as four 16-byte stores
+        const float4* o4 = reinterpret_cast<const float4*>(o + (size_t)j * VP_C_HEAD);
+        const float4 l0 = o4[0], l1v = o4[1], l2 = o4[2];
+        const float z[9] = {l0.x, l0.y, l0.z, l0.w, l1v.x, l1v.y, l1v.z, l1v.w, l2.x};
+        uint32_t wd[VP_C_HEAD / 2];
+#pragma unroll
+        for (int k = 0; k < VP_C_HEAD / 2; ++k) wd[k] = 0u;
+        const float s = softplusf(z[0]);
         const float d = s - rho_t[j] * tnorm;
         const bool mk = mask[j] != 0;
         float g0 = 0.f;
         if (mk) {
             l1 = fabs((double)d);
             cnt = 1.0;
-            g0 = (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f)) * sigmoidf(oj[0]) * inv_cnt;
+            g0 = (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f)) * sigmoidf(z[0]) * inv_cnt;
         }
-        dj[0] = f2bf(g0);
+        wd[0] = f2bf(g0);
         const float inv_q = lam / (float)((size_t)N * HW);
-        for (int c = 1; c < VP_C_HEAD; ++c) {
-            float g = 0.f;
-            if (c <= N) {
-                const float z = oj[c], qt = q_t[(size_t)(c - 1) * HW + j];
-                bce += (double)(softplusf(z) - qt * z);
-                g = (sigmoidf(z) - qt) * inv_q;
-            }
-            dj[c] = f2bf(g);
+#pragma unroll
+        for (int c = 1; c <= 8; ++c) {
+            if (c > N) break;
+            const float zc = z[c], qt = q_t[(size_t)(c - 1) * HW + j];
+            bce += (double)(softplusf(zc) - qt * zc);
+            const uint32_t h = f2bf((sigmoidf(zc) - qt) * inv_q);
+            wd[c >> 1] |= (c & 1) ? (h << 16) : h;
         }
+        u32x4* dq = reinterpret_cast<u32x4*>(dout + (size_t)j * VP_C_HEAD);
+#pragma unroll
+        for (int q = 0; q < VP_C_HEAD / 8; ++q) dq[q] = u32x4{wd[4 * q], wd[4 * q + 1], wd[4 * q + 2], wd[4 * q + 3]};
     }
     double v[3] = {l1, cnt, bce};
 #pragma unroll
@@ -766,12 +1006,19 @@ static void conv2_launch(const ConvArgs& a, int mode, hipStream_t st) {
     else hipLaunchKernelGGL((k_conv2<WAVES_M, WM, WN, KC, 1>), grid, dim3(256), 0, st, a);
 }
 
+// S = 1: stride 1 (forward, upsampling forward or data gradient); 2: stride-2 forward;
+// -2: data gradient of a stride-2 layer by sub-pixel classes
 template <int WAVES_M, int WM, int WN, int KC, int S>
 static void halo_launch(const ConvArgs& a, int mode, hipStream_t st) {
     constexpr int TH = WAVES_M * WM, BN = (4 / WAVES_M) * 32 * WN;
     const dim3 grid((unsigned)(((a.Wo + 31) / 32) * ((a.Ho + TH - 1) / TH)), (unsigned)((a.Cout + BN - 1) / BN));
     if constexpr (S == 2) {
         hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 0, false, 2>), grid, dim3(256), 0, st, a);
+    } else if constexpr (S == -2) {
+        // sub-pixel data gradient: tiles of the largest class's grid, one z slice per class
+        const int Hq = (a.Ho + 1) / 2, Wq = (a.Wo + 1) / 2;
+        const dim3 gq((unsigned)(((Wq + 31) / 32) * ((Hq + TH - 1) / TH)), (unsigned)((a.Cout + BN - 1) / BN), 4u);
+        hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 1, false, 2>), gq, dim3(256), 0, st, a);
     } else {
         if (mode == 1) hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 1, false, 1>), grid, dim3(256), 0, st, a);
         else if (a.up) hipLaunchKernelGGL((k_conv_halo<WAVES_M, WM, WN, KC, 0, true, 1>), grid, dim3(256), 0, st, a);
@@ -784,13 +1031,16 @@ static void halo_launch(const ConvArgs& a, int mode, hipStream_t st) {
 // output channels take two such blocks per tile, which keeps 3 blocks per CU) or x 32
 // channels (chunks of 32).
 static bool launch_halo(const ConvArgs& a, int mode, hipStream_t st) {
-    if ((mode == 1 && (a.up || a.stride != 1)) || (a.up && (a.stride != 1 || a.Hs != 2 * a.Hx || a.Ws != 2 * a.Wx)))
-        return false;
+    if ((mode == 1 && a.up) || (a.up && (a.stride != 1 || a.Hs != 2 * a.Hx || a.Ws != 2 * a.Wx))) return false;
     // heads: stride-1 forward, 32 output channels (one 32-channel block), no skip input
     if (a.hN > 0 && (mode != 0 || a.up || a.stride != 1 || a.skip || a.Cout != 32 || a.hN >= a.Cout)) return false;
-    if (a.stride == 2) {                                // 4-row tiles: the halo spans 2 x 32 + 1 columns
+    // pooled data gradient: stride 1, even output grid, no skip / addend / activation
+    if (a.pool && (mode != 1 || a.up || a.stride != 1 || (a.Ho & 1) || (a.Wo & 1) || a.skip || a.addf || a.relu))
+        return false;
+    if (a.stride == 2) {
         if (a.Cout % 64 != 0) return false;
-        halo_launch<4, 1, 2, 16, 2>(a, mode, st);
+        if (mode == 1) halo_launch<4, 2, 2, 16, -2>(a, mode, st);   // sub-pixel classes
+        else halo_launch<4, 1, 2, 16, 2>(a, mode, st);              // 4-row tiles: 2 x 32 + 1 halo columns
         return true;
     }
     if (a.Cout % 64 == 0) halo_launch<4, 2, 2, 16, 1>(a, mode, st);
@@ -814,19 +1064,22 @@ static void launch_conv2(const ConvArgs& a, int mode, hipStream_t st) {
 
 hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t st) {
     if (launch_halo(a, mode, st)) return hipGetLastError();
-    if (a.hN > 0) return hipErrorInvalidValue;            // fused heads: stride-1 forward only
+    if (a.hN > 0 || a.pool) return hipErrorInvalidValue;  // fused heads, pooling: the halo kernel only
     launch_conv2(a, mode, st);
     return hipGetLastError();
 }
 
-hipError_t launch_pool2(const float* g, int H2, int W2, int C, const uint16_t* mask, uint16_t* out, float* outf,
-                        hipStream_t st) {
-    const size_t n = (size_t)(H2 / 2) * (W2 / 2) * C;
-    hipLaunchKernelGGL(k_pool2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, H2, W2, C, mask, out, outf);
-    return hipGetLastError();
-}
-
 hipError_t launch_wgrad(const WgradArgs& a, int nchunks, hipStream_t st) {
+    // the staged kernel reads 16-byte channel groups: both arrays 16-byte aligned
+    const bool aligned = ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.dy)) & 15) == 0;
+    if (aligned && a.Cin % 8 == 0) {
+        const int cot = wgrad_co_tile(a.Cout);
+        const dim3 grid((unsigned)(a.Cout / cot), (unsigned)((a.Cin + 31) / 32), (unsigned)nchunks);
+        if (cot == 128) hipLaunchKernelGGL(k_wgrad2<128>, grid, dim3(256), 0, st, a);
+        else if (cot == 64) hipLaunchKernelGGL(k_wgrad2<64>, grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(k_wgrad2<32>, grid, dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)(a.Cout / 32), (unsigned)(9 * ((a.Cin + 31) / 32)), (unsigned)nchunks);
     hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, a);
     return hipGetLastError();
@@ -841,7 +1094,7 @@ hipError_t launch_bgrad(const uint16_t* dy, int Mpix, int C, int nchunks, float*
 }
 
 hipError_t launch_sum_chunks(const float* part, int n, int nchunks, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, n, nchunks, out);
+    hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, st, part, n, nchunks, out);
     return hipGetLastError();
 }
 
