@@ -44,6 +44,28 @@ struct PoseF {          // rotation (row-major) and translation, FP32 copy of a 
     int pad[2];
 };
 
+// The frame pose tables are not written by the kernels that evaluate energies: their reads
+// go through the constant address space, so a wave-uniform read is a scalar load (scalar
+// cache, SGPR operands) rather than three vector loads per pixel and frame
+struct PoseTD {
+    float t[3];
+    float d[9];
+};
+__device__ __forceinline__ PoseTD pose_td(const PoseF* P, int t) {
+    typedef const PoseF __attribute__((address_space(4))) CPoseF;
+    const CPoseF* p = (const CPoseF*)(P) + t;
+    PoseTD r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r.t[i] = p->t[i];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r.d[i] = p->d[i];
+    return r;
+}
+__device__ __forceinline__ bool pose_ident(const PoseF* P, int t) {
+    typedef const PoseF __attribute__((address_space(4))) CPoseF;
+    return ((const CPoseF*)(P) + t)->ident != 0;
+}
+
 struct PoseD {          // FP64 rotation matrix (row-major) and translation of a frame
     double R[9];
     double t[3];
@@ -440,11 +462,11 @@ __device__ __forceinline__ void pix_geometry(const Win& w, const PoseF* __restri
 __device__ __forceinline__ bool prior_z(const Win& w, const PoseF* __restrict__ P, const float* __restrict__ prior,
                                         const Pix& c, int k, float rho, float& z) {
     float rh, inv_phi;
-    if (P[w.N + k].ident) {
+    if (pose_ident(P, w.N + k)) {
         rh = c.rh[k];
         inv_phi = rho;
     } else {
-        const PoseF& T = P[w.N + k];
+        const PoseTD T = pose_td(P, w.N + k);
         const float Qx = fmaf(rho, T.t[0], c.px[k]);
         const float Qy = fmaf(rho, T.t[1], c.py[k]);
         const float Qz = fmaf(rho, T.t[2], c.pz[k]);
@@ -486,7 +508,7 @@ __device__ __forceinline__ void frame_residuals(const Win& w, const PoseF* __res
 #pragma unroll
     for (int t = 0; t < VD_NMAX; ++t) {
         if (t < w.N) {
-            const PoseF& T = P[t];
+            const PoseTD T = pose_td(P, t);
             const float Dx = fmaf(rho, T.t[0], fmaf(T.d[0], c.x0, fmaf(T.d[1], c.x1, T.d[2])));
             const float Dy = fmaf(rho, T.t[1], fmaf(T.d[3], c.x0, fmaf(T.d[4], c.x1, T.d[5])));
             const float Dz = fmaf(rho, T.t[2], fmaf(T.d[6], c.x0, fmaf(T.d[7], c.x1, T.d[8])));
@@ -573,7 +595,7 @@ __device__ __forceinline__ energy_t energy2_costs(const Win& w, const PoseF* __r
 template <bool B2>
 __device__ __forceinline__ float frame_cost(const Win& w, const PoseF* __restrict__ P, const float4* __restrict__ flow2,
                                             const Pix& c, float rho, int t) {
-    const PoseF& T = P[t];
+    const PoseTD T = pose_td(P, t);
     const float Dx = fmaf(rho, T.t[0], fmaf(T.d[0], c.x0, fmaf(T.d[1], c.x1, T.d[2])));
     const float Dy = fmaf(rho, T.t[1], fmaf(T.d[3], c.x0, fmaf(T.d[4], c.x1, T.d[5])));
     const float Dz = fmaf(rho, T.t[2], fmaf(T.d[6], c.x0, fmaf(T.d[7], c.x1, T.d[8])));
@@ -587,7 +609,7 @@ __device__ __forceinline__ float frame_cost(const Win& w, const PoseF* __restric
     if (t == 0) {
         fx = c.f1x; fy = c.f1y; fok = c.ok1;
     } else {
-        const PoseF& Tp = P[t - 1];
+        const PoseTD Tp = pose_td(P, t - 1);
         const float Ex = fmaf(rho, Tp.t[0], fmaf(Tp.d[0], c.x0, fmaf(Tp.d[1], c.x1, Tp.d[2])));
         const float Ey = fmaf(rho, Tp.t[1], fmaf(Tp.d[3], c.x0, fmaf(Tp.d[4], c.x1, Tp.d[5])));
         const float Ez = fmaf(rho, Tp.t[2], fmaf(Tp.d[6], c.x0, fmaf(Tp.d[7], c.x1, Tp.d[8])));
@@ -648,7 +670,7 @@ __device__ __forceinline__ energy_t energy2_bounded(const Win& w, const PoseF* _
 #pragma unroll
     for (int t = 0; t < VD_NMAX; ++t) {
         if (t >= w.N) break;
-        const PoseF& T = P[t];
+        const PoseTD T = pose_td(P, t);
         const float Dx = fmaf(rho, T.t[0], fmaf(T.d[0], c.x0, fmaf(T.d[1], c.x1, T.d[2])));
         const float Dy = fmaf(rho, T.t[1], fmaf(T.d[3], c.x0, fmaf(T.d[4], c.x1, T.d[5])));
         const float Dz = fmaf(rho, T.t[2], fmaf(T.d[6], c.x0, fmaf(T.d[7], c.x1, T.d[8])));
@@ -701,7 +723,7 @@ __device__ __forceinline__ void energy2_bounded_m(const Win& w, const PoseF* __r
 #pragma unroll
     for (int t = 0; t < VD_NMAX; ++t) {
         if (t >= w.N || live == 0u) break;
-        const PoseF& T = P[t];
+        const PoseTD T = pose_td(P, t);
         float dx[M], dy[M], fx[M], fy[M];
         bool zok[M], fok[M];
 #pragma unroll
