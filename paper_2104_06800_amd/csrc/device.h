@@ -393,22 +393,40 @@ __device__ __forceinline__ bool sample_flow(const float2* __restrict__ F, int H,
 
 // Same sample from the row-pair layout F2[y][x] = (X(x, y), X(x, y + 1)) (rows 0..H-2): the
 // four taps are 32 contiguous bytes.  Arithmetic identical to sample_flow.
-__device__ __forceinline__ bool sample_flow2(const float4* __restrict__ F2, int H, int W, float x, float y,
-                                             float& fx, float& fy) {
-    const bool inside = (x >= 0.f) && (x <= (float)(W - 1)) && (y >= 0.f) && (y <= (float)(H - 1));
-    float xs = inside ? x : 0.f, ys = inside ? y : 0.f;
+// In two parts, so that callers can issue several gathers before the first blend: the
+// fetch (position, weights, the two 16-byte loads) and the blend.
+struct FlowTap {
+    float4 l, r;
+    float ax, ay;
+    bool inside;
+};
+__device__ __forceinline__ FlowTap fetch_flow2(const float4* __restrict__ F2, int H, int W, float x, float y) {
+    FlowTap f;
+    f.inside = (x >= 0.f) && (x <= (float)(W - 1)) && (y >= 0.f) && (y <= (float)(H - 1));
+    float xs = f.inside ? x : 0.f, ys = f.inside ? y : 0.f;
     int x0 = (int)xs, y0 = (int)ys;
     x0 = min(x0, W - 2);
     y0 = min(y0, H - 2);
-    const float ax = xs - (float)x0, ay = ys - (float)y0;
+    f.ax = xs - (float)x0;
+    f.ay = ys - (float)y0;
     const unsigned o = __umul24((unsigned)y0, (unsigned)W) + (unsigned)x0;
     const float4* q = (const float4*)((const char*)F2 + (o << 4));
-    const float4 l = q[0], r = q[1];
+    f.l = q[0];
+    f.r = q[1];
+    return f;
+}
+__device__ __forceinline__ bool blend_flow2(const FlowTap& f, float& fx, float& fy) {
+    const float4 l = f.l, r = f.r;
+    const float ax = f.ax, ay = f.ay;
     const float tx = fmaf(ax, r.x - l.x, l.x), ty = fmaf(ax, r.y - l.y, l.y);
     const float bx = fmaf(ax, r.z - l.z, l.z), by = fmaf(ax, r.w - l.w, l.w);
     fx = fmaf(ay, bx - tx, tx);
     fy = fmaf(ay, by - ty, ty);
-    return inside && isfinite(fx) && isfinite(fy);
+    return f.inside && isfinite(fx) && isfinite(fy);
+}
+__device__ __forceinline__ bool sample_flow2(const float4* __restrict__ F2, int H, int W, float x, float y,
+                                             float& fx, float& fy) {
+    return blend_flow2(fetch_flow2(F2, H, W, x, y), fx, fy);
 }
 
 // Block index remapped so that each of the 8 XCDs (own L2; workgroups are dispatched to
@@ -723,6 +741,17 @@ __device__ __forceinline__ void energy2_bounded_m(const Win& w, const PoseF* __r
 #pragma unroll
     for (int t = 0; t < VD_NMAX; ++t) {
         if (t >= w.N || live == 0u) break;
+        // the gathers first, without branches: their positions are the previous frame's
+        // reprojections, so the loads are in flight together during this frame's
+        // reprojection; a pruned candidate fetches the in-range tap at (0, 0), unused
+        FlowTap tap[M];
+        if (t > 0) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const bool lv = (live >> m) & 1u;
+                tap[m] = fetch_flow2(flow2 + t * plane, w.H, w.W, lv ? c.u + dpx[m] : -1.f, lv ? c.v + dpy[m] : -1.f);
+            }
+        }
         const PoseTD T = pose_td(P, t);
         float dx[M], dy[M], fx[M], fy[M];
         bool zok[M], fok[M];
@@ -737,11 +766,14 @@ __device__ __forceinline__ void energy2_bounded_m(const Win& w, const PoseF* __r
             const float iz = rcp(Qz);
             dx[m] = w.fx * fmaf(-c.x0, Dz, Dx) * iz;
             dy[m] = w.fy * fmaf(-c.x1, Dz, Dy) * iz;
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
             fx[m] = 0.f; fy[m] = 0.f; fok[m] = false;
             if (t == 0) {
                 fx[m] = c.f1x; fy[m] = c.f1y; fok[m] = c.ok1;
             } else if ((live >> m) & 1u) {
-                fok[m] = sample_flow2(flow2 + t * plane, w.H, w.W, c.u + dpx[m], c.v + dpy[m], fx[m], fy[m]);
+                fok[m] = blend_flow2(tap[m], fx[m], fy[m]);
             }
         }
 #pragma unroll

@@ -473,10 +473,10 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
             if (e < bE) { bE = e; bV = rc; bS = 2; }
         }
         // the candidates of a draw are evaluated in groups of PG against the best before the
-        // group, then merged in slot order: the same winner and energy as one at a time.  With
-        // priors the per-pixel context is larger and single candidates keep more waves resident;
-        // groups of 4 hold too many registers for the gathers they overlap.
-        constexpr int PG = PR ? 1 : 2;
+        // group, then merged in slot order: the same winner and energy as one at a time.  A
+        // group's flow gathers of a frame are issued together; a whole Philox draw per group
+        // (pairs with priors, whose per-pixel context is larger) at 4 waves per SIMD.
+        constexpr int PG = PR ? 2 : 4;
         for (int gi = 0; gi < G; ++gi) {
             const uint4 r = philox10(make_uint4((uint32_t)p.li, (uint32_t)gi, word2, w.window_id), w.key0, w.key1);
             const uint32_t words[4] = {r.x, r.y, r.z, r.w};
@@ -784,8 +784,9 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
 
 // LC: the E-only and scan-only launches of a level with few long chains (the coarse
 // lattice): forward-backward as a segmented scan, and the streamlined serial scan
+// 4 waves per SIMD (up to 128 VGPRs): the candidate groups' gathers need the registers
 template <bool B2, bool PR, bool LC>
-__global__ void __launch_bounds__(VD_BLOCK)
+__global__ void __launch_bounds__(VD_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     extern __shared__ __align__(16) float lds[];
     level_body<B2, PR, LC>(w, g, B, do_e, do_m, xcd_block(blockIdx.x, gridDim.x), lds);
@@ -1332,8 +1333,8 @@ __global__ void __launch_bounds__(VD_BLOCK) k_setup_batch(const PrepItem* __rest
 // mode 0: fused level pass (do_e / do_m of the item); 1: phase A; 2: phase A2; 3: E-only or
 // scan-only pass of the coarse level (long chains)
 template <bool B2, bool PR, int MODE>
-__global__ void __launch_bounds__(VD_BLOCK) k_level_batch(const LevelItem* __restrict__ items,
-                                                          const int* __restrict__ blk2item) {
+__global__ void __launch_bounds__(VD_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+k_level_batch(const LevelItem* __restrict__ items, const int* __restrict__ blk2item) {
     extern __shared__ __align__(16) float lds[];
     const int gb = xcd_block(blockIdx.x, gridDim.x);
     const LevelItem& it = items[blk2item[gb]];
