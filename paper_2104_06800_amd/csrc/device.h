@@ -724,11 +724,11 @@ __device__ __forceinline__ energy_t energy2_bounded(const Win& w, const PoseF* _
 }
 
 // M candidates against one bound with their frames in lockstep.  Each candidate keeps the
-// running sum and (non-strict) stop test of energy2_bounded, so every returned value is
-// exactly what energy2_bounded returns for that candidate and bound; the flow gathers of
-// the live candidates of a frame are in flight together.  Bit m of live selects
+// running sum and stop test of energy2_bounded (STRICT as there), so every returned value
+// is exactly what energy2_bounded returns for that candidate and bound; the flow gathers of
+// the candidates of a frame are in flight together.  Bit m of live selects
 // candidate m; an unselected candidate's value is meaningless.
-template <bool B2, bool PR, int M>
+template <bool B2, bool PR, int M, bool STRICT = false>
 __device__ __forceinline__ void energy2_bounded_m(const Win& w, const PoseF* __restrict__ P,
                                                   const float4* __restrict__ flow2, const float* __restrict__ prior,
                                                   const Pix& c, const float* rho, unsigned live, energy_t bound,
@@ -782,7 +782,7 @@ __device__ __forceinline__ void energy2_bounded_m(const Win& w, const PoseF* __r
                 const bool ok = zprev[m] && zok[m] && fok[m];
                 const float ex = (dx[m] - dpx[m]) - fx[m], ey = (dy[m] - dpy[m]) - fy[m];
                 E[m] = eacc(c.q[t], ok ? flow_cost2<B2>(w, fmaf(ex, ex, ey * ey)) : 1.0f, E[m]);
-                if (E[m] >= bound) live &= ~(1u << m);
+                if (STRICT ? (E[m] > bound) : (E[m] >= bound)) live &= ~(1u << m);
             }
             dpx[m] = dx[m]; dpy[m] = dy[m]; zprev[m] = zok[m];
         }

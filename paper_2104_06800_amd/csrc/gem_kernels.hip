@@ -517,11 +517,24 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
 #pragma unroll
         for (int t = 0; t < VD_NMAX; ++t) if (t < w.N) c.q[t] = q_s[t * nodes + o];
         prior_posteriors<PR>(w, B.P, B.prior, B.prior_weight, p.v * w.W + p.u, c, rcur[o]);
-        for (int d = 0; d < g.spec; ++d) {
-            const int ip = p.i - (d + 1) * di;
-            if (ip < 0 || ip >= L) break;
-            specE[d * nodes + o] =
-                energy2_bounded<B2, PR, true>(w, B.P, B.flow2, B.prior, c, bestV[p.c * stride + ip], bestE[o]);
+        // the speculative energies in lockstep pairs (one strict bound, no merging): each is
+        // the value of its own bounded evaluation, their gathers in flight together
+        for (int d0 = 0; d0 < g.spec; d0 += 2) {
+            float cand[2];
+            unsigned live = 0u;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int ip = p.i - (d0 + m + 1) * di;
+                const bool in = d0 + m < g.spec && ip >= 0 && ip < L;
+                cand[m] = in ? bestV[p.c * stride + ip] : 0.f;
+                if (in) live |= 1u << m;
+            }
+            if (live == 0u) break;
+            energy_t e[2];
+            energy2_bounded_m<B2, PR, 2, true>(w, B.P, B.flow2, B.prior, c, cand, live, bestE[o], e);
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+                if ((live >> m) & 1u) specE[(d0 + m) * nodes + o] = e[m];
         }
     }
     __syncthreads();
