@@ -434,7 +434,6 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
         }
         __syncthreads();
     }
-    const int G = (w.K - 3 + 3) / 4;
     const uint32_t word2 = philox_word2(w.it, w.level, PURPOSE_CAND);
     const bool local = (w.level == 1);
 
@@ -466,38 +465,49 @@ __device__ __forceinline__ void level_body(const Win& w, const LevelGeom& g, con
                                 : energy2<B2, PR>(w, B.P, B.flow2, B.prior, c, r0);
         float bV = r0;
         int bS = 0;
+        // the candidates are evaluated in groups of PG against the best before the group,
+        // then merged in slot order: the same winner and energy as one at a time.  A group's
+        // flow gathers of a frame are issued together.  Group h holds slots 4h + 2 .. 4h + 5:
+        // slot 2 (the coarse value, local level only) rides with the first three draws of
+        // Philox group 0, and each later group starts with the previous Philox group's last
+        // draw.  Groups of 4 (pairs with priors, whose per-pixel context is larger) at 4
+        // waves per SIMD.
+        float rc = 0.f;
         if (local) {
             const int U = min(p.u / w.s, w.wc - 1), V = min(p.v / w.s, w.hc - 1);
-            const float rc = B.idepth_coarse[V * w.wc + U];
-            const energy_t e = energy2_bounded<B2, PR, false>(w, B.P, B.flow2, B.prior, c, rc, bE);
-            if (e < bE) { bE = e; bV = rc; bS = 2; }
+            rc = B.idepth_coarse[V * w.wc + U];
         }
-        // the candidates of a draw are evaluated in groups of PG against the best before the
-        // group, then merged in slot order: the same winner and energy as one at a time.  A
-        // group's flow gathers of a frame are issued together; a whole Philox draw per group
-        // (pairs with priors, whose per-pixel context is larger) at 4 waves per SIMD.
         constexpr int PG = PR ? 2 : 4;
-        for (int gi = 0; gi < G; ++gi) {
-            const uint4 r = philox10(make_uint4((uint32_t)p.li, (uint32_t)gi, word2, w.window_id), w.key0, w.key1);
-            const uint32_t words[4] = {r.x, r.y, r.z, r.w};
+        const int NH = (w.K - 2 + 3) / 4;
+        uint32_t carry = 0u;
+        for (int h = 0; h < NH; ++h) {
+            uint4 r = make_uint4(0u, 0u, 0u, 0u);
+            if (4 * h + 3 < w.K)
+                r = philox10(make_uint4((uint32_t)p.li, (uint32_t)h, word2, w.window_id), w.key0, w.key1);
+            const uint32_t words[4] = {carry, r.x, r.y, r.z};
+            carry = r.w;
             float cand[4];
             energy_t e[4];
             unsigned live = 0u;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const int slot = 3 + 4 * gi + m;
+                const int slot = 4 * h + 2 + m;
                 const float uu = unit24(words[m]);
                 cand[m] = (slot & 1) ? fminf(fmaxf(r0 * fmaf(w.sigma_it, fmaf(2.f, uu, -1.f), 1.f), w.rmin), w.rmax)
                                      : fmaf(uu, w.rmax - w.rmin, w.rmin);
                 if (slot < w.K) live |= 1u << m;
             }
+            if (h == 0) {
+                cand[0] = rc;
+                if (!local) live &= ~1u;
+            }
 #pragma unroll
-            for (int h = 0; h < 4; h += PG) {
-                energy2_bounded_m<B2, PR, PG>(w, B.P, B.flow2, B.prior, c, cand + h,
-                                                     (live >> h) & ((1u << PG) - 1u), bE, e + h);
+            for (int q = 0; q < 4; q += PG) {
+                energy2_bounded_m<B2, PR, PG>(w, B.P, B.flow2, B.prior, c, cand + q,
+                                              (live >> q) & ((1u << PG) - 1u), bE, e + q);
 #pragma unroll
-                for (int m = h; m < h + PG; ++m)
-                    if (((live >> m) & 1u) && e[m] < bE) { bE = e[m]; bV = cand[m]; bS = 3 + 4 * gi + m; }
+                for (int m = q; m < q + PG; ++m)
+                    if (((live >> m) & 1u) && e[m] < bE) { bE = e[m]; bV = cand[m]; bS = 4 * h + 2 + m; }
             }
         }
         bestE[o] = bE; bestV[o] = bV; bestS[o] = bS; rcur[o] = r0;
