@@ -85,11 +85,7 @@ inline int wgrad_co_tile(int Cout) { return Cout % 128 == 0 ? 128 : (Cout % 64 =
 hipError_t launch_wgrad(const WgradArgs& a, int nchunks, hipStream_t st);
 hipError_t launch_bgrad(const uint16_t* dy, int Mpix, int C, int nchunks, float* part, hipStream_t st);
 hipError_t launch_sum_chunks(const float* part, int n, int nchunks, float* out, hipStream_t st);
-hipError_t launch_heads(const float* o, int HW, int N, float tnorm, float rmin, float rmax, float* rho, float* q,
-                        hipStream_t st);
 hipError_t launch_flag_clear(int* flag, hipStream_t st);
-hipError_t launch_start_heads(const float* o, int HW, int N, const double* pose, float rmin, float rmax, float* rho,
-                              float* q, int* flag, hipStream_t st);
 // blocks of the mask count (4096 mask bytes each): the loss's count buffer holds that many ints
 inline int mask_count_blocks(int HW) { return (HW + 4095) / 4096; }
 hipError_t launch_loss(const float* o, int HW, int N, float tnorm, const float* rho_t, const float* q_t,

@@ -14,7 +14,7 @@
 //                     partials), dy and the 9 im2col slices staged pixel-contiguous in LDS;
 //                     k_wgrad the fallback for unaligned pointers; k_sum_chunks reduces the
 //                     partials in a fixed order; k_bgrad the bias gradient
-//   k_features, k_heads, k_loss (+ finish), k_adam: the element-wise rest.
+//   k_features, k_loss (+ finish), k_adam: the element-wise rest.
 //
 // MFMA operand layout (32x32x16, wave64): lane l supplies A[i = l%32][k = 8(l/32) .. +7] and
 // B[k = 8(l/32) .. +7][j = l%32]; the 16 accumulators of lane l hold D[i][j = l%32] for
@@ -800,50 +800,15 @@ __global__ void __launch_bounds__(1024) k_sum_chunks(const float* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------------------
-// heads as a pass of their own over FP32 logits (the same arithmetic as the fused epilogue)
-// ---------------------------------------------------------------------------------------
-__global__ void k_heads(const float* __restrict__ o, int HW, int N, float tnorm, float rmin, float rmax,
-                        float* __restrict__ rho, float* __restrict__ q) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= HW) return;
-    const float* oj = o + (size_t)j * VP_C_HEAD;
-    if (rho) rho[j] = fminf(fmaxf(softplusf(oj[0]) / tnorm, rmin), rmax);
-    if (q)
-        for (int t = 0; t < N; ++t) q[(size_t)t * HW + j] = sigmoidf(oj[1 + t]);
-}
-
-// ---------------------------------------------------------------------------------------
-// learned start of a GEM window: tnorm = |t| of frame 1's pose (FP64, on the device); a
-// non-finite depth logit or an unusable tnorm raises the window's fallback flag (cleared by
-// k_flag_clear beforehand), in which case the caller's random start replaces every pixel
+// learned start of a GEM window: the heads fused into the last layer take tnorm = |t| of
+// frame 1's pose (FP64, on the device); a non-finite depth logit or an unusable tnorm raises
+// the window's fallback flag (cleared here beforehand), in which case the caller's random
+// start replaces every pixel
 // ---------------------------------------------------------------------------------------
 __global__ void k_flag_clear(int* __restrict__ flag) { *flag = 0; }
 
-__global__ void k_start_heads(const float* __restrict__ o, int HW, int N, const double* __restrict__ pose,
-                              float rmin, float rmax, float* __restrict__ rho, float* __restrict__ q,
-                              int* __restrict__ flag) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const double t0 = pose[3], t1 = pose[4], t2 = pose[5];
-    const float tnorm = (float)sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-    const bool tn_ok = isfinite(tnorm) && tnorm > 0.f;
-    if (j >= HW) return;
-    const float* oj = o + (size_t)j * VP_C_HEAD;
-    const bool ok = tn_ok && isfinite(oj[0]);
-    if (!ok) atomicOr(flag, 1);
-    rho[j] = ok ? fminf(fmaxf(softplusf(oj[0]) / tnorm, rmin), rmax) : rmin;
-    for (int t = 0; t < N; ++t) q[(size_t)t * HW + j] = sigmoidf(oj[1 + t]);
-}
-
 hipError_t launch_flag_clear(int* flag, hipStream_t st) {
     hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, st, flag);
-    return hipGetLastError();
-}
-
-hipError_t launch_start_heads(const float* o, int HW, int N, const double* pose, float rmin, float rmax, float* rho,
-                              float* q, int* flag, hipStream_t st) {
-    hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, st, flag);
-    hipLaunchKernelGGL(k_start_heads, dim3((HW + 255) / 256), dim3(256), 0, st, o, HW, N, pose, rmin, rmax, rho, q,
-                       flag);
     return hipGetLastError();
 }
 
@@ -1095,12 +1060,6 @@ hipError_t launch_bgrad(const uint16_t* dy, int Mpix, int C, int nchunks, float*
 
 hipError_t launch_sum_chunks(const float* part, int n, int nchunks, float* out, hipStream_t st) {
     hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, st, part, n, nchunks, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_heads(const float* o, int HW, int N, float tnorm, float rmin, float rmax, float* rho, float* q,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_heads, dim3((HW + 255) / 256), dim3(256), 0, st, o, HW, N, tnorm, rmin, rmax, rho, q);
     return hipGetLastError();
 }
 
