@@ -300,7 +300,8 @@ int voldor_timing_read(voldor_ctx ctx, int timer, double* total_ms, int64_t* lau
 
 typedef struct {
     float*    params;        /* [VOLDOR_NET_PARAMS] FP32 master parameters                  */
-    uint16_t* wbf16;         /* [VOLDOR_NET_PARAMS] BF16 copy of params (the kernels' weights) */
+    uint16_t* wbf16;         /* [VOLDOR_NET_PARAMS] BF16 copy of params (the kernels' weights;
+                                this and wt_bf16 16-byte aligned, VOLDOR_EINVAL otherwise) */
     uint16_t* wt_bf16;       /* [VOLDOR_NET_PARAMS] BF16 weights transposed to [Cin][3][3][Cout]
                                 per layer (training; NULL for inference)                    */
     float*    adam_m;        /* [VOLDOR_NET_PARAMS] Adam moments (training; else NULL)       */
@@ -332,14 +333,17 @@ int voldor_proposal_train_step(voldor_ctx ctx, const voldor_net* net, int32_t H,
  * nearest upsampling when up = 1), weights w [Cout][3][3][Cin] BF16, bias [Cout] FP32 (or
  * NULL), optional skip [Ho][Wo][Cout] BF16 added before the optional ReLU; output y BF16
  * and/or yf FP32, [Ho][Wo][Cout] with Ho = (H' - 1) / stride + 1 on the (upsampled) input
- * H'.  Cin a multiple of 16, Cout of 32; stride 1 or 2 (not with up). */
+ * H'.  Cin a multiple of 16, Cout of 32; stride 1 or 2 (not with up).  The BF16 arrays (x,
+ * w, skip, y) must be 16-byte aligned, as every hipMalloc allocation is: VOLDOR_EINVAL
+ * otherwise, before any launch. */
 int voldor_conv3x3_bf16(voldor_ctx ctx, int32_t H, int32_t W, int32_t Cin, int32_t Cout, int32_t stride,
                         int32_t up, int32_t relu, const uint16_t* x, const uint16_t* w, const float* bias,
                         const uint16_t* skip, uint16_t* y, float* yf, void* stream);
 
 /* Gradients of that layer (without its activation) for an upstream gradient dy
  * [Ho][Wo][Cout] BF16: dx [H][W][Cin], dw [Cout][3][3][Cin], db [Cout], all FP32 (each
- * may be NULL).  w_t is the BF16 weight transposed to [Cin][3][3][Cout]. */
+ * may be NULL).  w_t is the BF16 weight transposed to [Cin][3][3][Cout].  x, w_t and dy
+ * must be 16-byte aligned (VOLDOR_EINVAL otherwise). */
 int voldor_conv3x3_bf16_backward(voldor_ctx ctx, int32_t H, int32_t W, int32_t Cin, int32_t Cout,
                                  int32_t stride, int32_t up, const uint16_t* x, const uint16_t* w_t,
                                  const uint16_t* dy, float* dx, float* dw, float* db, void* stream);

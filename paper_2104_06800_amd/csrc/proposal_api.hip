@@ -189,6 +189,9 @@ vp::ConvArgs dgrad_args(const vp::ConvArgs& f, const uint16_t* wt, const uint16_
     return d;
 }
 
+// the convolution kernels read and write BF16 arrays as 16-byte vectors (null passes)
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 int check_conv(voldor_ctx ctx, int H, int W, int Cin, int Cout, int stride, int up) {
     if (H < 1 || W < 1 || (int64_t)H * W > (1 << 26)) return fail(ctx, VOLDOR_EINVAL, "bad conv input size");
     if (Cin < 16 || Cin % 16 || Cin > 1024 || Cout < 32 || Cout % 32 || Cout > 1024)
@@ -213,6 +216,7 @@ int proposal_start(voldor_ctx ctx, const voldor_net* net, int H, int W, int N, c
     int rc;
     if ((rc = check_net_shape(ctx, H, W, N))) return rc;
     if (!net || !net->params || !net->wbf16) return fail(ctx, VOLDOR_EINVAL, "null network pointer");
+    if (!aligned16(net->wbf16)) return fail(ctx, VOLDOR_EINVAL, "network BF16 weights must be 16-byte aligned");
     Acts A;
     if ((rc = layout(ctx, H, W, false, st, A))) return rc;
     VD_CHECK(vp::launch_flag_clear(A.flag, st), "flag clear launch");
@@ -246,6 +250,7 @@ int voldor_proposal_forward(voldor_ctx ctx, const voldor_net* net, int32_t H, in
     int rc;
     if ((rc = check_net_shape(ctx, H, W, N))) return rc;
     if (!net || !net->params || !net->wbf16 || !flow) return fail(ctx, VOLDOR_EINVAL, "null pointer");
+    if (!aligned16(net->wbf16)) return fail(ctx, VOLDOR_EINVAL, "network BF16 weights must be 16-byte aligned");
     if (!(tnorm > 0.f) || !std::isfinite(tnorm)) return fail(ctx, VOLDOR_EINVAL, "tnorm must be > 0");
     if (!(idepth_min > 0.f) || !(idepth_max > idepth_min)) return fail(ctx, VOLDOR_EINVAL, "bad idepth range");
     hipStream_t st = (hipStream_t)stream;
@@ -266,6 +271,8 @@ int voldor_proposal_train_step(voldor_ctx ctx, const voldor_net* net, int32_t H,
     if ((rc = check_net_shape(ctx, H, W, N))) return rc;
     if (!net || !net->params || !net->wbf16 || !net->wt_bf16 || !net->adam_m || !net->adam_v || !net->grads)
         return fail(ctx, VOLDOR_EINVAL, "training needs every network buffer");
+    if (!aligned16(net->wbf16) || !aligned16(net->wt_bf16))
+        return fail(ctx, VOLDOR_EINVAL, "network BF16 weights must be 16-byte aligned");
     if (!flow || !idepth_target || !rigid_target || !mask || !loss_out)
         return fail(ctx, VOLDOR_EINVAL, "null training input");
     if (!(tnorm > 0.f) || !std::isfinite(tnorm) || !(lam >= 0.f) || !(lr > 0.f) || step < 1)
@@ -341,6 +348,8 @@ int voldor_conv3x3_bf16(voldor_ctx ctx, int32_t H, int32_t W, int32_t Cin, int32
     int rc;
     if ((rc = check_conv(ctx, H, W, Cin, Cout, stride, up))) return rc;
     if (!x || !w || (!y && !yf)) return fail(ctx, VOLDOR_EINVAL, "null conv pointer");
+    if (!aligned16(x) || !aligned16(w) || !aligned16(skip) || !aligned16(y))
+        return fail(ctx, VOLDOR_EINVAL, "conv BF16 arrays must be 16-byte aligned");
     VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
     vp::ConvArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -362,6 +371,8 @@ int voldor_conv3x3_bf16_backward(voldor_ctx ctx, int32_t H, int32_t W, int32_t C
     int rc;
     if ((rc = check_conv(ctx, H, W, Cin, Cout, stride, up))) return rc;
     if (!x || !dy || (dx && !w_t)) return fail(ctx, VOLDOR_EINVAL, "null conv pointer");
+    if (!aligned16(x) || !aligned16(dy) || !aligned16(w_t))
+        return fail(ctx, VOLDOR_EINVAL, "conv BF16 arrays must be 16-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     VD_CHECK(hipSetDevice(ctx->device), "hipSetDevice");
     vp::ConvArgs f;

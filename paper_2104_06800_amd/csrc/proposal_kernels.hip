@@ -12,8 +12,8 @@
 //                     roles; Cin a multiple of 16, Cout of 16)
 //   k_wgrad2          dW[co][tap][ci] = sum_m dy[m][co] x_tap(m)[ci] per pixel chunk (FP32
 //                     partials), dy and the 9 im2col slices staged pixel-contiguous in LDS;
-//                     k_wgrad the fallback for unaligned pointers; k_sum_chunks reduces the
-//                     partials in a fixed order; k_bgrad the bias gradient
+//                     k_sum_chunks reduces the partials in a fixed order; k_bgrad the bias
+//                     gradient (16-byte aligned BF16 arrays throughout)
 //   k_features, k_loss (+ finish), k_adam: the element-wise rest.
 //
 // MFMA operand layout (32x32x16, wave64): lane l supplies A[i = l%32][k = 8(l/32) .. +7] and
@@ -568,60 +568,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 }
 
 // ---------------------------------------------------------------------------------------
-// weight gradient: block = (32 output channels) x (one tap, 32 input channels) x pixel chunk
-// D[co][ci] = sum_m dy[m][co] x_tap(m)[ci]; the 4 waves take interleaved 16-pixel steps of the
-// chunk and are summed through LDS.  A lane's 8 k-values are 8 consecutive pixels.
-// ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
-    __shared__ float red[4][64][16];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int co0 = blockIdx.x * 32;
-    const int ci_tiles = (a.Cin + 31) / 32;   // a 16-channel input uses half a tile
-    const int tap = blockIdx.y / ci_tiles, ci0 = (blockIdx.y - tap * ci_tiles) * 32;
-    const int ky = tap / 3, kx = tap - 3 * ky;
-    const int Mpix = a.Ho * a.Wo;
-    const int chunk = (Mpix + gridDim.z - 1) / gridDim.z;
-    const int mbeg = blockIdx.z * chunk, mend = min(Mpix, mbeg + chunk);
-    const int co = co0 + (lane & 31), ci = ci0 + (lane & 31);
-    const bool civ = ci < a.Cin;
-    f32x16 acc;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = 0.f;
-    for (int m0 = mbeg + 16 * wave; m0 < mend; m0 += 64) {
-        bf16x8 A, B;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int m = m0 + 8 * (lane >> 5) + e;
-            uint16_t av = 0, bv = 0;
-            if (m < mend) {
-                av = a.dy[(size_t)m * a.Cout + co];
-                const int oy = m / a.Wo, ox = m - oy * a.Wo;
-                int sy = oy * a.stride + ky - 1, sx = ox * a.stride + kx - 1;
-                if (civ && sy >= 0 && sy < a.Hs && sx >= 0 && sx < a.Ws) {
-                    if (a.up) { sy >>= 1; sx >>= 1; }
-                    bv = a.x[((size_t)sy * a.Wx + sx) * a.Cin + ci];
-                }
-            }
-            A[e] = __builtin_bit_cast(__bf16, av);
-            B[e] = __builtin_bit_cast(__bf16, bv);
-        }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) red[wave][lane][e] = acc[e];
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const float s = (red[0][lane][e] + red[1][lane][e]) + (red[2][lane][e] + red[3][lane][e]);
-            const int i = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);     // co within tile
-            const int j = lane & 31;                                   // ci within tile
-            if (ci0 + j < a.Cin) a.part[(size_t)blockIdx.z * a.nparam + ((size_t)(co0 + i) * 9 + tap) * a.Cin + ci0 + j] = s;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------------------
 // weight gradient, LDS-staged: block = (CO_T output channels) x (32 input channels) x all 9
 // taps x a chunk of output pixels.  D[co][ci] (one 32 x 32 tile per tap and 32 output
 // channels) = sum over pixels m of dy[m][co] x_tap(m)[ci]: the contraction runs over pixels,
@@ -742,9 +688,9 @@ __global__ void __launch_bounds__(256) k_wgrad2(WgradArgs a) {
 }
 
 // bias gradient partials: block b sums the pixels [b chunk, (b + 1) chunk) of dy [Mpix][C].
-// Thread t takes the 8 channels of group g = t % G (G = C / 8; one 16-byte load per pixel
-// when dy is 16-byte aligned) on the pixels mbeg + p, mbeg + p + P, ... (p = t / G,
-// P = 256 / G); the P sums of a channel are added in LDS in a fixed order.
+// Thread t takes the 8 channels of group g = t % G (G = C / 8; one 16-byte load per pixel)
+// on the pixels mbeg + p, mbeg + p + P, ... (p = t / G, P = 256 / G); the P sums of a
+// channel are added in LDS in a fixed order.
 __global__ void __launch_bounds__(256) k_bgrad(const uint16_t* __restrict__ dy, int Mpix, int C, int nchunks,
                                                float* __restrict__ part) {
     extern __shared__ float red_b[];                    // [P][C]
@@ -754,19 +700,13 @@ __global__ void __launch_bounds__(256) k_bgrad(const uint16_t* __restrict__ dy, 
     const int mbeg = blockIdx.x * chunk, mend = min(Mpix, mbeg + chunk);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (pl < P) {
-        if ((reinterpret_cast<uintptr_t>(dy) & 15) == 0) {
-            for (int m = mbeg + pl; m < mend; m += P) {
-                const u32x4 v = *reinterpret_cast<const u32x4*>(dy + (size_t)m * C + 8 * g);
+        for (int m = mbeg + pl; m < mend; m += P) {
+            const u32x4 v = *reinterpret_cast<const u32x4*>(dy + (size_t)m * C + 8 * g);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    acc[2 * e] += __uint_as_float(v[e] << 16);
-                    acc[2 * e + 1] += __uint_as_float(v[e] & 0xffff0000u);
-                }
+            for (int e = 0; e < 4; ++e) {
+                acc[2 * e] += __uint_as_float(v[e] << 16);
+                acc[2 * e + 1] += __uint_as_float(v[e] & 0xffff0000u);
             }
-        } else {
-            for (int m = mbeg + pl; m < mend; m += P)
-#pragma unroll
-                for (int e = 0; e < 8; ++e) acc[e] += bf2f(dy[(size_t)m * C + 8 * g + e]);
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) red_b[pl * C + 8 * g + e] = acc[e];
@@ -1035,23 +975,19 @@ hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t st) {
 }
 
 hipError_t launch_wgrad(const WgradArgs& a, int nchunks, hipStream_t st) {
-    // the staged kernel reads 16-byte channel groups: both arrays 16-byte aligned
-    const bool aligned = ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.dy)) & 15) == 0;
-    if (aligned && a.Cin % 8 == 0) {
-        const int cot = wgrad_co_tile(a.Cout);
-        const dim3 grid((unsigned)(a.Cout / cot), (unsigned)((a.Cin + 31) / 32), (unsigned)nchunks);
-        if (cot == 128) hipLaunchKernelGGL(k_wgrad2<128>, grid, dim3(256), 0, st, a);
-        else if (cot == 64) hipLaunchKernelGGL(k_wgrad2<64>, grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL(k_wgrad2<32>, grid, dim3(256), 0, st, a);
-        return hipGetLastError();
-    }
-    const dim3 grid((unsigned)(a.Cout / 32), (unsigned)(9 * ((a.Cin + 31) / 32)), (unsigned)nchunks);
-    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, a);
+    // 16-byte channel groups: both arrays 16-byte aligned, Cin a multiple of 8
+    if (((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.dy)) & 15) != 0 || a.Cin % 8 != 0)
+        return hipErrorInvalidValue;
+    const int cot = wgrad_co_tile(a.Cout);
+    const dim3 grid((unsigned)(a.Cout / cot), (unsigned)((a.Cin + 31) / 32), (unsigned)nchunks);
+    if (cot == 128) hipLaunchKernelGGL(k_wgrad2<128>, grid, dim3(256), 0, st, a);
+    else if (cot == 64) hipLaunchKernelGGL(k_wgrad2<64>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_wgrad2<32>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_bgrad(const uint16_t* dy, int Mpix, int C, int nchunks, float* part, hipStream_t st) {
-    if (C % 8 != 0 || C > 2048) return hipErrorInvalidValue;
+    if (C % 8 != 0 || C > 2048 || (reinterpret_cast<uintptr_t>(dy) & 15) != 0) return hipErrorInvalidValue;
     const int P = 256 / (C / 8);
     hipLaunchKernelGGL(k_bgrad, dim3((unsigned)nchunks), dim3(256), (size_t)P * C * sizeof(float), st, dy, Mpix, C,
                        nchunks, part);

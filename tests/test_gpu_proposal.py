@@ -158,6 +158,32 @@ def test_network_forward(lib):
     assert np.array_equal(np_(rho2), np_(rho)) and np.array_equal(np_(q2), np_(q))
 
 
+def test_conv_rejects_unaligned_bf16_arrays(lib):
+    """The single-layer entry points read BF16 arrays as 16-byte vectors: a view 2 bytes off
+    an allocation is rejected with EINVAL before any launch, forward and backward."""
+    from paper_2104_06800_amd.binding import VoldorError
+    c = CASES[0]
+    x, w, b, rng = case_data(c, 5)
+    xb, wb = bits(x), bits(w)
+
+    def shifted(t):
+        big = torch.zeros(t.numel() + 8, dtype=torch.int16, device="cuda")
+        v = big[1:1 + t.numel()].view(t.shape)
+        v.copy_(t)
+        return v
+
+    with pytest.raises(VoldorError, match="16-byte aligned"):
+        lib.conv3x3_bf16(shifted(xb), wb, None)
+    with pytest.raises(VoldorError, match="16-byte aligned"):
+        lib.conv3x3_bf16(xb, shifted(wb), None)
+    dy = bits(P.bf16(rng.normal(size=(c["H"], c["W"], c["Cout"]))))
+    w_t = bits(np.ascontiguousarray(np.transpose(w, (3, 1, 2, 0))))
+    with pytest.raises(VoldorError, match="16-byte aligned"):
+        lib.conv3x3_bf16_backward(xb, w_t, shifted(dy))
+    y, yf = lib.conv3x3_bf16(xb, wb, None)          # the aligned call still works
+    assert y is not None and torch.isfinite(yf).all()
+
+
 def test_training_step(lib):
     params, flow, rng = params_and_window(seed=4, N=3, H=24, W=32)
     N, H, W, _ = flow.shape
