@@ -282,6 +282,7 @@ struct GemLaunch {
     int pose_blocks;
     int max_level_blocks;
     bool timers = true;   // bracket launches with the context's timers (when enabled)
+    bool may_alloc = true; // may create context-owned buffers (not in the no-allocation entry)
     voldor_knobs kn;      // launch knobs of the window (results do not depend on them)
     struct { size_t head, f2, hist, obs, ll, red, pa; } sz;
 };
@@ -356,6 +357,7 @@ vd::LevelBufs level_bufs(const GemLaunch& L, int level, bool want_ll) {
     B.flow2 = L.flow2;
     B.idepth = L.b->idepth;
     B.idepth_coarse = L.b->idepth_coarse;
+    B.blk_order = nullptr;
     B.prior = L.b->prior_idepth;
     B.prior_weight = L.b->prior_weight;
     float* q = level == VOLDOR_LEVEL_COARSE ? L.b->rigid_coarse : L.b->rigid;
@@ -402,13 +404,54 @@ vd::FinalBufs final_bufs(const GemLaunch& L) {
     return B;
 }
 
+// Block order of the local level: the level's blocks sorted by the angle of their centre
+// around the principal point.  Each XCD takes a contiguous range of logical blocks
+// (xcd_block), so it then works on an angular sector of the image.  For a camera moving
+// forward the epipolar lines radiate from near the principal point, so the flow samples of
+// a sector's candidates stay in that sector's part of the flows and the XCD's L2 holds more
+// of them.  Only the schedule changes: every block computes what it computes in order.
+// Created once per context and geometry, outside stream capture and never by the
+// no-allocation entry; null (blocks in order) otherwise.
+const int* block_order(GemLaunch& L, const vd::LevelGeom& g, const vd::Win& w) {
+    voldor_ctx ctx = L.ctx;
+    int cxb, cyb;
+    std::memcpy(&cxb, &w.cx, sizeof(int));
+    std::memcpy(&cyb, &w.cy, sizeof(int));
+    const std::array<int, 10> key = {g.h, g.w, g.s, g.off, g.seg, g.horizontal, g.C, g.nseg, cxb, cyb};
+    for (const auto& e : ctx->block_orders)
+        if (e.key == key) return e.d;
+    if (!L.may_alloc) return nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(L.st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    const int nb = g.nblocks;
+    std::vector<std::pair<double, int>> a((size_t)nb);
+    for (int b = 0; b < nb; ++b) {
+        const int sidx = b % g.nseg, lb = b / g.nseg;
+        const double line = lb * g.C + 0.5 * g.C, pos = sidx * g.seg + 0.5 * g.seg;
+        const double lx = g.horizontal ? pos : line, ly = g.horizontal ? line : pos;
+        a[(size_t)b] = {std::atan2(g.s * ly + g.off - w.cy, g.s * lx + g.off - w.cx), b};
+    }
+    std::sort(a.begin(), a.end());
+    std::vector<int> order((size_t)nb);
+    for (int i = 0; i < nb; ++i) order[(size_t)i] = a[(size_t)i].second;
+    int* d = nullptr;
+    if (hipMalloc(&d, sizeof(int) * (size_t)nb) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, order.data(), sizeof(int) * (size_t)nb, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return nullptr;
+    }
+    ctx->block_orders.push_back({key, d});
+    return d;
+}
+
 int run_level(GemLaunch& L, int it, int level, int do_e, int do_m, bool want_ll) {
     voldor_ctx ctx = L.ctx;
     const vd::Win w = make_win(L.v, it, level, L.b);
     const vd::LevelGeom g = make_geom(L.v, w, level, it, L.kn);
     const size_t lds = vd::level_lds_bytes(g);
     if (lds > kLevelLdsMax) return fail(ctx, VOLDOR_EINVAL, "chain segment too long for LDS (%zu bytes)", lds);
-    const vd::LevelBufs B = level_bufs(L, level, want_ll);
+    vd::LevelBufs B = level_bufs(L, level, want_ll);
+    if (level == VOLDOR_LEVEL_LOCAL) B.blk_order = block_order(L, g, w);
     hipEvent_t t0 = nullptr;
     const int timer = level == VOLDOR_LEVEL_COARSE ? VOLDOR_TIMER_COARSE : VOLDOR_TIMER_LOCAL;
     const bool timed = L.timers && (level == VOLDOR_LEVEL_COARSE || (do_e && do_m));
@@ -817,6 +860,7 @@ void voldor_ctx_destroy(voldor_ctx ctx) {
     drop_graph(ctx);
     if (ctx->batch_ws) (void)hipFree(ctx->batch_ws);
     if (ctx->batch_tab) (void)hipFree(ctx->batch_tab);
+    for (const auto& e : ctx->block_orders) (void)hipFree(e.d);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     timers_discard(ctx);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -970,6 +1014,7 @@ int voldor_run_noalloc(voldor_ctx ctx, const voldor_window* v, const voldor_buff
     GemLaunch L;
     L.ctx = ctx; L.v = v; L.b = b; L.st = (hipStream_t)stream;
     L.timers = false;
+    L.may_alloc = false;
     const size_t need = gem_layout(v, 1, L);
     if (need > (size_t)VOLDOR_NOALLOC_SCRATCH_BYTES)
         return fail(ctx, VOLDOR_EINVAL, "window %dx%d with N=%d needs %zu bytes of scratch; the static area holds %zu",

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <string>
 #include <utility>
 #include <vector>
@@ -33,6 +34,11 @@ struct voldor_ctx_s {
         voldor_knobs k;
     };
     std::vector<KnobEntry> knobs;
+    struct BlockOrder {               // local-level block order of one level geometry
+        std::array<int, 10> key;      // geometry fields and the principal point's bits
+        int* d;                       // device copy [nblocks]
+    };
+    std::vector<BlockOrder> block_orders;
     int n_cu = 256;
     unsigned timing = 0;              // enabled timer classes, bit (1 << timer)
     std::vector<hipEvent_t> ev_pool;                                   // idle events

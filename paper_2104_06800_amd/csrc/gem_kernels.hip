@@ -812,7 +812,8 @@ template <bool B2, bool PR, bool LC>
 __global__ void __launch_bounds__(VD_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 k_level(Win w, LevelGeom g, LevelBufs B, int do_e, int do_m) {
     extern __shared__ __align__(16) float lds[];
-    level_body<B2, PR, LC>(w, g, B, do_e, do_m, xcd_block(blockIdx.x, gridDim.x), lds);
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    level_body<B2, PR, LC>(w, g, B, do_e, do_m, B.blk_order ? B.blk_order[xb] : xb, lds);
 }
 
 // ----------------------------------------------------------------------------------

@@ -31,6 +31,7 @@ struct LevelBufs {
     const float4* flow2;         // row-pair layout of frames t >= 2
     const float* idepth;         // full resolution, read
     const float* idepth_coarse;  // slot 2 source (local level)
+    const int* blk_order;        // logical block of each launched block (null: in order)
     const float* prior;
     const float* prior_weight;
     float* q_out;                // E-step output (level grid)
