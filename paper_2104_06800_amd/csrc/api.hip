@@ -60,6 +60,7 @@ void* noalloc_base(int dev, hipError_t* err) {
 
 constexpr size_t kMaxBatch = 4096;         // candidates per pose_score call / pairs per align call
 constexpr size_t kLevelLdsMax = 150 * 1024;
+constexpr size_t kMaxBlockOrders = 1024;   // cached local-level block orders per context
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -410,9 +411,9 @@ vd::FinalBufs final_bufs(const GemLaunch& L) {
 // forward the epipolar lines radiate from near the principal point, so the flow samples of
 // a sector's candidates stay in that sector's part of the flows and the XCD's L2 holds more
 // of them.  Only the schedule changes: every block computes what it computes in order.
-// Created once per context and geometry, outside stream capture and never by the
-// no-allocation entry; null (blocks in order) otherwise.
-const int* block_order(GemLaunch& L, const vd::LevelGeom& g, const vd::Win& w) {
+// Created once per context and geometry (up to kMaxBlockOrders of them), outside stream
+// capture and never by the no-allocation entry; null (blocks in order) otherwise.
+const int* block_order(const GemLaunch& L, const vd::LevelGeom& g, const vd::Win& w) {
     voldor_ctx ctx = L.ctx;
     int cxb, cyb;
     std::memcpy(&cxb, &w.cx, sizeof(int));
@@ -420,7 +421,7 @@ const int* block_order(GemLaunch& L, const vd::LevelGeom& g, const vd::Win& w) {
     const std::array<int, 10> key = {g.h, g.w, g.s, g.off, g.seg, g.horizontal, g.C, g.nseg, cxb, cyb};
     for (const auto& e : ctx->block_orders)
         if (e.key == key) return e.d;
-    if (!L.may_alloc) return nullptr;
+    if (!L.may_alloc || ctx->block_orders.size() >= kMaxBlockOrders) return nullptr;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(L.st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
     const int nb = g.nblocks;
@@ -659,6 +660,7 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
             x.g = make_geom(L.v, x.w, level, it, L.kn);
             x.g.pa_lanes = VD_PA_LANES;             // the batched phase-A grid keeps 8 lanes
             x.b = level_bufs(L, level, want_ll);
+            if (level == VOLDOR_LEVEL_LOCAL) x.b.blk_order = block_order(L, x.g, x.w);
             x.do_e = do_e;
             x.do_m = do_m;
             return x;
@@ -713,6 +715,7 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
         x.w = make_win(L.v, last, VOLDOR_LEVEL_LOCAL, L.b);
         x.g = make_geom(L.v, x.w, VOLDOR_LEVEL_LOCAL, last, L.kn);
         x.b = level_bufs(L, VOLDOR_LEVEL_LOCAL, true);
+        x.b.blk_order = block_order(L, x.g, x.w);
         x.do_e = 1;
         x.do_m = 0;
         return x;

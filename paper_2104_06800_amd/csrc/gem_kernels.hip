@@ -1362,7 +1362,8 @@ k_level_batch(const LevelItem* __restrict__ items, const int* __restrict__ blk2i
     extern __shared__ __align__(16) float lds[];
     const int gb = xcd_block(blockIdx.x, gridDim.x);
     const LevelItem& it = items[blk2item[gb]];
-    const int blk = gb - it.begin;
+    const int lb = gb - it.begin;
+    const int blk = MODE == 0 && it.b.blk_order ? it.b.blk_order[lb] : lb;
     if (MODE == 0) level_body<B2, PR>(it.w, it.g, it.b, it.do_e, it.do_m, blk, lds);
     else if (MODE == 3) level_body<B2, PR, true>(it.w, it.g, it.b, it.do_e, it.do_m, blk, lds);
     else if (MODE == 1) phase_a_body<B2, PR>(it.w, it.g, it.b, blk);
