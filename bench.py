@@ -577,7 +577,7 @@ def batch_workload(lib, np, torch, args, pool=True):
     # autotuned knobs per window shape (coordinate descent; results must not change)
     from paper_2104_06800_amd import autotune
     t0 = time.time()
-    space = dict(local_chains=(2, 4, 8), local_spec=(1, 2, 3), coarse_spec=(4, 6, 8))
+    space = dict(local_chains=(2, 4, 8), local_spec=(1, 2, 3), coarse_spec=(4, 6, 8), local_order=(1, 2))
     table = {}
     for w in wins:
         table[autotune.bucket(w["params"])] = autotune.tune(lib, w, reps=2, space=space)

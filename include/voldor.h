@@ -250,12 +250,18 @@ int voldor_batch_run(voldor_ctx ctx, int n_windows, const voldor_window* wins, c
  *                 energies evaluated ahead in the parallel phase
  *   coarse_spec   speculation depth of the coarse scan, 1..8 (default 8)
  *   coarse_lanes  lanes per lattice node of the coarse phase-A grid, 4, 8 or 16 (default 8;
- *                 the batched run keeps 8) */
+ *                 the batched run keeps 8)
+ *   local_order   order in which the local level's blocks are handed to the XCDs: 1 by the
+ *                 angle of the block's centre around the principal point, so that each XCD
+ *                 works on one angular sector (default; pays off when the camera moves
+ *                 forward and the flows' epipolar lines radiate from near the principal
+ *                 point), 2 row by row.  The no-allocation entry always takes row order. */
 typedef struct {
     int32_t local_chains;
     int32_t local_spec;
     int32_t coarse_spec;
     int32_t coarse_lanes;
+    int32_t local_order;
 } voldor_knobs;
 
 /* Sets (knobs != NULL) or removes (NULL) the knobs of every window with the same H, W, N,

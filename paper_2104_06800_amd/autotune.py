@@ -1,7 +1,7 @@
 """Autotuner of the library's launch knobs.
 
 The knobs (voldor_knobs: local chains per block, local and coarse speculation depths, coarse
-phase-A lanes per node) change how a window's work is split over the chip, never its
+phase-A lanes per node, the order of the local level's blocks) change how a window's work is split over the chip, never its
 results.  The best setting depends on the window's shape (image size, N, K, priors), so the
 tuner times whole windows per (H, W, N, K, prior) bucket over a grid of settings, checks
 that every setting gives the default's results bit for bit, and keeps the fastest.  Choices
@@ -13,7 +13,8 @@ import os
 
 import torch
 
-SPACE = dict(local_chains=(2, 4, 8), local_spec=(1, 2, 3), coarse_spec=(4, 6, 8), coarse_lanes=(4, 8, 16))
+SPACE = dict(local_chains=(2, 4, 8), local_spec=(1, 2, 3), coarse_spec=(4, 6, 8), coarse_lanes=(4, 8, 16),
+             local_order=(1, 2))
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "voldor", "knobs.json")
 OUT_KEYS = ("idepth", "rigid", "pose", "conf", "stats")
 

@@ -71,7 +71,8 @@ EXPORTS = sorted(["voldor_ctx_create", "voldor_ctx_destroy", "voldor_last_error"
 
 class Knobs(ctypes.Structure):
     _fields_ = [("local_chains", ctypes.c_int32), ("local_spec", ctypes.c_int32),
-                ("coarse_spec", ctypes.c_int32), ("coarse_lanes", ctypes.c_int32)]
+                ("coarse_spec", ctypes.c_int32), ("coarse_lanes", ctypes.c_int32),
+                ("local_order", ctypes.c_int32)]
 
 
 class SampleParams(ctypes.Structure):

@@ -412,16 +412,18 @@ vd::FinalBufs final_bufs(const GemLaunch& L) {
 // a sector's candidates stay in that sector's part of the flows and the XCD's L2 holds more
 // of them.  Only the schedule changes: every block computes what it computes in order.
 // Created once per context and geometry (up to kMaxBlockOrders of them), outside stream
-// capture and never by the no-allocation entry; null (blocks in order) otherwise.
+// capture; null (blocks in row order) under the local_order knob 2, in the no-allocation
+// entry, and where it cannot be created.
 const int* block_order(const GemLaunch& L, const vd::LevelGeom& g, const vd::Win& w) {
     voldor_ctx ctx = L.ctx;
+    if (L.kn.local_order == 2 || !L.may_alloc) return nullptr;
     int cxb, cyb;
     std::memcpy(&cxb, &w.cx, sizeof(int));
     std::memcpy(&cyb, &w.cy, sizeof(int));
     const std::array<int, 10> key = {g.h, g.w, g.s, g.off, g.seg, g.horizontal, g.C, g.nseg, cxb, cyb};
     for (const auto& e : ctx->block_orders)
         if (e.key == key) return e.d;
-    if (!L.may_alloc || ctx->block_orders.size() >= kMaxBlockOrders) return nullptr;
+    if (ctx->block_orders.size() >= kMaxBlockOrders) return nullptr;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(L.st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
     const int nb = g.nblocks;
@@ -1185,6 +1187,7 @@ int voldor_set_knobs(voldor_ctx ctx, const voldor_window* bucket, const voldor_k
             return fail(ctx, VOLDOR_EINVAL, "speculation depths outside 0..%d", VD_SPEC);
         if (k.coarse_lanes != 0 && k.coarse_lanes != 4 && k.coarse_lanes != 8 && k.coarse_lanes != 16)
             return fail(ctx, VOLDOR_EINVAL, "coarse_lanes must be 0, 4, 8 or 16");
+        if (k.local_order < 0 || k.local_order > 2) return fail(ctx, VOLDOR_EINVAL, "local_order must be 0, 1 or 2");
     }
     // a batch graph captured with the old knobs would no longer match the table
     drop_graph(ctx);

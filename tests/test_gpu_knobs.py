@@ -31,7 +31,8 @@ def host(b):
 
 SETTINGS = [dict(local_chains=1), dict(local_chains=2, local_spec=1), dict(local_chains=4, local_spec=3),
             dict(local_spec=8, coarse_spec=1), dict(coarse_spec=4, coarse_lanes=4), dict(coarse_lanes=16),
-            dict(local_chains=2, local_spec=5, coarse_spec=3, coarse_lanes=16)]
+            dict(local_chains=2, local_spec=5, coarse_spec=3, coarse_lanes=16), dict(local_order=2),
+            dict(local_order=1, local_chains=2), dict(local_order=2, local_chains=4, local_spec=3)]
 
 
 @pytest.mark.parametrize("case", ["street_320x240", "indoor_prior_160x120", "plain_64x48"])
@@ -47,19 +48,21 @@ def test_knobs_leave_results_bit_identical(lib, case):
     for kn in SETTINGS:
         print(f"{case}: knobs {kn}", flush=True)
         lib.set_knobs(p, kn)
-        assert lib.get_knobs(p) == dict(dict(local_chains=0, local_spec=0, coarse_spec=0, coarse_lanes=0), **kn)
+        assert lib.get_knobs(p) == dict(dict(local_chains=0, local_spec=0, coarse_spec=0, coarse_lanes=0,
+                                             local_order=0), **kn)
         b = alloc(lib, w)
         lib.run(p, b, iters=3)
         got = host(b)
         for k in KEYS:
             assert np.array_equal(got[k], ref[k], equal_nan=True), (kn, k)
     lib.set_knobs(p, None)
-    assert lib.get_knobs(p) == dict(local_chains=0, local_spec=0, coarse_spec=0, coarse_lanes=0)
+    assert lib.get_knobs(p) == dict(local_chains=0, local_spec=0, coarse_spec=0, coarse_lanes=0, local_order=0)
 
 
 def test_batch_with_per_window_knobs_equals_individual_runs(lib):
     ws = [synth.make_window(1, 30), synth.make_window(3, 31, H=53, W=70, N=4), synth.make_window(2, 32, H=64, W=96)]
-    for w, kn in zip(ws, (dict(local_chains=2, local_spec=3), dict(local_chains=1, coarse_spec=2), {})):
+    knobs = (dict(local_chains=2, local_spec=3), dict(local_chains=1, coarse_spec=2, local_order=2), {})
+    for w, kn in zip(ws, knobs):
         lib.set_knobs(w["params"], kn or None)
     single = [(w["params"], alloc(lib, w)) for w in ws]
     for p, b in single:
@@ -77,7 +80,8 @@ def test_batch_with_per_window_knobs_equals_individual_runs(lib):
 def test_bad_knobs_rejected(lib):
     from paper_2104_06800_amd.binding import VoldorError
     p = synth.make_window(1, 0)["params"]
-    for bad in (dict(local_spec=9), dict(coarse_lanes=6), dict(local_chains=-1), dict(coarse_spec=-2)):
+    for bad in (dict(local_spec=9), dict(coarse_lanes=6), dict(local_chains=-1), dict(coarse_spec=-2),
+                dict(local_order=3), dict(local_order=-1)):
         with pytest.raises(VoldorError):
             lib.set_knobs(p, bad)
 
