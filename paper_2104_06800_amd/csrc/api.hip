@@ -439,7 +439,9 @@ const int* block_order(const GemLaunch& L, const vd::LevelGeom& g, const vd::Win
     for (int i = 0; i < nb; ++i) order[(size_t)i] = a[(size_t)i].second;
     int* d = nullptr;
     if (hipMalloc(&d, sizeof(int) * (size_t)nb) != hipSuccess) return nullptr;
-    if (hipMemcpy(d, order.data(), sizeof(int) * (size_t)nb, hipMemcpyHostToDevice) != hipSuccess) {
+    // on the launch stream, waited for before the host copy goes away (as the batch tables)
+    if (hipMemcpyAsync(d, order.data(), sizeof(int) * (size_t)nb, hipMemcpyHostToDevice, L.st) != hipSuccess ||
+        hipStreamSynchronize(L.st) != hipSuccess) {
         (void)hipFree(d);
         return nullptr;
     }
