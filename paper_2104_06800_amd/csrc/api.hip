@@ -757,8 +757,47 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
     return VOLDOR_OK;
 }
 
+// The streams of the window classes (shape-2 cost or not, priors or not) and their events.
+int ensure_class_streams(voldor_ctx ctx) {
+    for (int c = 0; c < 4; ++c)
+        if (!ctx->class_streams[c])
+            VD_CHECK(hipStreamCreateWithFlags(&ctx->class_streams[c], hipStreamNonBlocking), "stream create");
+    for (int i = 0; i < 5; ++i)
+        if (!ctx->class_events[i])
+            VD_CHECK(hipEventCreateWithFlags(&ctx->class_events[i], hipEventDisableTiming), "event create");
+    return VOLDOR_OK;
+}
+
+// Enqueues the plan on st.  A run of level launches (one per window class and step) goes to
+// the classes' own streams, forked from st at its first launch and joined back into st before
+// the next launch that serves every window: the windows of different classes share no
+// buffer, so their level passes (latency-bound coarse launches above all) overlap.
 int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st) {
+    const bool par = ctx->class_streams[0] != nullptr;
+    unsigned open = 0;                           // classes forked in the current run
+    auto join = [&]() -> int {
+        for (int c = 0; c < 4; ++c)
+            if (open & (1u << c)) {
+                VD_CHECK(hipEventRecord(ctx->class_events[1 + c], ctx->class_streams[c]), "join record");
+                VD_CHECK(hipStreamWaitEvent(st, ctx->class_events[1 + c], 0), "join wait");
+            }
+        open = 0;
+        return VOLDOR_OK;
+    };
     for (const BLaunch& l : P.launches) {
+        hipStream_t s = st;
+        if (par && l.kind == BK_LEVEL) {
+            const int c = (l.b2 ? 1 : 0) + (l.pr ? 2 : 0);
+            if (!open) VD_CHECK(hipEventRecord(ctx->class_events[0], st), "fork record");
+            if (!(open & (1u << c))) {
+                VD_CHECK(hipStreamWaitEvent(ctx->class_streams[c], ctx->class_events[0], 0), "fork wait");
+                open |= 1u << c;
+            }
+            s = ctx->class_streams[c];
+        } else if (open) {
+            const int rc = join();
+            if (rc) return rc;
+        }
         const void* items = dev + l.items;
         const int* b2i = (const int*)(dev + l.b2i);
         hipError_t e = hipSuccess;
@@ -766,7 +805,7 @@ int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st
         case BK_PREP: e = vd::launch_prep_batch((const vd::PrepItem*)items, l.n_items, st); break;
         case BK_SETUP: e = vd::launch_setup_batch((const vd::PrepItem*)items, b2i, l.nblocks, st); break;
         case BK_LEVEL:
-            e = vd::launch_level_batch((const vd::LevelItem*)items, b2i, l.nblocks, l.lds, l.mode, l.b2, l.pr, st);
+            e = vd::launch_level_batch((const vd::LevelItem*)items, b2i, l.nblocks, l.lds, l.mode, l.b2, l.pr, s);
             break;
         case BK_POSE: e = vd::launch_pose_gn_batch((const vd::PoseItem*)items, b2i, l.nblocks, l.s, l.b2, st); break;
         case BK_POSE_SOLVE: e = vd::launch_pose_gn_solve_batch((const vd::PoseItem*)items, l.n_items, l.s, st); break;
@@ -775,7 +814,7 @@ int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st
         }
         VD_CHECK(e, "batched launch");
     }
-    return VOLDOR_OK;
+    return open ? join() : VOLDOR_OK;
 }
 
 void drop_graph(voldor_ctx ctx) {
@@ -869,6 +908,10 @@ void voldor_ctx_destroy(voldor_ctx ctx) {
     if (ctx->batch_tab) (void)hipFree(ctx->batch_tab);
     for (const auto& e : ctx->block_orders) (void)hipFree(e.d);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    for (hipStream_t s : ctx->class_streams)
+        if (s) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : ctx->class_events)
+        if (e) (void)hipEventDestroy(e);
     timers_discard(ctx);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -1111,6 +1154,7 @@ int batch_run_impl(voldor_ctx ctx, const voldor_net* net, int n_windows, const v
     VD_CHECK(hipMemcpyAsync(tables, ctx->batch_host.data(), ctx->batch_host.size(), hipMemcpyHostToDevice, st),
              "table upload");
     VD_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if ((rc = ensure_class_streams(ctx))) return rc;
     auto enqueue = [&](hipStream_t s) -> int {
         if (net) {
             for (int i = 0; i < n_windows; ++i) {

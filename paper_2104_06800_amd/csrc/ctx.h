@@ -26,6 +26,8 @@ struct voldor_ctx_s {
     std::vector<char> batch_host;     // host copy of the item tables
     std::vector<char> batch_key;      // windows / buffers / settings of the captured graph
     hipStream_t cap_stream = nullptr; // capture stream (default priority, non-blocking)
+    hipStream_t class_streams[4] = {};  // batched run: one stream per window class (same)
+    hipEvent_t class_events[5] = {};    // their fork (0) and join (1 + class) events
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     struct KnobEntry {                // launch knobs per (H, W, N, K, prior) bucket
