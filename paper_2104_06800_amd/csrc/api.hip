@@ -687,12 +687,15 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
             x.nblocks = L.gn_blocks;
             all.push_back(x);
         }
+        // per window class (as the level launches), so that the classes' step chains run
+        // side by side
         for (int s = 0; s < maxS; ++s) {
-            for (int b2 = 0; b2 < 2; ++b2) {
+            for (int cls = 0; cls < 4; ++cls) {
+                const bool b2 = cls & 1, pr = cls & 2;
                 std::vector<vd::PoseItem> items;
                 std::vector<int> counts;
                 for (size_t i = 0; i < W.size(); ++i)
-                    if ((int)W[i].b2 == b2 && s < all[i].S) {
+                    if (W[i].b2 == b2 && W[i].pr == pr && s < all[i].S) {
                         items.push_back(all[i]);
                         counts.push_back(all[i].nblocks);
                     }
@@ -701,13 +704,10 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
                 const std::vector<int> b2i = blocks_to_items(counts, begins);
                 for (size_t i = 0; i < items.size(); ++i) items[i].begin = begins[i];
                 const size_t io = P.put(items), bo = P.put(b2i);
-                P.add(BK_POSE, io, bo, (int)items.size(), (int)b2i.size(), 0, 0, s, b2 != 0);
+                P.add(BK_POSE, io, bo, (int)items.size(), (int)b2i.size(), 0, 0, s, b2, pr);
+                // step s's solve, one block per window of the class that has the step
+                P.add(BK_POSE_SOLVE, P.put(items), 0, (int)items.size(), (int)items.size(), 0, 0, s, b2, pr);
             }
-            // step s's solve, one block per window that has the step
-            std::vector<vd::PoseItem> act;
-            for (size_t i = 0; i < W.size(); ++i)
-                if (s < all[i].S) act.push_back(all[i]);
-            P.add(BK_POSE_SOLVE, P.put(act), 0, (int)act.size(), (int)act.size(), 0, 0, s);
         }
     }
     // final E-step, confidence and statistics
@@ -768,10 +768,11 @@ int ensure_class_streams(voldor_ctx ctx) {
     return VOLDOR_OK;
 }
 
-// Enqueues the plan on st.  A run of level launches (one per window class and step) goes to
-// the classes' own streams, forked from st at its first launch and joined back into st before
-// the next launch that serves every window: the windows of different classes share no
-// buffer, so their level passes (latency-bound coarse launches above all) overlap.
+// Enqueues the plan on st.  A run of level and pose launches (one per window class and step)
+// goes to the classes' own streams, forked from st at its first launch and joined back into
+// st before the next launch that serves every window: the windows of different classes share
+// no buffer, so their passes (latency-bound coarse launches and pose steps above all)
+// overlap.
 int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st) {
     const bool par = ctx->class_streams[0] != nullptr;
     unsigned open = 0;                           // classes forked in the current run
@@ -786,7 +787,7 @@ int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st
     };
     for (const BLaunch& l : P.launches) {
         hipStream_t s = st;
-        if (par && l.kind == BK_LEVEL) {
+        if (par && (l.kind == BK_LEVEL || l.kind == BK_POSE || l.kind == BK_POSE_SOLVE)) {
             const int c = (l.b2 ? 1 : 0) + (l.pr ? 2 : 0);
             if (!open) VD_CHECK(hipEventRecord(ctx->class_events[0], st), "fork record");
             if (!(open & (1u << c))) {
@@ -807,8 +808,8 @@ int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st
         case BK_LEVEL:
             e = vd::launch_level_batch((const vd::LevelItem*)items, b2i, l.nblocks, l.lds, l.mode, l.b2, l.pr, s);
             break;
-        case BK_POSE: e = vd::launch_pose_gn_batch((const vd::PoseItem*)items, b2i, l.nblocks, l.s, l.b2, st); break;
-        case BK_POSE_SOLVE: e = vd::launch_pose_gn_solve_batch((const vd::PoseItem*)items, l.n_items, l.s, st); break;
+        case BK_POSE: e = vd::launch_pose_gn_batch((const vd::PoseItem*)items, b2i, l.nblocks, l.s, l.b2, s); break;
+        case BK_POSE_SOLVE: e = vd::launch_pose_gn_solve_batch((const vd::PoseItem*)items, l.n_items, l.s, s); break;
         case BK_FINAL: e = vd::launch_finalize_batch((const vd::FinalItem*)items, b2i, l.nblocks, l.b2, l.pr, st); break;
         case BK_FINAL_FINISH: e = vd::launch_finalize_finish_batch((const vd::FinalItem*)items, l.n_items, st); break;
         }
