@@ -904,6 +904,8 @@ void voldor_ctx_destroy(voldor_ctx ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->net_ws) (void)hipFree(ctx->net_ws);
+    for (void* p : ctx->lane_ws)
+        if (p) (void)hipFree(p);
     drop_graph(ctx);
     if (ctx->batch_ws) (void)hipFree(ctx->batch_ws);
     if (ctx->batch_tab) (void)hipFree(ctx->batch_tab);
@@ -1139,13 +1141,21 @@ int batch_run_impl(voldor_ctx ctx, const voldor_net* net, int n_windows, const v
     if ((rc = vdc::ensure_buffer(ctx, &ctx->batch_ws, &ctx->batch_ws_bytes, total, st))) return rc;
     for (int i = 0; i < n_windows; ++i) gem_carve((char*)ctx->batch_ws + offs[i], W[i].L);
     auto net_ok = [&](const voldor_window& v) { return !(v.H & 1) && !(v.W & 1) && (int64_t)v.H * v.W <= (1 << 26); };
+    auto lane_of = [&](int i) { return (W[i].b2 ? 1 : 0) + (W[i].pr ? 2 : 0); };
     if (net) {
-        // the network's workspace for the largest window, allocated before any capture
-        int64_t best = 0;
-        int bi = -1;
-        for (int i = 0; i < n_windows; ++i)
-            if (net_ok(wins[i]) && (int64_t)wins[i].H * wins[i].W > best) { best = (int64_t)wins[i].H * wins[i].W; bi = i; }
-        if (bi >= 0 && (rc = vdc::net_workspace(ctx, wins[bi].H, wins[bi].W, st))) return rc;
+        // a forward workspace per class stream for the largest window of the class, allocated
+        // before any capture
+        int64_t best[4] = {0, 0, 0, 0};
+        int bi[4] = {-1, -1, -1, -1};
+        for (int i = 0; i < n_windows; ++i) {
+            const int c = lane_of(i);
+            if (net_ok(wins[i]) && (int64_t)wins[i].H * wins[i].W > best[c]) {
+                best[c] = (int64_t)wins[i].H * wins[i].W;
+                bi[c] = i;
+            }
+        }
+        for (int c = 0; c < 4; ++c)
+            if (bi[c] >= 0 && (rc = vdc::net_workspace(ctx, wins[bi[c]].H, wins[bi[c]].W, st, c))) return rc;
     }
     BPlan plan;
     if ((rc = build_plan(ctx, W, n_iters, flags, plan))) return rc;
@@ -1158,18 +1168,33 @@ int batch_run_impl(voldor_ctx ctx, const voldor_net* net, int n_windows, const v
     if ((rc = ensure_class_streams(ctx))) return rc;
     auto enqueue = [&](hipStream_t s) -> int {
         if (net) {
+            // each window's start on its class stream with that stream's workspace, so the
+            // classes' network passes overlap; joined back into s before the plan
+            unsigned open = 0;
+            VD_CHECK(hipEventRecord(ctx->class_events[0], s), "fork record");
             for (int i = 0; i < n_windows; ++i) {
                 const voldor_window& v = wins[i];
                 const voldor_buffers& b = bufs[i];
+                const int c = lane_of(i);
+                hipStream_t cs = ctx->class_streams[c];
+                if (!(open & (1u << c))) {
+                    VD_CHECK(hipStreamWaitEvent(cs, ctx->class_events[0], 0), "fork wait");
+                    open |= 1u << c;
+                }
                 int32_t* fo = fallback_out ? fallback_out + i : nullptr;
                 int* flag = nullptr;
                 if (net_ok(v)) {
                     int r = vdc::proposal_start(ctx, net, v.H, v.W, v.N, b.flow, b.pose, v.idepth_min, v.idepth_max,
-                                                b.idepth, b.rigid, &flag, s);
+                                                b.idepth, b.rigid, &flag, cs, c);
                     if (r) return r;
                 }
-                VD_CHECK(vd::launch_init_if(make_win(&v, 0, 1), b.idepth, boot_src(&v, &b), flag, fo, s), "start launch");
+                VD_CHECK(vd::launch_init_if(make_win(&v, 0, 1), b.idepth, boot_src(&v, &b), flag, fo, cs), "start launch");
             }
+            for (int c = 0; c < 4; ++c)
+                if (open & (1u << c)) {
+                    VD_CHECK(hipEventRecord(ctx->class_events[1 + c], ctx->class_streams[c]), "join record");
+                    VD_CHECK(hipStreamWaitEvent(s, ctx->class_events[1 + c], 0), "join wait");
+                }
         }
         return enqueue_plan(ctx, plan, tables, s);
     };

@@ -19,6 +19,8 @@ struct voldor_ctx_s {
     size_t scratch_bytes = 0;
     void* net_ws = nullptr;           // proposal-network workspace (activations, gradients)
     size_t net_ws_bytes = 0;
+    void* lane_ws[4] = {};            // batched learned start: forward workspace per class stream
+    size_t lane_ws_bytes[4] = {};
     void* batch_ws = nullptr;         // batched run: every window's scratch
     size_t batch_ws_bytes = 0;
     void* batch_tab = nullptr;        // batched run: item tables of the launch sequence
@@ -60,9 +62,10 @@ int ensure_buffer(voldor_ctx ctx, void** buf, size_t* cap, size_t need, hipStrea
 // Proposal network (proposal_api.hip): sizes the context's network workspace for an H x W
 // input; runs the network on a window's flows and writes its start (inverse depth, rigidness)
 // with *flag (device) set where the output is unusable.
-int net_workspace(voldor_ctx ctx, int H, int W, hipStream_t st);
+// lane >= 0: the forward workspace of that class stream of the batched run instead.
+int net_workspace(voldor_ctx ctx, int H, int W, hipStream_t st, int lane = -1);
 int proposal_start(voldor_ctx ctx, const voldor_net* net, int H, int W, int N, const float* flow, const double* pose,
-                   float rmin, float rmax, float* idepth, float* rigid, int** flag, hipStream_t st);
+                   float rmin, float rmax, float* idepth, float* rigid, int** flag, hipStream_t st, int lane = -1);
 
 }  // namespace vdc
 

@@ -51,7 +51,7 @@ int check_net_shape(voldor_ctx ctx, int H, int W, int N) {
     return VOLDOR_OK;
 }
 
-int layout(voldor_ctx ctx, int H, int W, bool train, hipStream_t st, Acts& A) {
+int layout(voldor_ctx ctx, int H, int W, bool train, hipStream_t st, Acts& A, int lane = -1) {
     const size_t HW = (size_t)H * W, HW2 = (size_t)(H / 2) * (W / 2);
     const size_t b16 = sizeof(uint16_t);
     size_t sz[24];
@@ -78,9 +78,10 @@ int layout(voldor_ctx ctx, int H, int W, bool train, hipStream_t st, Acts& A) {
     const int n = train ? k : nfwd;
     size_t total = 0;
     for (int i = 0; i < n; ++i) total += sz[i];
-    int rc = vdc::ensure_buffer(ctx, &ctx->net_ws, &ctx->net_ws_bytes, total, st);
+    void** ws = lane < 0 ? &ctx->net_ws : &ctx->lane_ws[lane];
+    int rc = vdc::ensure_buffer(ctx, ws, lane < 0 ? &ctx->net_ws_bytes : &ctx->lane_ws_bytes[lane], total, st);
     if (rc) return rc;
-    char* p = (char*)ctx->net_ws;
+    char* p = (char*)*ws;
     void** slots[18] = {(void**)&A.x, (void**)&A.a1, (void**)&A.a2, (void**)&A.a3, (void**)&A.a4, (void**)&A.a5,
                         (void**)&A.o, (void**)&A.flag, (void**)&A.go, (void**)&A.g5, (void**)&A.g4, (void**)&A.g3, (void**)&A.g2,
                         (void**)&A.g1, (void**)&A.wpart, (void**)&A.bpart, (void**)&A.lpart,
@@ -206,19 +207,19 @@ int check_conv(voldor_ctx ctx, int H, int W, int Cin, int Cout, int stride, int 
 
 namespace vdc {
 
-int net_workspace(voldor_ctx ctx, int H, int W, hipStream_t st) {
+int net_workspace(voldor_ctx ctx, int H, int W, hipStream_t st, int lane) {
     Acts A;
-    return layout(ctx, H, W, false, st, A);
+    return layout(ctx, H, W, false, st, A, lane);
 }
 
 int proposal_start(voldor_ctx ctx, const voldor_net* net, int H, int W, int N, const float* flow, const double* pose,
-                   float rmin, float rmax, float* idepth, float* rigid, int** flag, hipStream_t st) {
+                   float rmin, float rmax, float* idepth, float* rigid, int** flag, hipStream_t st, int lane) {
     int rc;
     if ((rc = check_net_shape(ctx, H, W, N))) return rc;
     if (!net || !net->params || !net->wbf16) return fail(ctx, VOLDOR_EINVAL, "null network pointer");
     if (!aligned16(net->wbf16)) return fail(ctx, VOLDOR_EINVAL, "network BF16 weights must be 16-byte aligned");
     Acts A;
-    if ((rc = layout(ctx, H, W, false, st, A))) return rc;
+    if ((rc = layout(ctx, H, W, false, st, A, lane))) return rc;
     VD_CHECK(vp::launch_flag_clear(A.flag, st), "flag clear launch");
     const Heads h = {idepth, rigid, 0.f, rmin, rmax, pose, A.flag, nullptr};
     if ((rc = run_forward(ctx, net, H, W, N, flow, A, st, &h))) return rc;
