@@ -369,7 +369,9 @@ int voldor_proposal_start(voldor_ctx ctx, const voldor_net* net, const voldor_wi
 /* voldor_batch_run with every window started by the proposal network as voldor_proposal_start
  * does (VOLDOR_RUN_INIT is ignored): windows with odd H or W, and windows whose network
  * output is unusable, take the random start (fallback_out[i] = 1, device int32 [n_windows],
- * or NULL).  The starts are part of the captured graph. */
+ * or NULL).  The starts are part of the captured graph; each window class runs its
+ * windows' network passes on its own stream with a forward workspace of its own (held by the
+ * context, about 0.6 KB per pixel of the class's largest window). */
 int voldor_batch_run_learned(voldor_ctx ctx, const voldor_net* net, int n_windows, const voldor_window* wins,
                              const voldor_buffers* bufs, int n_iters, int flags, int32_t* fallback_out, void* stream);
 
