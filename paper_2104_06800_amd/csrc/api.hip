@@ -639,24 +639,36 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
         const size_t io = P.put(items), bo = P.put(b2i);
         P.add(BK_SETUP, io, bo, (int)items.size(), (int)b2i.size());
     }
-    std::vector<vd::PrepItem> prep;
-    for (BWin& bw : W) {
-        const GemLaunch& L = bw.L;
-        vd::PrepItem it;
-        std::memset(&it, 0, sizeof(it));
-        it.pose = L.b->pose;
-        it.prior_pose = L.b->prior_pose;
-        it.N = L.v->N;
-        it.P = L.v->P;
-        it.out = L.s.poses;
-        it.outd = L.s.posed;
-        prep.push_back(it);
+    // pose tables per window class (as every later per-iteration launch), so that the classes'
+    // iteration chains need no common step until the statistics
+    size_t prep_off[4] = {0, 0, 0, 0};
+    int prep_n[4] = {0, 0, 0, 0};
+    for (int cls = 0; cls < 4; ++cls) {
+        std::vector<vd::PrepItem> prep;
+        for (BWin& bw : W) {
+            if ((bw.b2 ? 1 : 0) + (bw.pr ? 2 : 0) != cls) continue;
+            const GemLaunch& L = bw.L;
+            vd::PrepItem it;
+            std::memset(&it, 0, sizeof(it));
+            it.pose = L.b->pose;
+            it.prior_pose = L.b->prior_pose;
+            it.N = L.v->N;
+            it.P = L.v->P;
+            it.out = L.s.poses;
+            it.outd = L.s.posed;
+            prep.push_back(it);
+        }
+        prep_n[cls] = (int)prep.size();
+        if (!prep.empty()) prep_off[cls] = P.put(prep);
     }
-    const size_t prep_off = P.put(prep);
+    auto add_prep = [&]() {
+        for (int cls = 0; cls < 4; ++cls)
+            if (prep_n[cls]) P.add(BK_PREP, prep_off[cls], 0, prep_n[cls], prep_n[cls], 0, 0, 0, cls & 1, cls & 2);
+    };
     int maxS = 0;
     for (BWin& bw : W) maxS = std::max(maxS, bw.L.v->N * bw.L.v->pose_gn_steps);
     for (int it = 0; it < n_iters; ++it) {
-        P.add(BK_PREP, prep_off, 0, (int)W.size(), (int)W.size());
+        add_prep();
         auto item = [&](const GemLaunch& L, int level, int do_e, int do_m, bool want_ll) {
             vd::LevelItem x;
             std::memset(&x, 0, sizeof(x));
@@ -711,7 +723,7 @@ int build_plan(voldor_ctx ctx, std::vector<BWin>& W, int n_iters, int flags, BPl
         }
     }
     // final E-step, confidence and statistics
-    P.add(BK_PREP, prep_off, 0, (int)W.size(), (int)W.size());
+    add_prep();
     const int last = n_iters - 1;
     plan_level(P, W, 0, [&](const GemLaunch& L) {
         vd::LevelItem x;
@@ -768,11 +780,11 @@ int ensure_class_streams(voldor_ctx ctx) {
     return VOLDOR_OK;
 }
 
-// Enqueues the plan on st.  A run of level and pose launches (one per window class and step)
-// goes to the classes' own streams, forked from st at its first launch and joined back into
-// st before the next launch that serves every window: the windows of different classes share
-// no buffer, so their passes (latency-bound coarse launches and pose steps above all)
-// overlap.
+// Enqueues the plan on st.  Every launch of one window class (all but the setup and the
+// statistics' finish, which serve every window) goes to the class's own stream, forked from
+// st at the class's first launch and joined back into st before the next launch that serves
+// every window: the windows of different classes share no buffer, so the classes' whole
+// iteration chains (latency-bound coarse launches and pose steps above all) overlap.
 int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st) {
     const bool par = ctx->class_streams[0] != nullptr;
     unsigned open = 0;                           // classes forked in the current run
@@ -787,7 +799,7 @@ int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st
     };
     for (const BLaunch& l : P.launches) {
         hipStream_t s = st;
-        if (par && (l.kind == BK_LEVEL || l.kind == BK_POSE || l.kind == BK_POSE_SOLVE)) {
+        if (par && l.kind != BK_SETUP && l.kind != BK_FINAL_FINISH) {
             const int c = (l.b2 ? 1 : 0) + (l.pr ? 2 : 0);
             if (!open) VD_CHECK(hipEventRecord(ctx->class_events[0], st), "fork record");
             if (!(open & (1u << c))) {
@@ -803,14 +815,14 @@ int enqueue_plan(voldor_ctx ctx, const BPlan& P, const char* dev, hipStream_t st
         const int* b2i = (const int*)(dev + l.b2i);
         hipError_t e = hipSuccess;
         switch (l.kind) {
-        case BK_PREP: e = vd::launch_prep_batch((const vd::PrepItem*)items, l.n_items, st); break;
+        case BK_PREP: e = vd::launch_prep_batch((const vd::PrepItem*)items, l.n_items, s); break;
         case BK_SETUP: e = vd::launch_setup_batch((const vd::PrepItem*)items, b2i, l.nblocks, st); break;
         case BK_LEVEL:
             e = vd::launch_level_batch((const vd::LevelItem*)items, b2i, l.nblocks, l.lds, l.mode, l.b2, l.pr, s);
             break;
         case BK_POSE: e = vd::launch_pose_gn_batch((const vd::PoseItem*)items, b2i, l.nblocks, l.s, l.b2, s); break;
         case BK_POSE_SOLVE: e = vd::launch_pose_gn_solve_batch((const vd::PoseItem*)items, l.n_items, l.s, s); break;
-        case BK_FINAL: e = vd::launch_finalize_batch((const vd::FinalItem*)items, b2i, l.nblocks, l.b2, l.pr, st); break;
+        case BK_FINAL: e = vd::launch_finalize_batch((const vd::FinalItem*)items, b2i, l.nblocks, l.b2, l.pr, s); break;
         case BK_FINAL_FINISH: e = vd::launch_finalize_finish_batch((const vd::FinalItem*)items, l.n_items, st); break;
         }
         VD_CHECK(e, "batched launch");
