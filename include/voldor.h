@@ -232,9 +232,9 @@ int voldor_run_noalloc(voldor_ctx ctx, const voldor_window* win, const voldor_bu
  * each as voldor_run from iteration 0 with the same n_iters and flags (VOLDOR_RUN_INIT),
  * bit for bit.  Each
  * step of the launch sequence is one launch over all windows per shape class (log-logistic
- * shape 2 or not, priors or not): a block finds its window in an item table.  The classes'
- * level and pose launches run on streams of the context's own (forked from and joined back
- * into `stream`), so they overlap; the call's work is still ordered on `stream` as a whole.
+ * shape 2 or not, priors or not): a block finds its window in an item table.  Each class's
+ * launches run on a stream of the context's own (forked from and joined back into
+ * `stream`), so the classes overlap; the call's work is still ordered on `stream` as a whole.
  * The whole sequence is captured once into a HIP graph on the first call for a given set of windows,
  * buffers and settings and replayed by later identical calls (VOLDOR_RUN_NO_GRAPH launches
  * directly).  The context keeps every window's scratch (about 60 MB for 1216x352, N = 6) for
